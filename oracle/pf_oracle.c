@@ -1,0 +1,737 @@
+/*
+ * pf_oracle.c -- plain, slow FP64 reference of the LMM PF-SMC sampler
+ * (Arnold, Calvetti & Somersalo, "Vectorized and Parallel Particle Filter SMC
+ * Parameter Estimation for Stiff ODEs", Sec. 2, Algorithm 1).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the oracle that the GPU path is
+ * checked against.  Only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark may load it.  It shares no source with the HIP library
+ * (no headers, tables or helpers): every formula below is written out again
+ * from the paper and from the published definitions it cites.
+ *
+ * Everything is double precision.  Particles are stored array-of-structures
+ * (x[n*d + i], theta[n*p + i]) because that is the plainest layout; loops over
+ * particles carry an OpenMP pragma and nothing else.
+ *
+ * Readings of points the paper leaves open are marked "Reading:" where they
+ * are used.  Parity status of each function is in its comment; the one piece
+ * with no pin beyond internal consistency is the innovation-variance reading
+ * (the paper defers its formula to a companion paper): parity unpinned.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define OR_DMAX 16
+#define OR_PMAX 12
+#define OR_MMAX 4
+
+/* status codes (plain ints; mirrored by the Python wrapper) */
+#define OR_OK 0
+#define OR_EINVAL 1
+#define OR_EDEGENERATE 4
+
+/* ------------------------------------------------------------------------- */
+/* Counter-based RNG: Philox4x64-10 (Salmon, Moraes, Dror, Shaw, "Parallel    */
+/* random numbers: as easy as 1, 2, 3", SC'11).  A round maps the counter     */
+/* (c0,c1,c2,c3) with key (k0,k1) to                                          */
+/*   (hi(M1*c2) ^ c1 ^ k0, lo(M1*c2), hi(M0*c0) ^ c3 ^ k1, lo(M0*c0));          */
+/* the key is bumped by the Weyl constants between rounds; ten rounds.        */
+/* ------------------------------------------------------------------------- */
+static const uint64_t PHX_M0 = 0xD2E7470EE14C6C93ULL;
+static const uint64_t PHX_M1 = 0xCA5A826395121157ULL;
+static const uint64_t PHX_W0 = 0x9E3779B97F4A7C15ULL;
+static const uint64_t PHX_W1 = 0xBB67AE8584CAA73BULL;
+
+void or_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4])
+{
+    uint64_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint64_t k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) { k0 += PHX_W0; k1 += PHX_W1; }
+        unsigned __int128 p0 = (unsigned __int128)PHX_M0 * c0;
+        unsigned __int128 p1 = (unsigned __int128)PHX_M1 * c2;
+        uint64_t hi0 = (uint64_t)(p0 >> 64), lo0 = (uint64_t)p0;
+        uint64_t hi1 = (uint64_t)(p1 >> 64), lo1 = (uint64_t)p1;
+        c0 = hi1 ^ c1 ^ k0;
+        c1 = lo1;
+        c2 = hi0 ^ c3 ^ k1;
+        c3 = lo0;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* uniform on the open interval (0,1) from the top 53 bits */
+double or_u01(uint64_t w) { return ((double)(w >> 11) + 0.5) * 0x1p-53; }
+
+/*
+ * Gaussian draws of one purpose: counter (step, particle, purpose, block),
+ * key (seed, 0).  A block gives four words -> four uniforms u0..u3 -> two
+ * Box-Muller pairs (Box & Muller 1958):
+ *   z0 = sqrt(-2 ln u0) cos(2 pi u1),  z1 = sqrt(-2 ln u0) sin(2 pi u1),
+ *   z2 = sqrt(-2 ln u2) cos(2 pi u3),  z3 = sqrt(-2 ln u2) sin(2 pi u3).
+ * Normal number k of the purpose comes from block k/4, slot k%4.
+ */
+void or_normals(uint64_t seed, uint64_t step, uint64_t particle, uint64_t purpose,
+                int count, double* out)
+{
+    const double two_pi = 6.283185307179586476925286766559;
+    uint64_t key[2] = {seed, 0};
+    for (int b = 0; 4 * b < count; ++b) {
+        uint64_t ctr[4] = {step, particle, purpose, (uint64_t)b};
+        uint64_t w[4];
+        or_philox4x64(ctr, key, w);
+        double u0 = or_u01(w[0]), u1 = or_u01(w[1]), u2 = or_u01(w[2]), u3 = or_u01(w[3]);
+        double r0 = sqrt(-2.0 * log(u0)), r1 = sqrt(-2.0 * log(u2));
+        double z[4] = {r0 * cos(two_pi * u1), r0 * sin(two_pi * u1),
+                       r1 * cos(two_pi * u3), r1 * sin(two_pi * u3)};
+        for (int s = 0; s < 4 && 4 * b + s < count; ++s) out[4 * b + s] = z[s];
+    }
+}
+
+/* RNG purposes (third counter word) */
+enum { PUR_PRIOR = 1, PUR_RESAMPLE = 2, PUR_PROLIF = 3, PUR_INNOV = 4 };
+
+/* ------------------------------------------------------------------------- */
+/* Backward differentiation formulas (Sec. 2.1: implicit LMMs for the stiff   */
+/* propagation).  Normalised with the coefficient of x_m equal to one:        */
+/*   x_m + sum_{i=1..q} alpha_i x_{m-i} = h beta f(x_m),                       */
+/* error constant C_{q+1}: the residual of the formula on the exact solution  */
+/* is C_{q+1} h^{q+1} x^{(q+1)} + O(h^{q+2}).  Textbook values.               */
+/* ------------------------------------------------------------------------- */
+int or_bdf(int q, double alpha[4], double* beta, double* errc)
+{
+    for (int i = 0; i < 4; ++i) alpha[i] = 0.0;
+    alpha[0] = 1.0;
+    switch (q) {
+    case 1: alpha[1] = -1.0; *beta = 1.0; *errc = -1.0 / 2.0; return 0;
+    case 2: alpha[1] = -4.0 / 3.0; alpha[2] = 1.0 / 3.0; *beta = 2.0 / 3.0; *errc = -2.0 / 9.0; return 0;
+    case 3: alpha[1] = -18.0 / 11.0; alpha[2] = 9.0 / 11.0; alpha[3] = -2.0 / 11.0;
+            *beta = 6.0 / 11.0; *errc = -3.0 / 22.0; return 0;
+    default: return OR_EINVAL;
+    }
+}
+
+/* weights of the degree-q polynomial through x_{m-1},...,x_{m-1-q} evaluated
+ * one step ahead: (-1)^i binom(q+1, i+1) for x_{m-1-i}. */
+static void or_extrap_weights(int q, double w[4])
+{
+    static const double tab[4][4] = {{1, 0, 0, 0}, {2, -1, 0, 0}, {3, -3, 1, 0}, {4, -6, 4, -1}};
+    for (int i = 0; i < 4; ++i) w[i] = tab[q][i];
+}
+
+/* ------------------------------------------------------------------------- */
+/* Models: right-hand side f(x; k) and Jacobian J = df/dx (row-major d x d).  */
+/* `k` is the full vector of rate constants; `mc` the fixed model constants. */
+/* ------------------------------------------------------------------------- */
+enum { MODEL_DECAY = 0, MODEL_ROBERTSON = 1, MODEL_CHAIN = 2 };
+
+/* x_i' = -k_i x_i (test problem with a closed form; d = p) */
+static void rhs_decay(int d, const double* x, const double* k, double* f, double* J)
+{
+    for (int i = 0; i < d; ++i) f[i] = -k[i] * x[i];
+    if (J) {
+        for (int i = 0; i < d * d; ++i) J[i] = 0.0;
+        for (int i = 0; i < d; ++i) J[i * d + i] = -k[i];
+    }
+}
+
+/* Robertson kinetics: A -> B (k1), 2B -> B + C (k2), B + C -> A + C (k3) */
+static void rhs_robertson(const double* x, const double* k, double* f, double* J)
+{
+    double k1 = k[0], k2 = k[1], k3 = k[2];
+    f[0] = -k1 * x[0] + k3 * x[1] * x[2];
+    f[1] = k1 * x[0] - k2 * x[1] * x[1] - k3 * x[1] * x[2];
+    f[2] = k2 * x[1] * x[1];
+    if (J) {
+        J[0] = -k1; J[1] = k3 * x[2];                    J[2] = k3 * x[1];
+        J[3] = k1;  J[4] = -2.0 * k2 * x[1] - k3 * x[2]; J[5] = -k3 * x[1];
+        J[6] = 0.0; J[7] = 2.0 * k2 * x[1];              J[8] = 0.0;
+    }
+}
+
+/* Compartment chain with Michaelis-Menten losses:
+ *   x_i' = k_{i-1} x_{i-1} - k_i x_i - V_i x_i / (K_i + x_i),
+ * with a constant unit influx into the first compartment.
+ * mc layout: [V_1..V_d, K_1..K_d]. */
+static void rhs_chain(int d, const double* x, const double* k, const double* mc,
+                      double* f, double* J)
+{
+    const double* V = mc;
+    const double* K = mc + d;
+    for (int i = 0; i < d; ++i) {
+        double in = (i == 0) ? 1.0 : k[i - 1] * x[i - 1];
+        f[i] = in - k[i] * x[i] - V[i] * x[i] / (K[i] + x[i]);
+    }
+    if (J) {
+        for (int i = 0; i < d * d; ++i) J[i] = 0.0;
+        for (int i = 0; i < d; ++i) {
+            double den = K[i] + x[i];
+            J[i * d + i] = -k[i] - V[i] * K[i] / (den * den);
+            if (i > 0) J[i * d + i - 1] = k[i - 1];
+        }
+    }
+}
+
+/*
+ * Model description.  Rate constants: the first p are exp(theta); the rest
+ * (chain only) are fixed and come from `rates_fixed`.
+ */
+typedef struct {
+    int model;          /* MODEL_* */
+    int d;              /* state dimension */
+    int p;              /* number of estimated log-parameters */
+    const double* mc;   /* chain: [V(d), K(d)]; unused otherwise */
+    const double* rates_fixed; /* chain: full k(d); entries p..d-1 are used */
+} or_model;
+
+void or_rhs(int model, int d, int p, const double* mc, const double* rates_fixed,
+            const double* x, const double* theta, double* f, double* J)
+{
+    double k[OR_DMAX];
+    int nk = (model == MODEL_ROBERTSON) ? 3 : d;
+    for (int i = 0; i < nk; ++i) k[i] = (i < p) ? exp(theta[i]) : rates_fixed[i];
+    if (model == MODEL_DECAY) rhs_decay(d, x, k, f, J);
+    else if (model == MODEL_ROBERTSON) rhs_robertson(x, k, f, J);
+    else rhs_chain(d, x, k, mc, f, J);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Dense LU with partial pivoting: solve A z = b (A row-major, destroyed).    */
+/* Returns 0, or -1 if a pivot is exactly zero or not finite.                 */
+/* ------------------------------------------------------------------------- */
+int or_lu_solve(int d, double* A, double* b)
+{
+    for (int c = 0; c < d; ++c) {
+        int piv = c;
+        double best = fabs(A[c * d + c]);
+        for (int r = c + 1; r < d; ++r)
+            if (fabs(A[r * d + c]) > best) { best = fabs(A[r * d + c]); piv = r; }
+        if (!(best > 0.0) || !isfinite(best)) return -1;
+        if (piv != c) {
+            for (int j = 0; j < d; ++j) { double t = A[c * d + j]; A[c * d + j] = A[piv * d + j]; A[piv * d + j] = t; }
+            double t = b[c]; b[c] = b[piv]; b[piv] = t;
+        }
+        for (int r = c + 1; r < d; ++r) {
+            double l = A[r * d + c] / A[c * d + c];
+            A[r * d + c] = 0.0;
+            for (int j = c + 1; j < d; ++j) A[r * d + j] -= l * A[c * d + j];
+            b[r] -= l * b[c];
+        }
+    }
+    for (int r = d - 1; r >= 0; --r) {
+        double s = b[r];
+        for (int j = r + 1; j < d; ++j) s -= A[r * d + j] * b[j];
+        b[r] = s / A[r * d + r];
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Psi: propagate one particle over one observation interval with M fixed    */
+/* BDF steps of size h (Algorithm 1, steps 2 and 4(d)); optionally also the   */
+/* LMM local-error estimate that sets the innovation variance (step 4(b)).    */
+/*                                                                            */
+/* Reading (start-up): Psi only receives x_j, so every interval restarts from */
+/* a single value.  Step m (1-based) uses order q = max(1, min(k, m-1)): the  */
+/* order a degree-q extrapolation predictor through the available history     */
+/* can support.  Step 1 uses the explicit Euler predictor x_0 + h f(x_0).     */
+/*                                                                            */
+/* Reading (Newton): full Newton on G(x) = x - psi - h beta f(x) from the     */
+/* predictor, analytic Jacobian refreshed every iteration, solve              */
+/* (I - h beta J) dx = -G, x += dx; stop after the first iteration with       */
+/* max_i |dx_i| / max(|x_i|, floor_i) <= rtol, or after kmax iterations.      */
+/*                                                                            */
+/* Reading (Newton start): the predictor below at steps m >= 2; at step 1     */
+/* the previous value x_0 itself (an explicit Euler guess is unstable for the */
+/* stiff components when h |lambda| >> 1).                                    */
+/*                                                                            */
+/* Reading (innovation variance, parity unpinned against the paper): the     */
+/* Milne-device estimate of each step's local error, filtered through the     */
+/* Newton matrix so that stiff components are not over-estimated:             */
+/*   e_m = |C_{q+1}| / (C* + |C_{q+1}|) * (I - h beta J)^{-1} (x_m - x_m^(0)), */
+/* with x^(0) the degree-q extrapolation (error constant C* = 1) or, at step  */
+/* 1, the Euler value x_0 + h f(x_0) (C* = 1/2); J is the Jacobian of the     */
+/* last Newton iteration.  Steps add as independent variances:                */
+/*   Gamma = diag(sum_m e_m^2).                                               */
+/*                                                                            */
+/* `hist` (optional, pins only): q_hist earlier values x_{-1},...,x_{-q_hist} */
+/* on the same grid, so that the formula runs at full order from step 1.      */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    long newton_iters;  /* total Newton iterations */
+    long newton_fails;  /* steps that hit kmax without meeting the test */
+    long lu_fails;      /* singular or non-finite pivots */
+} or_psi_stats;
+
+int or_psi(int model, int d, int p, const double* mc, const double* rates_fixed,
+           const double* x0, const double* theta, double h, int M, int k,
+           int want_lte, double rtol, int kmax, const double* floor_,
+           const double* hist, int q_hist,
+           double* x_out, double* gamma_out, or_psi_stats* st)
+{
+    /* H[0] = x_{m-1}, H[1] = x_{m-2}, ... (ring of up to 4 values) */
+    double H[4][OR_DMAX];
+    int nh = 1;
+    memcpy(H[0], x0, sizeof(double) * d);
+    if (hist) {
+        for (int r = 0; r < q_hist && r < 3; ++r) memcpy(H[r + 1], hist + r * d, sizeof(double) * d);
+        nh = 1 + (q_hist < 3 ? q_hist : 3);
+    }
+    double gam[OR_DMAX];
+    for (int i = 0; i < d; ++i) gam[i] = 0.0;
+
+    for (int m = 1; m <= M; ++m) {
+        int avail = nh - 1;               /* past values beyond x_{m-1} */
+        int q = avail < k ? avail : k;
+        if (q < 1) q = 1;
+        double alpha[4], beta, errc;
+        or_bdf(q, alpha, &beta, &errc);
+
+        /* predictor x^(0) and its error constant */
+        double xp[OR_DMAX], cstar;
+        if (avail == 0) {
+            double f0[OR_DMAX];
+            or_rhs(model, d, p, mc, rates_fixed, H[0], theta, f0, NULL);
+            for (int i = 0; i < d; ++i) xp[i] = H[0][i] + h * f0[i];
+            cstar = 0.5;
+        } else {
+            double w[4];
+            or_extrap_weights(q, w);
+            for (int i = 0; i < d; ++i) {
+                double s = 0.0;
+                for (int r = 0; r <= q; ++r) s += w[r] * H[r][i];
+                xp[i] = s;
+            }
+            cstar = 1.0;
+        }
+
+        /* psi = -sum_{i>=1} alpha_i x_{m-i} */
+        double psi[OR_DMAX];
+        for (int i = 0; i < d; ++i) {
+            double s = 0.0;
+            for (int r = 1; r <= q; ++r) s -= alpha[r] * H[r - 1][i];
+            psi[i] = s;
+        }
+
+        /* Newton, from x_0 at step 1 and from the predictor afterwards */
+        double x[OR_DMAX], Alast[OR_DMAX * OR_DMAX];
+        memcpy(x, avail == 0 ? H[0] : xp, sizeof(double) * d);
+        double c = h * beta;
+        int conv = 0;
+        for (int it = 0; it < kmax; ++it) {
+            double f[OR_DMAX], J[OR_DMAX * OR_DMAX], A[OR_DMAX * OR_DMAX], rhs[OR_DMAX];
+            or_rhs(model, d, p, mc, rates_fixed, x, theta, f, J);
+            for (int i = 0; i < d; ++i) rhs[i] = -(x[i] - psi[i] - c * f[i]);
+            for (int r = 0; r < d; ++r)
+                for (int s = 0; s < d; ++s) A[r * d + s] = (r == s ? 1.0 : 0.0) - c * J[r * d + s];
+            memcpy(Alast, A, sizeof(double) * d * d);
+            if (st) st->newton_iters++;
+            if (or_lu_solve(d, A, rhs) != 0) {
+                if (st) st->lu_fails++;
+                for (int i = 0; i < d; ++i) x[i] = NAN;
+                break;
+            }
+            double worst = 0.0;
+            for (int i = 0; i < d; ++i) {
+                x[i] += rhs[i];
+                double sc = fabs(x[i]) > floor_[i] ? fabs(x[i]) : floor_[i];
+                double r = fabs(rhs[i]) / sc;
+                if (r != r) r = INFINITY;       /* NaN counts as "not converged" */
+                if (r > worst) worst = r;
+            }
+            if (worst <= rtol) { conv = 1; break; }
+        }
+        if (!conv && st) st->newton_fails++;
+
+        if (want_lte) {
+            double kap = fabs(errc) / (cstar + fabs(errc));
+            double e[OR_DMAX];
+            for (int i = 0; i < d; ++i) e[i] = x[i] - xp[i];
+            if (or_lu_solve(d, Alast, e) != 0)
+                for (int i = 0; i < d; ++i) e[i] = NAN;
+            for (int i = 0; i < d; ++i) {
+                double ei = kap * e[i];
+                gam[i] += ei * ei;
+            }
+        }
+
+        /* shift history */
+        for (int r = 3; r > 0; --r) memcpy(H[r], H[r - 1], sizeof(double) * d);
+        memcpy(H[0], x, sizeof(double) * d);
+        if (nh < 4) nh++;
+    }
+    memcpy(x_out, H[0], sizeof(double) * d);
+    if (gamma_out) memcpy(gamma_out, gam, sizeof(double) * d);
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Likelihood pi(y | x): Gaussian, independent components, known sd sigma_i, */
+/* observing x_{o_i}.  Normalising constants cancel in both weight           */
+/* normalisations of Algorithm 1 (steps 3(a) and 5) and are dropped.         */
+/* Non-finite states give -inf.                                              */
+/* ------------------------------------------------------------------------- */
+double or_loglik(int m, const int* obs, const double* y, const double* sigma, const double* x)
+{
+    double s = 0.0;
+    for (int i = 0; i < m; ++i) {
+        double v = x[obs[i]];
+        if (!isfinite(v)) return -INFINITY;
+        double r = (y[i] - v) / sigma[i];
+        s += r * r;
+    }
+    return -0.5 * s;
+}
+
+/* normalised weights w = exp(l - max) / sum exp(l - max); returns the log of
+ * the normaliser (-inf if every entry is -inf / NaN, then w is left zero). */
+double or_normalise(long N, const double* l, double* w)
+{
+    double mx = -INFINITY;
+    for (long n = 0; n < N; ++n) if (l[n] > mx) mx = l[n];   /* NaN compares false */
+    if (!(mx > -INFINITY) || !isfinite(mx)) {
+        for (long n = 0; n < N; ++n) w[n] = 0.0;
+        return -INFINITY;
+    }
+    double s = 0.0;
+    for (long n = 0; n < N; ++n) {
+        double e = (l[n] > -INFINITY) ? exp(l[n] - mx) : 0.0;  /* NaN -> 0 */
+        w[n] = e;
+        s += e;
+    }
+    for (long n = 0; n < N; ++n) w[n] /= s;
+    return mx + log(s);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Systematic resampling in exact integer arithmetic (replaces the            */
+/* multinomial draw of step 3(b) with the systematic scheme).                 */
+/*   q_k = floor(g_k 2^S), S = 62 - ceil(log2 N); C_k = q_1 + ... + q_k;     */
+/*   T = C_N; V = floor(r T / 2^64) for a uniform word r;                     */
+/* output slot i (0-based) takes the first k with C_k > floor((i T + V)/N). */
+/* A particle with q_k = 0 is never chosen.                                   */
+/* ------------------------------------------------------------------------- */
+int or_resample_shift(long N)
+{
+    int c = 0;
+    while ((1L << c) < N) ++c;          /* ceil(log2 N) */
+    return 62 - c;
+}
+
+/* integer core: q[N] (sum T, with T*N < 2^63), offset V in [0, T) */
+int or_resample_int(long N, const uint64_t* q, uint64_t V, int32_t* anc)
+{
+    uint64_t T = 0;
+    for (long k = 0; k < N; ++k) T += q[k];
+    if (T == 0 || V >= T) return OR_EDEGENERATE;
+    long k = 0;
+    uint64_t Ck = q[0];
+    for (long i = 0; i < N; ++i) {
+        uint64_t target = ((uint64_t)i * T + V) / (uint64_t)N;
+        while (!(Ck > target)) { ++k; Ck += q[k]; }
+        anc[i] = (int32_t)k;
+    }
+    return OR_OK;
+}
+
+int or_resample(long N, const double* g, uint64_t r, int32_t* anc)
+{
+    int S = or_resample_shift(N);
+    uint64_t* q = (uint64_t*)malloc(sizeof(uint64_t) * (N > 0 ? N : 1));
+    uint64_t T = 0;
+    for (long k = 0; k < N; ++k) {
+        double v = (g[k] > 0.0) ? floor(ldexp(g[k], S)) : 0.0;
+        q[k] = (uint64_t)v;
+        T += q[k];
+    }
+    uint64_t V = (uint64_t)(((unsigned __int128)r * T) >> 64);
+    int st = or_resample_int(N, q, V, anc);
+    free(q);
+    return st;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Weighted parameter mean and covariance (Algorithm 1 steps 1 and 6):       */
+/*   mean = sum_n w_n theta_n,  C = sum_n w_n (theta_n - mean)(...)^T.       */
+/* Two passes; weights are taken as given (they sum to one).                  */
+/* ------------------------------------------------------------------------- */
+void or_moments(long N, int p, const double* theta, const double* w, double* mean, double* cov)
+{
+    for (int i = 0; i < p; ++i) {
+        double s = 0.0;
+        for (long n = 0; n < N; ++n) s += w[n] * theta[n * p + i];
+        mean[i] = s;
+    }
+    for (int i = 0; i < p; ++i)
+        for (int j = 0; j < p; ++j) {
+            double s = 0.0;
+            for (long n = 0; n < N; ++n)
+                s += w[n] * (theta[n * p + i] - mean[i]) * (theta[n * p + j] - mean[j]);
+            cov[i * p + j] = s;
+        }
+}
+
+/* Cholesky C = L L^T (L lower, row-major).  Reading: if C is not positive   */
+/* definite, retry with C + delta I, delta = 1e-10 tr(C)/p, then 10x larger,  */
+/* at most five retries; then the step is degenerate.                        */
+int or_cholesky(int p, const double* C, double* L, int* jitters)
+{
+    double tr = 0.0;
+    for (int i = 0; i < p; ++i) tr += C[i * p + i];
+    double delta = 0.0;
+    for (int attempt = 0; attempt <= 5; ++attempt) {
+        if (attempt == 1) delta = 1e-10 * tr / p;
+        else if (attempt > 1) delta *= 10.0;
+        int ok = 1;
+        for (int i = 0; i < p * p; ++i) L[i] = 0.0;
+        for (int j = 0; j < p && ok; ++j) {
+            double s = C[j * p + j] + delta;
+            for (int k = 0; k < j; ++k) s -= L[j * p + k] * L[j * p + k];
+            if (!(s > 0.0) || !isfinite(s)) { ok = 0; break; }
+            double ljj = sqrt(s);
+            L[j * p + j] = ljj;
+            for (int i = j + 1; i < p; ++i) {
+                double t = C[i * p + j];
+                for (int k = 0; k < j; ++k) t -= L[i * p + k] * L[j * p + k];
+                L[i * p + j] = t / ljj;
+            }
+        }
+        if (ok) { if (jitters) *jitters = attempt; return OR_OK; }
+    }
+    if (jitters) *jitters = 6;
+    return OR_EDEGENERATE;
+}
+
+/* ------------------------------------------------------------------------- */
+/* The filter (Algorithm 1)                                                  */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    int model, d, p, m;
+    int obs[OR_MMAX];
+    const double* mc;           /* model constants (chain: V, K) */
+    const double* rates_fixed;  /* chain: full rate vector */
+    long N;
+    uint64_t seed;
+    double a;                   /* Liu-West shrinkage factor, 0 < a < 1 */
+    int order, substeps;        /* BDF order k and steps per interval M */
+    int kmax; double rtol;      /* Newton */
+    double floor_[OR_DMAX];
+    double x0[OR_DMAX];
+    double prior_mean[OR_PMAX], prior_sd[OR_PMAX];
+} or_config;
+
+typedef struct {
+    uint64_t j;                 /* observations assimilated */
+    double t;                   /* time of x */
+    double* x;                  /* [N*d] */
+    double* theta;              /* [N*p] */
+    double* logw;               /* [N], normalised log-weights */
+    double theta_bar[OR_PMAX];
+    double C[OR_PMAX * OR_PMAX];
+    double L[OR_PMAX * OR_PMAX];
+} or_state;
+
+typedef struct {
+    double ess;
+    double state_mean[OR_DMAX];
+    long newton_iters, newton_fails, lu_fails;
+    long nonfinite;             /* particles given weight zero at step 5 */
+    int jitters;
+    int32_t first_anc;          /* spare diagnostics */
+} or_diag;
+
+/* Step 1: initialisation.  theta_0 = prior_mean + prior_sd * z (PRIOR draws of
+ * step 0), x_0 = x0 for every particle, w = 1/N, then mean, covariance and
+ * the Cholesky factor used by the first proliferation. */
+int or_filter_init(const or_config* cfg, double t0, or_state* s)
+{
+    long N = cfg->N;
+    int d = cfg->d, p = cfg->p;
+    if (N < 1 || d < 1 || d > OR_DMAX || p < 1 || p > OR_PMAX) return OR_EINVAL;
+#pragma omp parallel for schedule(static)
+    for (long n = 0; n < N; ++n) {
+        double z[OR_PMAX];
+        or_normals(cfg->seed, 0, (uint64_t)n, PUR_PRIOR, p, z);
+        for (int i = 0; i < p; ++i) s->theta[n * p + i] = cfg->prior_mean[i] + cfg->prior_sd[i] * z[i];
+        for (int i = 0; i < d; ++i) s->x[n * d + i] = cfg->x0[i];
+        s->logw[n] = -log((double)N);
+    }
+    double* w = (double*)malloc(sizeof(double) * N);
+    for (long n = 0; n < N; ++n) w[n] = 1.0 / (double)N;
+    or_moments(N, p, s->theta, w, s->theta_bar, s->C);
+    free(w);
+    int jit = 0;
+    int st = or_cholesky(p, s->C, s->L, &jit);
+    s->j = 0;
+    s->t = t0;
+    return st;
+}
+
+/* Steps 2-6 for the next observation y (m values, sd sigma) at t_next. */
+int or_filter_step(const or_config* cfg, or_state* s, double t_next,
+                   const double* y, const double* sigma, or_diag* dg)
+{
+    long N = cfg->N;
+    int d = cfg->d, p = cfg->p, m = cfg->m;
+    if (!(t_next > s->t)) return OR_EINVAL;
+    for (int i = 0; i < m; ++i) if (!isfinite(y[i]) || !(sigma[i] > 0.0) || !isfinite(sigma[i])) return OR_EINVAL;
+    double h = (t_next - s->t) / cfg->substeps;
+    uint64_t step = s->j + 1;
+    double a = cfg->a, sh = sqrt(1.0 - a * a);
+
+    double* mshr = (double*)malloc(sizeof(double) * N * p);   /* shrunk parameters */
+    double* xbar = (double*)malloc(sizeof(double) * N * d);   /* predictor states */
+    double* lbar = (double*)malloc(sizeof(double) * N);       /* log pi(y | xbar) */
+    double* lg   = (double*)malloc(sizeof(double) * N);
+    double* g    = (double*)malloc(sizeof(double) * N);
+    int32_t* anc = (int32_t*)malloc(sizeof(int32_t) * N);
+    double* xn   = (double*)malloc(sizeof(double) * N * d);
+    double* thn  = (double*)malloc(sizeof(double) * N * p);
+    double* lwn  = (double*)malloc(sizeof(double) * N);
+    double* wn   = (double*)malloc(sizeof(double) * N);
+    long it_tot = 0, fail_tot = 0, lu_tot = 0;
+    int status = OR_OK;
+
+    /* Step 2: shrink, then the predictor Psi(x_j, theta_bar_j^n, h) */
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : it_tot, fail_tot, lu_tot)
+    for (long n = 0; n < N; ++n) {
+        for (int i = 0; i < p; ++i) mshr[n * p + i] = a * s->theta[n * p + i] + (1.0 - a) * s->theta_bar[i];
+        or_psi_stats st = {0, 0, 0};
+        or_psi(cfg->model, d, p, cfg->mc, cfg->rates_fixed, s->x + n * d, mshr + n * p, h,
+               cfg->substeps, cfg->order, 0, cfg->rtol, cfg->kmax, cfg->floor_, NULL, 0,
+               xbar + n * d, NULL, &st);
+        it_tot += st.newton_iters; fail_tot += st.newton_fails; lu_tot += st.lu_fails;
+        /* Step 3(a): fitness weights g = w_j pi(y | xbar), in logs */
+        lbar[n] = or_loglik(m, cfg->obs, y, sigma, xbar + n * d);
+        lg[n] = s->logw[n] + lbar[n];
+    }
+    if (or_normalise(N, lg, g) == -INFINITY) { status = OR_EDEGENERATE; goto done; }
+
+    /* Step 3(b): indices, one uniform word per filter and step */
+    {
+        uint64_t key[2] = {cfg->seed, 0}, ctr[4] = {step, 0, PUR_RESAMPLE, 0}, wv[4];
+        or_philox4x64(ctr, key, wv);
+        if (or_resample(N, g, wv[0], anc) != OR_OK) { status = OR_EDEGENERATE; goto done; }
+    }
+
+    /* Steps 3(c), 4, 5 per output slot n */
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : it_tot, fail_tot, lu_tot)
+    for (long n = 0; n < N; ++n) {
+        long k = anc[n];
+        /* 3(c) reshuffle: x_j, xbar_{j+1}, theta_bar_j^n follow the ancestor */
+        const double* xj = s->x + k * d;
+        const double* mj = mshr + k * p;
+        double lbar_anc = lbar[k];
+        /* 4(a) proliferate: theta_{j+1} ~ N(theta_bar^n, s^2 C_j) */
+        double z[OR_PMAX];
+        or_normals(cfg->seed, step, (uint64_t)n, PUR_PROLIF, p, z);
+        for (int i = 0; i < p; ++i) {
+            double v = 0.0;
+            for (int c = 0; c <= i; ++c) v += s->L[i * p + c] * z[c];
+            thn[n * p + i] = mj[i] + sh * v;
+        }
+        /* 4(b)-(d): Gamma from the LMM error estimate, v ~ N(0, Gamma),
+         * x_{j+1} = Psi(x_j, theta_{j+1}, h) + v */
+        double xt[OR_DMAX], gam[OR_DMAX], zz[OR_DMAX];
+        or_psi_stats st = {0, 0, 0};
+        or_psi(cfg->model, d, p, cfg->mc, cfg->rates_fixed, xj, thn + n * p, h, cfg->substeps,
+               cfg->order, 1, cfg->rtol, cfg->kmax, cfg->floor_, NULL, 0, xt, gam, &st);
+        it_tot += st.newton_iters; fail_tot += st.newton_fails; lu_tot += st.lu_fails;
+        or_normals(cfg->seed, step, (uint64_t)n, PUR_INNOV, d, zz);
+        for (int i = 0; i < d; ++i) xn[n * d + i] = xt[i] + sqrt(gam[i]) * zz[i];
+        /* 5: w = pi(y | x_{j+1}) / pi(y | xbar^{l_n}) */
+        lwn[n] = or_loglik(m, cfg->obs, y, sigma, xn + n * d) - lbar_anc;
+    }
+    double lz = or_normalise(N, lwn, wn);
+    if (lz == -INFINITY) { status = OR_EDEGENERATE; goto done; }
+
+    /* 6: mean, covariance, Cholesky factor */
+    double mean[OR_PMAX], cov[OR_PMAX * OR_PMAX], L[OR_PMAX * OR_PMAX];
+    or_moments(N, p, thn, wn, mean, cov);
+    int jit = 0;
+    if (or_cholesky(p, cov, L, &jit) != OR_OK) { status = OR_EDEGENERATE; goto done; }
+
+    /* commit */
+    long nonf = 0;
+    double sw2 = 0.0;
+    for (long n = 0; n < N; ++n) {
+        if (!(wn[n] > 0.0)) nonf += (lwn[n] == -INFINITY || lwn[n] != lwn[n]) ? 1 : 0;
+        sw2 += wn[n] * wn[n];
+        s->logw[n] = (wn[n] > 0.0) ? log(wn[n]) : -INFINITY;
+    }
+    memcpy(s->x, xn, sizeof(double) * N * d);
+    memcpy(s->theta, thn, sizeof(double) * N * p);
+    memcpy(s->theta_bar, mean, sizeof(double) * p);
+    memcpy(s->C, cov, sizeof(double) * p * p);
+    memcpy(s->L, L, sizeof(double) * p * p);
+    s->j = step;
+    s->t = t_next;
+    if (dg) {
+        dg->ess = 1.0 / sw2;
+        for (int i = 0; i < d; ++i) {
+            double v = 0.0;
+            for (long n = 0; n < N; ++n) if (wn[n] > 0.0) v += wn[n] * xn[n * d + i];
+            dg->state_mean[i] = v;
+        }
+        dg->newton_iters = it_tot; dg->newton_fails = fail_tot; dg->lu_fails = lu_tot;
+        dg->nonfinite = nonf; dg->jitters = jit; dg->first_anc = anc[0];
+    }
+done:
+    free(mshr); free(xbar); free(lbar); free(lg); free(g); free(anc);
+    free(xn); free(thn); free(lwn); free(wn);
+    return status;
+}
+
+/* diagnostic entry used by the pins: the ancestor vector and the first-stage
+ * weights of one step, without committing anything (same arithmetic as
+ * steps 2-3 of or_filter_step). */
+int or_filter_stage1(const or_config* cfg, const or_state* s, double t_next,
+                     const double* y, const double* sigma, double* g_out, int32_t* anc_out)
+{
+    long N = cfg->N;
+    int d = cfg->d, p = cfg->p, m = cfg->m;
+    double h = (t_next - s->t) / cfg->substeps;
+    double a = cfg->a;
+    double* lg = (double*)malloc(sizeof(double) * N);
+#pragma omp parallel for schedule(dynamic, 64)
+    for (long n = 0; n < N; ++n) {
+        double mm[OR_PMAX], xb[OR_DMAX];
+        for (int i = 0; i < p; ++i) mm[i] = a * s->theta[n * p + i] + (1.0 - a) * s->theta_bar[i];
+        or_psi(cfg->model, d, p, cfg->mc, cfg->rates_fixed, s->x + n * d, mm, h, cfg->substeps,
+               cfg->order, 0, cfg->rtol, cfg->kmax, cfg->floor_, NULL, 0, xb, NULL, NULL);
+        lg[n] = s->logw[n] + or_loglik(m, cfg->obs, y, sigma, xb);
+    }
+    int st = OR_OK;
+    if (or_normalise(N, lg, g_out) == -INFINITY) st = OR_EDEGENERATE;
+    else {
+        uint64_t key[2] = {cfg->seed, 0}, ctr[4] = {s->j + 1, 0, PUR_RESAMPLE, 0}, wv[4];
+        or_philox4x64(ctr, key, wv);
+        st = or_resample(N, g_out, wv[0], anc_out);
+    }
+    free(lg);
+    return st;
+}
+
+int or_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void or_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
