@@ -1,0 +1,163 @@
+/*
+ * pf.h -- C ABI of the MI355X particle-filter library.
+ *
+ * The library implements the LMM PF-SMC sampler (Arnold, Calvetti &
+ * Somersalo, Sec. 2, Algorithm 1): a Liu-West auxiliary particle filter whose
+ * particles carry a stiff ODE state propagated between observations by fixed
+ * step BDF formulas with Newton iterations, an innovation whose variance
+ * comes from the integrator's local-error estimate, likelihood weighting,
+ * systematic resampling and the weighted parameter mean and covariance.
+ *
+ * Conventions for every call:
+ *  - Pointers named in the signatures are HOST pointers unless stated.
+ *    Host arrays are owned by the caller and only read (or written) during
+ *    the call; the library keeps no reference to them.
+ *  - Handles are owned by the library and released by the matching destroy.
+ *  - Errors are returned as pf_status; pf_last_error() gives a message for
+ *    the calling thread.  On any error the filter's ensemble is unchanged.
+ *  - A filter is not re-entrant; different filters of one context may be
+ *    driven from different threads (the context serialises submission).
+ *
+ * Layout of the ensemble in device memory (HBM): structure of arrays, one
+ * contiguous array per state component and per parameter, padded to a
+ * multiple of 256 particles (padding particles carry zero weight).
+ */
+#ifndef PF_H
+#define PF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pf_context pf_context;
+typedef struct pf_filter pf_filter;
+
+typedef enum {
+    PF_OK = 0,
+    PF_EINVAL = 1,       /* bad argument, NULL pointer, size mismatch, NaN data */
+    PF_ENOMEM = 2,       /* the context's device pool cannot hold the request */
+    PF_EADMIT = 3,       /* not admitted now (serving: try again when memory frees) */
+    PF_EDEGENERATE = 4,  /* every weight zero or covariance not factorable: step skipped */
+    PF_ENONFINITE = 5,   /* reserved */
+    PF_EDEVICE = 6,      /* HIP runtime error (message in pf_last_error) */
+    PF_EBUSY = 7,        /* too many steps in flight for this filter */
+    PF_EORDER = 8        /* observation time not after the filter's current time */
+} pf_status;
+
+typedef enum {
+    PF_MODEL_ROBERTSON = 1, /* 3 states, 3 log-rates (A->B, 2B->B+C, B+C->A+C) */
+    PF_MODEL_CHAIN16 = 2    /* 16 compartments, first 12 log-rates estimated */
+} pf_model;
+
+typedef enum { PF_LMM_BDF = 0 } pf_lmm;
+
+typedef enum {
+    PF_PREC_FP64 = 0,      /* propagation (BDF + Newton + LU) in double */
+    PF_PREC_FP32_PROP = 1  /* propagation in float; weights, moments, Cholesky in double */
+} pf_precision;
+
+/*
+ * Filter configuration (Algorithm 1, problem statement of Sec. 2).
+ * Array fields are host pointers read during pf_create only.
+ */
+typedef struct {
+    uint32_t struct_size;        /* sizeof(pf_config), for ABI versioning */
+    pf_model model;
+    uint32_t d, p, m;            /* state dim, estimated log-params, observed components */
+    const uint32_t* obs_index;   /* [m] observed state components (0-based) */
+    const double* model_consts;  /* chain: [V(16), K(16)]; Robertson: NULL */
+    uint32_t n_model_consts;     /* 32 for the chain, 0 for Robertson */
+    const double* rates_fixed;   /* chain: [16] rates; entries p..15 are the known ones */
+    uint32_t n_rates_fixed;
+    uint64_t n_particles;        /* N >= 1, at most 2^24 */
+    uint64_t seed;               /* key of the counter-based RNG */
+    double t0;                   /* time of x0 */
+    const double* x0;            /* [d] initial state, the same for every particle */
+    const double* prior_mean;    /* [p] Gaussian prior of the log-parameters */
+    const double* prior_sd;      /* [p] */
+    double shrink_a;             /* Liu-West factor, 0 < a < 1; jitter s = sqrt(1 - a^2) */
+    pf_lmm lmm;
+    uint32_t order;              /* BDF order k, 1..3 */
+    uint32_t substeps;           /* fixed steps per observation interval, >= 1 */
+    uint32_t newton_max_iter;    /* >= 1 */
+    double newton_rtol;          /* stopping test max |dx_i| / max(|x_i|, floor_i) */
+    const double* state_floor;   /* [d] scale floors of that test */
+    pf_precision precision;
+} pf_config;
+
+/*
+ * Context: one device, one HIP stream, a device memory pool of pool_bytes
+ * (0 = 1/4 of free device memory) from which every filter's ensemble is
+ * carved.  hip_stream: a hipStream_t to submit on (NULL: the context creates
+ * its own).
+ */
+pf_status pf_context_create(int device, uint64_t pool_bytes, void* hip_stream, pf_context** out);
+void pf_context_destroy(pf_context* ctx);
+
+/* Bytes of pool memory one filter with this configuration needs. */
+uint64_t pf_filter_bytes(const pf_config* cfg);
+
+/* Pool memory: bytes in use and capacity. */
+pf_status pf_context_memory(pf_context* ctx, uint64_t* used, uint64_t* capacity);
+
+/*
+ * Algorithm 1, step 1: draw the ensemble from the prior (theta = mean + sd z,
+ * x = x0, w = 1/N) and compute the parameter mean, covariance and Cholesky
+ * factor.  Returns PF_ENOMEM when the pool cannot hold the ensemble.
+ * Synchronous.
+ */
+pf_status pf_create(pf_context* ctx, const pf_config* cfg, pf_filter** out);
+
+/*
+ * Algorithm 1, steps 2-6 for one observation y[m] with known noise sd
+ * sigma[m] at time t_obs > current time.  Synchronous: returns the step's
+ * status (PF_EDEGENERATE: the step was skipped, ensemble unchanged).
+ */
+pf_status pf_assimilate(pf_filter* f, double t_obs, const double* y, const double* sigma);
+
+/* Asynchronous form: enqueues the step and returns a ticket (per filter,
+ * increasing).  PF_EBUSY when 64 steps of this filter are already pending. */
+pf_status pf_assimilate_async(pf_filter* f, double t_obs, const double* y, const double* sigma,
+                              uint64_t* ticket);
+
+/* Waits for a ticket of this filter and returns that step's status. */
+pf_status pf_wait(pf_filter* f, uint64_t ticket);
+
+/*
+ * Batched form: one step for `count` distinct filters of one context, as a
+ * single submission.  y and sigma are [count][4] (row i uses its filter's
+ * first m entries).  Each filter's result is identical to assimilating it
+ * alone.  tickets[count] (may be NULL) receive the per-filter tickets.
+ */
+pf_status pf_assimilate_batch(pf_context* ctx, uint32_t count, pf_filter* const* filters,
+                              const double* t_obs, const double* y, const double* sigma,
+                              uint64_t* tickets);
+
+/*
+ * Posterior summary after the last completed step (waits for pending steps):
+ * mean[p] and cov[p*p] (row-major) of the log-parameters (Algorithm 1 step 6),
+ * optionally the weighted state mean[d], the effective sample size and the
+ * number of assimilated observations.  Any output pointer may be NULL.
+ */
+pf_status pf_posterior(pf_filter* f, double* mean, double* cov, double* state_mean, double* ess,
+                       uint64_t* step);
+
+/* Counters since creation: Newton iterations, steps that hit the iteration
+ * cap, particles given weight zero for a non-finite state, Cholesky jitters. */
+pf_status pf_stats(pf_filter* f, uint64_t* newton_iters, uint64_t* newton_fails,
+                   uint64_t* nonfinite, uint64_t* jitters);
+
+/* Releases the filter's pool memory after its pending steps complete. */
+void pf_destroy(pf_filter* f);
+
+const char* pf_status_str(pf_status s);
+const char* pf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PF_H */

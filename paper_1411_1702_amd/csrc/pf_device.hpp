@@ -1,0 +1,296 @@
+// pf_device.hpp -- per-lane device mathematics of the sampler: the
+// counter-based RNG, the two models, and the BDF integrator Psi with its
+// Newton solve and local-error estimate (Algorithm 1, steps 2 and 4).
+// One particle per lane; everything here lives in registers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pf_types.hpp"
+
+namespace pf {
+
+// ---------------------------------------------------------------------------
+// Philox4x64-10 (Salmon, Moraes, Dror & Shaw, SC'11): ten rounds of two
+// 64x64->128 multiplies; the key advances by the Weyl constants between
+// rounds.  Counter words are (step, particle, purpose, block), key (seed, 0).
+// ---------------------------------------------------------------------------
+struct Philox {
+    static constexpr uint64_t kMulA = 0xD2E7470EE14C6C93ULL;
+    static constexpr uint64_t kMulB = 0xCA5A826395121157ULL;
+    static constexpr uint64_t kWeylA = 0x9E3779B97F4A7C15ULL;
+    static constexpr uint64_t kWeylB = 0xBB67AE8584CAA73BULL;
+
+    __device__ static inline void block(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
+                                        uint64_t k0, uint64_t k1, uint64_t out[4])
+    {
+#pragma unroll
+        for (int round = 0; round < 10; ++round) {
+            const uint64_t pa_lo = kMulA * c0, pa_hi = __umul64hi(kMulA, c0);
+            const uint64_t pb_lo = kMulB * c2, pb_hi = __umul64hi(kMulB, c2);
+            const uint64_t n0 = pb_hi ^ c1 ^ k0;
+            const uint64_t n2 = pa_hi ^ c3 ^ k1;
+            c0 = n0;
+            c1 = pb_lo;
+            c2 = n2;
+            c3 = pa_lo;
+            k0 += kWeylA;
+            k1 += kWeylB;
+        }
+        out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+    }
+};
+
+// (0,1) uniform from the top 53 bits of a word
+__device__ inline double unit_open(uint64_t w) { return ((double)(w >> 11) + 0.5) * 0x1p-53; }
+
+// `count` standard normals of one (step, particle, purpose): block b gives
+// words w0..w3 and the Box-Muller pairs (w0, w1) and (w2, w3).
+template <int COUNT>
+__device__ inline void normals(uint64_t seed, uint64_t step, uint64_t particle, uint64_t purpose,
+                               double z[COUNT])
+{
+    constexpr double kTwoPi = 6.283185307179586476925286766559;
+#pragma unroll
+    for (int b = 0; b < (COUNT + 3) / 4; ++b) {
+        uint64_t w[4];
+        Philox::block(step, particle, purpose, (uint64_t)b, seed, 0, w);
+        const double rad0 = sqrt(-2.0 * log(unit_open(w[0])));
+        const double rad1 = sqrt(-2.0 * log(unit_open(w[2])));
+        double s0, c0, s1, c1;
+        sincos(kTwoPi * unit_open(w[1]), &s0, &c0);
+        sincos(kTwoPi * unit_open(w[3]), &s1, &c1);
+        const double v[4] = {rad0 * c0, rad0 * s0, rad1 * c1, rad1 * s1};
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+            if (4 * b + s < COUNT) z[4 * b + s] = v[s];
+    }
+}
+
+// reciprocal: single-instruction v_rcp_f32 in FP32 (about 1 ulp), correctly
+// rounded division in FP64
+__device__ inline float recip(float v) { return __builtin_amdgcn_rcpf(v); }
+__device__ inline double recip(double v) { return 1.0 / v; }
+
+template <class R> __device__ inline R rabs(R v) { return v < R(0) ? -v : v; }
+template <class R> __device__ inline R rmax(R a, R b) { return a > b ? a : b; }
+
+// ---------------------------------------------------------------------------
+// Models.  `eval` returns f(x) and the factorisation of the Newton matrix
+// A = I - c J(x); `solve` overwrites b with A^{-1} b.
+// ---------------------------------------------------------------------------
+
+// Robertson kinetics.  A = I - cJ has A31 = 0, and for x >= 0 every pivot of
+// the unpivoted elimination is >= 1 (the columns of J sum to zero), so the
+// elimination runs in the natural order: two multipliers and three pivots.
+template <class R>
+struct Robertson {
+    static constexpr int D = 3;
+    static constexpr int P = 3;
+    R k1, k2, k3;
+
+    struct LU { R inv11, l21, a12, a13, u23, inv22, l32, inv33, c; };
+
+    __device__ inline void set_params(const double th[P], const FilterDesc&)
+    {
+        k1 = (R)exp(th[0]);
+        k2 = (R)exp(th[1]);
+        k3 = (R)exp(th[2]);
+    }
+
+    __device__ inline void eval(const R x[D], R c, R f[D], LU& lu) const
+    {
+        const R r1 = k1 * x[0];
+        const R r2 = k2 * x[1] * x[1];
+        const R r3 = k3 * x[1] * x[2];
+        f[0] = r3 - r1;
+        f[1] = r1 - r2 - r3;
+        f[2] = r2;
+        const R ck1 = c * k1, ck3 = c * k3, c2k2x2 = R(2) * c * k2 * x[1];
+        const R a11 = R(1) + ck1;
+        lu.inv11 = recip(a11);
+        lu.l21 = -ck1 * lu.inv11;
+        lu.a12 = -ck3 * x[2];
+        lu.a13 = -ck3 * x[1];
+        const R a22 = R(1) + c2k2x2 + ck3 * x[2];
+        const R a23 = ck3 * x[1];
+        const R u22 = a22 - lu.l21 * lu.a12;
+        lu.u23 = a23 - lu.l21 * lu.a13;
+        lu.inv22 = recip(u22);
+        lu.l32 = -c2k2x2 * lu.inv22;
+        lu.inv33 = recip(R(1) - lu.l32 * lu.u23);
+        lu.c = c;
+    }
+
+    __device__ inline void solve(const LU& lu, R b[D]) const
+    {
+        const R b2 = b[1] - lu.l21 * b[0];
+        const R b3 = b[2] - lu.l32 * b2;
+        const R x3 = b3 * lu.inv33;
+        const R x2 = (b2 - lu.u23 * x3) * lu.inv22;
+        b[0] = (b[0] - lu.a12 * x2 - lu.a13 * x3) * lu.inv11;
+        b[1] = x2;
+        b[2] = x3;
+    }
+};
+
+// 16-compartment chain with Michaelis-Menten losses,
+//   x_i' = k_{i-1} x_{i-1} - k_i x_i - V_i x_i / (K_i + x_i),  unit influx at i = 1.
+// J is lower bidiagonal, so A = I - cJ is solved by forward substitution.
+template <class R>
+struct Chain16 {
+    static constexpr int D = 16;
+    static constexpr int P = 12;
+    R k[D];
+    const R* VK;   // [V(16), K(16)], wave-uniform
+
+    struct LU { R inv[D]; R c; };
+
+    __device__ inline void set_params(const double th[P], const FilterDesc& fd)
+    {
+#pragma unroll
+        for (int i = 0; i < D; ++i) k[i] = i < P ? (R)exp(th[i]) : (R)fd.rates_fixed[i];
+        if constexpr (sizeof(R) == 4) VK = (const R*)fd.mc_f;
+        else VK = (const R*)fd.mc;
+    }
+
+    __device__ inline void eval(const R x[D], R c, R f[D], LU& lu) const
+    {
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            const R V = VK[i], K = VK[D + i];
+            const R r = recip(K + x[i]);
+            const R inflow = i == 0 ? R(1) : k[i - 1] * x[i - 1];
+            f[i] = inflow - k[i] * x[i] - V * x[i] * r;
+            lu.inv[i] = recip(R(1) + c * (k[i] + V * K * r * r));
+        }
+        lu.c = c;
+    }
+
+    __device__ inline void solve(const LU& lu, R b[D]) const
+    {
+        b[0] = b[0] * lu.inv[0];
+#pragma unroll
+        for (int i = 1; i < D; ++i) b[i] = (b[i] + lu.c * k[i - 1] * b[i - 1]) * lu.inv[i];
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Psi: M fixed BDF steps of size h from x (overwritten with the result).
+// Step m uses order q = max(1, min(KORD, m-1)); the Newton iteration starts
+// from x_{m-1} at m = 1 and from the degree-q extrapolation afterwards; stop
+// when every |dx_i| <= rtol * max(|x_i|, floor_i), or after kmax iterations.
+// With LTE, gam accumulates the squared filtered Milne estimates
+//   e_m = kappa_q (I - h beta_q J)^{-1} (x_m - x_m^(0)),
+// x^(0) being the extrapolation (kappa = |C|/(1+|C|)) or, at m = 1, the
+// Euler value x_0 + h f(x_0) (kappa = 1/2); J from the last Newton iteration.
+// ---------------------------------------------------------------------------
+struct BdfCoef {
+    double a1, a2, a3;   // x_m + a1 x_{m-1} + a2 x_{m-2} + a3 x_{m-3} = h beta f_m
+    double beta;
+    double kappa;        // |C_{q+1}| / (1 + |C_{q+1}|)
+};
+
+__device__ inline BdfCoef bdf_coef(int q)
+{
+    if (q == 1) return {-1.0, 0.0, 0.0, 1.0, 1.0 / 3.0};
+    if (q == 2) return {-4.0 / 3.0, 1.0 / 3.0, 0.0, 2.0 / 3.0, 2.0 / 11.0};
+    return {-18.0 / 11.0, 9.0 / 11.0, -2.0 / 11.0, 6.0 / 11.0, 3.0 / 25.0};
+}
+
+template <class Model, class R, int KORD, bool LTE>
+__device__ inline void integrate(const Model& md, R x[Model::D], R gam[Model::D], double h_d,
+                                 int M, R rtol, const R* __restrict__ floor_, int kmax,
+                                 uint32_t& iters, uint32_t& fails)
+{
+    constexpr int D = Model::D;
+    const R h = (R)h_d;
+    R h1[D], h2[D], h3[D];   // x_{m-2}, x_{m-3}, x_{m-4}
+    if constexpr (LTE) {
+#pragma unroll
+        for (int i = 0; i < D; ++i) gam[i] = R(0);
+    }
+    int avail = 0;           // history beyond x_{m-1}
+    for (int m = 1; m <= M; ++m) {
+        const int q = avail < 1 ? 1 : (avail < KORD ? avail : KORD);
+        const BdfCoef co = bdf_coef(q);
+        const R c = h * (R)co.beta;
+        R psi[D], xp[D], xn[D];
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            R s = -(R)co.a1 * x[i];
+            if (KORD >= 2 && q >= 2) s -= (R)co.a2 * h1[i];
+            if (KORD >= 3 && q >= 3) s -= (R)co.a3 * h2[i];
+            psi[i] = s;
+            R p = x[i];
+            if (avail >= 1) {
+                if (q == 1) p = R(2) * x[i] - h1[i];
+                else if (KORD >= 2 && q == 2) p = R(3) * x[i] - R(3) * h1[i] + h2[i];
+                else if (KORD >= 3) p = R(4) * x[i] - R(6) * h1[i] + R(4) * h2[i] - h3[i];
+            }
+            xp[i] = p;
+            xn[i] = p;
+        }
+        typename Model::LU lu;
+        bool conv = false;
+        for (int it = 0; it < kmax; ++it) {
+            R f[D];
+            md.eval(xn, c, f, lu);
+            if (LTE && avail == 0 && it == 0) {
+#pragma unroll
+                for (int i = 0; i < D; ++i) xp[i] = x[i] + h * f[i];
+            }
+            R b[D];
+#pragma unroll
+            for (int i = 0; i < D; ++i) b[i] = (psi[i] + c * f[i]) - xn[i];
+            md.solve(lu, b);
+            ++iters;
+            bool ok = true;
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                xn[i] += b[i];
+                ok = ok && (rabs(b[i]) <= rtol * rmax(rabs(xn[i]), floor_[i]));
+            }
+            if (ok) { conv = true; break; }
+        }
+        if (!conv) ++fails;
+        if constexpr (LTE) {
+            const R kap = avail == 0 ? R(0.5) : (R)co.kappa;
+            R e[D];
+#pragma unroll
+            for (int i = 0; i < D; ++i) e[i] = xn[i] - xp[i];
+            md.solve(lu, e);
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                const R v = kap * e[i];
+                gam[i] += v * v;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            if (KORD >= 3) h3[i] = h2[i];
+            if (KORD >= 2) h2[i] = h1[i];
+            h1[i] = x[i];
+            x[i] = xn[i];
+        }
+        avail = avail < KORD ? avail + 1 : KORD;
+    }
+}
+
+// Gaussian log-likelihood of the observed components, constants dropped;
+// -inf for a non-finite observed state.
+template <class R>
+__device__ inline double loglik(const R* x, const int32_t* obs, const double* y, const double* sg,
+                                int m)
+{
+    double s = 0.0;
+    for (int i = 0; i < m; ++i) {
+        const double v = (double)x[obs[i]];
+        if (!isfinite(v)) return -INFINITY;
+        const double r = (y[i] - v) / sg[i];
+        s += r * r;
+    }
+    return -0.5 * s;
+}
+
+}  // namespace pf

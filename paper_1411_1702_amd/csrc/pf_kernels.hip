@@ -1,0 +1,692 @@
+// pf_kernels.hip -- the device side of one assimilation step (Algorithm 1,
+// steps 2-6) for a batch of filters, plus filter initialisation (step 1).
+//
+// Work is a list of (batch entry, tile) items; a workgroup of TILE lanes
+// owns one tile of TILE particles, one particle per lane.  Kernels loop over
+// the list (grid-stride), so one launch covers every filter in the batch.
+// Per-filter reductions use fixed tiles combined in a fixed order by the last
+// tile to finish (an atomic counter per filter and kernel), so a filter's
+// arithmetic never depends on what else is in the batch.
+//
+//   k_begin    : validate the step, compute h, copy y and sigma
+//   k_predict  : shrink, predictor Psi, first-stage log-weights, tile LSE
+//                (last tile: the filter's log-sum-exp)            steps 2, 3a
+//   k_count    : integer weights q = floor(g 2^S), tile sums
+//                (last tile: scan of tile sums, T and offset V)   step 3b
+//   k_scatter  : ancestors by scatter of the integer CDF           step 3b
+//   k_update   : gather, proliferate, Psi with local-error estimate,
+//                innovation, second-stage log-weights, tile moments
+//                (last tile: mean, covariance, ESS, Cholesky,
+//                commit)                                           steps 3c-6
+//   k_end      : record the step's status by ticket
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "pf_device.hpp"
+#include "pf_types.hpp"
+
+namespace pf {
+
+constexpr int WAVE = 64;
+constexpr int NWAVE = TILE / WAVE;
+
+// ---------------------------------------------------------------------------
+// block reductions (fixed butterfly + fixed wave order: deterministic)
+// ---------------------------------------------------------------------------
+__device__ inline double wave_max(double v)
+{
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ inline double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+__device__ inline unsigned long long wave_sum_u64(unsigned long long v)
+{
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+__device__ inline double block_max(double v, double* sh)
+{
+    v = wave_max(v);
+    const int w = threadIdx.x / WAVE, l = threadIdx.x % WAVE;
+    __syncthreads();
+    if (l == 0) sh[w] = v;
+    __syncthreads();
+    double r = sh[0];
+#pragma unroll
+    for (int i = 1; i < NWAVE; ++i) r = fmax(r, sh[i]);
+    return r;
+}
+__device__ inline double block_sum(double v, double* sh)
+{
+    v = wave_sum(v);
+    const int w = threadIdx.x / WAVE, l = threadIdx.x % WAVE;
+    __syncthreads();
+    if (l == 0) sh[w] = v;
+    __syncthreads();
+    double r = sh[0];
+#pragma unroll
+    for (int i = 1; i < NWAVE; ++i) r += sh[i];
+    return r;
+}
+__device__ inline unsigned long long block_sum_u64(unsigned long long v, unsigned long long* sh)
+{
+    v = wave_sum_u64(v);
+    const int w = threadIdx.x / WAVE, l = threadIdx.x % WAVE;
+    __syncthreads();
+    if (l == 0) sh[w] = v;
+    __syncthreads();
+    unsigned long long r = sh[0];
+#pragma unroll
+    for (int i = 1; i < NWAVE; ++i) r += sh[i];
+    return r;
+}
+
+// exclusive prefix sum over the block (uint64, exact); returns the total
+__device__ inline unsigned long long block_exscan_u64(unsigned long long v, unsigned long long& excl,
+                                                      unsigned long long* sh)
+{
+    const int w = threadIdx.x / WAVE, l = threadIdx.x % WAVE;
+    unsigned long long incl = v;
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+        const unsigned long long t = __shfl_up(incl, o);
+        if (l >= o) incl += t;
+    }
+    __syncthreads();
+    if (l == WAVE - 1) sh[w] = incl;
+    __syncthreads();
+    unsigned long long base = 0, total = 0;
+#pragma unroll
+    for (int i = 0; i < NWAVE; ++i) {
+        if (i < w) base += sh[i];
+        total += sh[i];
+    }
+    excl = base + incl - v;
+    return total;
+}
+
+// The calling block is the last of `ntiles` to arrive at counter `ctr`?
+// Release this tile's partial results, then acquire everybody's.
+__device__ inline bool last_tile(uint32_t* ctr, uint32_t ntiles, int* sh_flag)
+{
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t prev = atomicAdd(ctr, 1u);
+        const int last = prev == ntiles - 1;
+        if (last) *ctr = 0;   // every tile has arrived: reset for the next step
+        *sh_flag = last;
+    }
+    __syncthreads();
+    const bool last = *sh_flag != 0;
+    if (last) __threadfence();
+    return last;
+}
+
+// Combine per-tile log-domain partials part[t*stride + 0] = tile max,
+// part[t*stride + 1 + a] = sums scaled by exp(-tile max), a < nsum, in a
+// fixed order: out[a] = sum_t exp(max_t - M) part[t][1+a].  Returns M.
+__device__ double combine_tiles(const double* part, int stride, int ntiles, int nsum, double* out,
+                                double* sh /* >= TILE doubles */)
+{
+    // global max: fixed strided pass then the fixed block tree
+    double mx = -INFINITY;
+    for (int t = threadIdx.x; t < ntiles; t += TILE) mx = fmax(mx, part[(size_t)t * stride]);
+    const double M = block_max(mx, sh);
+    const int groups = TILE / nsum;
+    const int a = threadIdx.x % nsum, g = threadIdx.x / nsum;
+    double acc = 0.0;
+    if (g < groups && M > -INFINITY) {
+        for (int t = g; t < ntiles; t += groups) {
+            const double mt = part[(size_t)t * stride];
+            if (mt > -INFINITY) acc += exp(mt - M) * part[(size_t)t * stride + 1 + a];
+        }
+    }
+    __syncthreads();
+    if (g < groups) sh[g * nsum + a] = acc;
+    __syncthreads();
+    if (threadIdx.x < nsum) {
+        double s = 0.0;
+        for (int gg = 0; gg < groups; ++gg) s += sh[gg * nsum + threadIdx.x];
+        out[threadIdx.x] = s;
+    }
+    __syncthreads();
+    return M;
+}
+
+// ---------------------------------------------------------------------------
+// moments of the parameters for one tile: partial[0] = max l, then
+// s0 = sum e, s00 = sum e^2, S1 = sum e d, S2 = sum e d d^T (upper triangle,
+// row by row), Sx = sum e x, with e = exp(l - max) and d = theta - c.
+// PM, DM bound p and d at compile time so every register index is static.
+// ---------------------------------------------------------------------------
+template <class R, int PM, int DM>
+__device__ void tile_moments(double l, bool valid, const double* th, const R* x, const double* cshift,
+                             int p, int d, double* out_part, double* sh)
+{
+    const double lv = valid ? l : -INFINITY;
+    const double Mt = block_max(lv, sh);
+    const double e = (valid && lv > -INFINITY) ? exp(lv - Mt) : 0.0;
+    double dv[PM];
+#pragma unroll
+    for (int i = 0; i < PM; ++i) dv[i] = (i < p && e > 0.0) ? th[i] - cshift[i] : 0.0;
+    __shared__ double wsum[NWAVE][NACC_MAX];
+    const int w = threadIdx.x / WAVE, ln = threadIdx.x % WAVE;
+    int a = 0;
+    auto emit = [&](double v) {
+        v = wave_sum(v);
+        if (ln == 0) wsum[w][a] = v;
+        ++a;
+    };
+    emit(e);
+    emit(e * e);
+#pragma unroll
+    for (int i = 0; i < PM; ++i)
+        if (i < p) emit(e * dv[i]);
+#pragma unroll
+    for (int i = 0; i < PM; ++i)
+#pragma unroll
+        for (int j = i; j < PM; ++j)
+            if (j < p) emit(e * dv[i] * dv[j]);
+#pragma unroll
+    for (int i = 0; i < DM; ++i)
+        if (i < d) emit(e > 0.0 ? e * (double)x[i] : 0.0);
+    const int nsum = a;
+    __syncthreads();
+    if (threadIdx.x < nsum) {
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < NWAVE; ++i) s += wsum[i][threadIdx.x];
+        out_part[1 + threadIdx.x] = s;
+    }
+    if (threadIdx.x == 0) out_part[0] = Mt;
+    __syncthreads();
+}
+
+// Cholesky C = L L^T with the jitter rule (C + delta I, delta = 1e-10 tr/p,
+// then 10x, at most five times).  Returns the jitter count or -1.
+__device__ int chol_jitter(const double* C, double* L, int p)
+{
+    double tr = 0.0;
+    for (int i = 0; i < p; ++i) tr += C[i * p + i];
+    double delta = 0.0;
+    for (int attempt = 0; attempt <= 5; ++attempt) {
+        if (attempt == 1) delta = 1e-10 * tr / p;
+        else if (attempt > 1) delta *= 10.0;
+        bool ok = true;
+        for (int i = 0; i < p * p; ++i) L[i] = 0.0;
+        for (int j = 0; j < p && ok; ++j) {
+            double s = C[j * p + j] + delta;
+            for (int k = 0; k < j; ++k) s -= L[j * p + k] * L[j * p + k];
+            if (!(s > 0.0) || !isfinite(s)) { ok = false; break; }
+            const double ljj = sqrt(s);
+            L[j * p + j] = ljj;
+            for (int i = j + 1; i < p; ++i) {
+                double t = C[i * p + j];
+                for (int k = 0; k < j; ++k) t -= L[i * p + k] * L[j * p + k];
+                L[i * p + j] = t / ljj;
+            }
+        }
+        if (ok) return attempt;
+    }
+    return -1;
+}
+
+// Last tile of a moment pass: combine partials, form mean / covariance /
+// ESS / state mean, factor, and commit (flip = switch to the new buffers and
+// advance the step counter).
+__device__ void finalize_moments(const FilterDesc& fd, FilterState& st, bool flip, double* sh)
+{
+    __shared__ double tot[NACC_MAX];
+    __shared__ double mean[PMAX], dm[PMAX], Cm[PMAX * PMAX], Lm[PMAX * PMAX];
+    const int p = fd.p, d = fd.d;
+    combine_tiles(fd.part2, fd.nacc, fd.ntiles, fd.nacc - 1, tot, sh);
+    if (threadIdx.x == 0) {
+        const double s0 = tot[0], s00 = tot[1];
+        if (!(s0 > 0.0) || !isfinite(s0)) {
+            st.status = ST_EDEGENERATE;
+        } else {
+            const double inv = 1.0 / s0;
+            for (int i = 0; i < p; ++i) {
+                dm[i] = tot[2 + i] * inv;
+                mean[i] = st.theta_bar[i] + dm[i];
+            }
+            int a = 2 + p;
+            for (int i = 0; i < p; ++i)
+                for (int j = i; j < p; ++j, ++a) {
+                    const double v = tot[a] * inv - dm[i] * dm[j];
+                    Cm[i * p + j] = v;
+                    Cm[j * p + i] = v;
+                }
+            const int jit = chol_jitter(Cm, Lm, p);
+            if (jit < 0) {
+                st.status = ST_EDEGENERATE;
+            } else {
+                for (int i = 0; i < p; ++i) st.theta_bar[i] = mean[i];
+                for (int i = 0; i < p * p; ++i) { st.C[i] = Cm[i]; st.L[i] = Lm[i]; }
+                for (int i = 0; i < d; ++i) st.state_mean[i] = tot[a + i] * inv;
+                st.ess = s0 * s0 / s00;
+                st.jitters += (unsigned long long)jit;
+                if (flip) {
+                    st.cur ^= 1;
+                    st.j = st.step;
+                    st.t = st.t_next;
+                }
+                st.status = ST_OK;
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// common item decode
+// ---------------------------------------------------------------------------
+struct Item {
+    int slot, tile;
+};
+__device__ inline Item decode(uint32_t it, const StepRec* recs)
+{
+    Item r;
+    r.slot = recs[it >> 16].slot;
+    r.tile = (int)(it & 0xFFFFu);
+    return r;
+}
+
+// status broadcast from one lane: the whole block takes the same branch
+__device__ inline int block_status(const FilterState& st, int* sh)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) *sh = st.status;
+    __syncthreads();
+    return *sh;
+}
+
+// ---------------------------------------------------------------------------
+// begin / end of a step
+// ---------------------------------------------------------------------------
+__global__ void k_begin(const StepRec* recs, int count, const FilterDesc* descs, FilterState* states)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= count) return;
+    const StepRec& r = recs[b];
+    const FilterDesc& fd = descs[r.slot];
+    FilterState& st = states[r.slot];
+    st.seq = r.seq;
+    st.t_next = r.t_next;
+    for (int i = 0; i < MMAX; ++i) { st.y[i] = r.y[i]; st.sigma[i] = r.sigma[i]; }
+    st.step = st.j + 1;
+    if (!(r.t_next > st.t)) {
+        st.status = ST_EORDER;
+        return;
+    }
+    st.h = (r.t_next - st.t) / fd.substeps;
+    st.status = ST_OK;
+}
+
+__global__ void k_end(const StepRec* recs, int count, FilterState* states)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= count) return;
+    const StepRec& r = recs[b];
+    FilterState& st = states[r.slot];
+    st.ring[r.seq % RING] = st.status;
+}
+
+// ---------------------------------------------------------------------------
+// step 1: prior draw and initial moments
+// ---------------------------------------------------------------------------
+template <class R>
+__global__ __launch_bounds__(TILE) void k_init(int slot, const FilterDesc* descs, FilterState* states)
+{
+    __shared__ double sh[TILE];
+    __shared__ int flag;
+    const FilterDesc& fd = descs[slot];
+    FilterState& st = states[slot];
+    for (int tile = blockIdx.x; tile < fd.ntiles; tile += gridDim.x) {
+        const int n = tile * TILE + threadIdx.x;
+        const bool valid = n < fd.n;
+        double th[PMAX];
+        R xs[DMAX];
+        for (int i = 0; i < PMAX; ++i) th[i] = 0.0;
+        if (valid) {
+            double z[PMAX];
+            normals<PMAX>(fd.seed, 0, (uint64_t)n, PUR_PRIOR, z);
+            for (int i = 0; i < fd.p; ++i) {
+                th[i] = fd.prior_mean[i] + fd.prior_sd[i] * z[i];
+                fd.theta[0][(size_t)i * fd.npad + n] = th[i];
+            }
+            R* x = (R*)fd.x[0];
+            for (int i = 0; i < fd.d; ++i) {
+                xs[i] = (R)fd.x0[i];
+                x[(size_t)i * fd.npad + n] = xs[i];
+            }
+            fd.logw[0][n] = -log((double)fd.n);
+        } else {
+            for (int i = 0; i < DMAX; ++i) xs[i] = R(0);
+        }
+        tile_moments<R, PMAX, DMAX>(-log((double)fd.n), valid, th, xs, fd.prior_mean, fd.p, fd.d,
+                        fd.part2 + (size_t)tile * fd.nacc, sh);
+        if (last_tile(&fd.done[3], fd.ntiles, &flag)) {
+            if (threadIdx.x < PMAX) st.theta_bar[threadIdx.x] = fd.prior_mean[threadIdx.x];
+            __syncthreads();
+            finalize_moments(fd, st, false, sh);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// steps 2 and 3(a): shrink, predictor, first-stage log-weights
+// ---------------------------------------------------------------------------
+template <class Model, class R, int KORD>
+__global__ __launch_bounds__(TILE) void k_predict(const uint32_t* items, int n_items, const StepRec* recs,
+                                                  const FilterDesc* descs, FilterState* states)
+{
+    constexpr int D = Model::D, P = Model::P;
+    __shared__ double sh[TILE];
+    __shared__ unsigned long long shu[NWAVE];
+    __shared__ int flag;
+    for (int itx = blockIdx.x; itx < n_items; itx += gridDim.x) {
+        const Item itm = decode(items[itx], recs);
+        const FilterDesc& fd = descs[itm.slot];
+        FilterState& st = states[itm.slot];
+        if (block_status(st, &flag) != ST_OK) continue;
+        const int n = itm.tile * TILE + threadIdx.x;
+        const bool valid = n < fd.n;
+        const int cur = st.cur;
+        double lg = -INFINITY;
+        uint32_t iters = 0, fails = 0;
+        if (valid) {
+            const R* xb = (const R*)fd.x[cur];
+            R x[D];
+#pragma unroll
+            for (int i = 0; i < D; ++i) x[i] = xb[(size_t)i * fd.npad + n];
+            double m[P];
+            const double a = fd.a;
+#pragma unroll
+            for (int i = 0; i < P; ++i)
+                m[i] = a * fd.theta[cur][(size_t)i * fd.npad + n] + (1.0 - a) * st.theta_bar[i];
+            Model md;
+            md.set_params(m, fd);
+            const R* fl = sizeof(R) == 4 ? (const R*)fd.floor_f : (const R*)fd.floor_;
+            integrate<Model, R, KORD, false>(md, x, nullptr, st.h, fd.substeps, (R)fd.rtol, fl,
+                                             fd.kmax, iters, fails);
+            const double lb = loglik<R>(x, fd.obs, st.y, st.sigma, fd.m);
+            lg = fd.logw[cur][n] + lb;
+            if (!(lg > -INFINITY)) lg = -INFINITY;   // NaN -> zero weight
+            fd.lbar[n] = lb;
+            fd.lg[n] = lg;
+        }
+        const double Mt = block_max(lg, sh);
+        const double e = lg > -INFINITY ? exp(lg - Mt) : 0.0;
+        const double s = block_sum(e, sh);
+        const unsigned long long it_sum = block_sum_u64(iters, shu);
+        const unsigned long long fl_sum = block_sum_u64(fails, shu);
+        if (threadIdx.x == 0) {
+            fd.part1[2 * itm.tile] = Mt;
+            fd.part1[2 * itm.tile + 1] = s;
+            atomicAdd(&st.newton_iters, it_sum);
+            if (fl_sum) atomicAdd(&st.newton_fails, fl_sum);
+        }
+        if (last_tile(&fd.done[0], fd.ntiles, &flag)) {
+            double tot[1];
+            __shared__ double tsh[1];
+            const double M = combine_tiles(fd.part1, 2, fd.ntiles, 1, tsh, sh);
+            tot[0] = tsh[0];
+            if (threadIdx.x == 0) {
+                st.lse_max = M;
+                st.lse_sum = tot[0];
+                if (!(M > -INFINITY) || !(tot[0] > 0.0) || !isfinite(M)) st.status = ST_EDEGENERATE;
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// step 3(b): systematic resampling in integers
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(TILE) void k_count(const uint32_t* items, int n_items, const StepRec* recs,
+                                                const FilterDesc* descs, FilterState* states)
+{
+    __shared__ unsigned long long shu[NWAVE];
+    __shared__ int flag;
+    for (int itx = blockIdx.x; itx < n_items; itx += gridDim.x) {
+        const Item itm = decode(items[itx], recs);
+        const FilterDesc& fd = descs[itm.slot];
+        FilterState& st = states[itm.slot];
+        if (block_status(st, &flag) != ST_OK) continue;
+        const int n = itm.tile * TILE + threadIdx.x;
+        unsigned long long q = 0;
+        if (n < fd.n) {
+            const double l = fd.lg[n];
+            const double g = fd.g_direct ? l : (l > -INFINITY ? exp(l - st.lse_max) / st.lse_sum : 0.0);
+            if (g > 0.0) q = (unsigned long long)floor(ldexp(g, fd.shift));
+            fd.q[n] = q;
+        }
+        const unsigned long long ts = block_sum_u64(q, shu);
+        if (threadIdx.x == 0) fd.tsum[itm.tile] = ts;
+        if (last_tile(&fd.done[1], fd.ntiles, &flag)) {
+            // exclusive scan of the tile sums, in chunks of TILE
+            unsigned long long carry = 0;
+            for (int base = 0; base < fd.ntiles; base += TILE) {
+                const int t = base + threadIdx.x;
+                const unsigned long long v = t < fd.ntiles ? fd.tsum[t] : 0ull;
+                unsigned long long ex;
+                const unsigned long long tot = block_exscan_u64(v, ex, shu);
+                if (t < fd.ntiles) fd.tsum[t] = carry + ex;
+                carry += tot;
+                __syncthreads();
+            }
+            if (threadIdx.x == 0) {
+                const unsigned long long T = carry;
+                if (T == 0) {
+                    st.status = ST_EDEGENERATE;
+                } else {
+                    uint64_t r;
+                    if (fd.g_direct) {
+                        r = st.V;
+                    } else {
+                        uint64_t w[4];
+                        Philox::block(st.step, 0, PUR_RESAMPLE, 0, fd.seed, 0, w);
+                        r = w[0];
+                    }
+                    st.T = T;
+                    st.V = __umul64hi(r, T);
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// first output slot of the copies of a particle whose inclusive cumulative
+// integer weight is c: F(c) = min(N, ceil((c N - V) / T)) if c N > V, else 0
+__device__ inline uint64_t first_slot(uint64_t c, uint64_t N, uint64_t T, uint64_t V)
+{
+    const uint64_t cn = c * N;
+    if (cn <= V) return 0;
+    const uint64_t f = (cn - V + T - 1) / T;
+    return f < N ? f : N;
+}
+
+__global__ __launch_bounds__(TILE) void k_scatter(const uint32_t* items, int n_items, const StepRec* recs,
+                                                  const FilterDesc* descs, FilterState* states)
+{
+    __shared__ unsigned long long shu[NWAVE];
+    __shared__ int flag;
+    for (int itx = blockIdx.x; itx < n_items; itx += gridDim.x) {
+        const Item itm = decode(items[itx], recs);
+        const FilterDesc& fd = descs[itm.slot];
+        FilterState& st = states[itm.slot];
+        if (block_status(st, &flag) != ST_OK) continue;
+        const int n = itm.tile * TILE + threadIdx.x;
+        const unsigned long long q = n < fd.n ? fd.q[n] : 0ull;
+        unsigned long long ex;
+        block_exscan_u64(q, ex, shu);
+        if (q > 0) {
+            const uint64_t N = (uint64_t)fd.n, T = st.T, V = st.V;
+            const uint64_t lo_c = fd.tsum[itm.tile] + ex;
+            const uint64_t lo = first_slot(lo_c, N, T, V);
+            const uint64_t hi = first_slot(lo_c + q, N, T, V);
+            for (uint64_t i = lo; i < hi; ++i) fd.anc[i] = n;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// steps 3(c)-6 per output slot
+// ---------------------------------------------------------------------------
+template <class Model, class R, int KORD>
+__global__ __launch_bounds__(TILE) void k_update(const uint32_t* items, int n_items, const StepRec* recs,
+                                                 const FilterDesc* descs, FilterState* states)
+{
+    constexpr int D = Model::D, P = Model::P;
+    __shared__ double sh[TILE];
+    __shared__ unsigned long long shu[NWAVE];
+    __shared__ int flag;
+    for (int itx = blockIdx.x; itx < n_items; itx += gridDim.x) {
+        const Item itm = decode(items[itx], recs);
+        const FilterDesc& fd = descs[itm.slot];
+        FilterState& st = states[itm.slot];
+        if (block_status(st, &flag) != ST_OK) continue;
+        const int n = itm.tile * TILE + threadIdx.x;
+        const bool valid = n < fd.n;
+        const int cur = st.cur, nxt = cur ^ 1;
+        double l = -INFINITY;
+        double th[PMAX];
+        R x[DMAX];
+#pragma unroll
+        for (int i = 0; i < PMAX; ++i) th[i] = 0.0;
+#pragma unroll
+        for (int i = 0; i < DMAX; ++i) x[i] = R(0);
+        uint32_t iters = 0, fails = 0, nonf = 0;
+        if (valid) {
+            int k = fd.anc[n];
+            // the scatter covers every slot exactly once; an out-of-range
+            // ancestor would be a bug: keep the read in bounds, zero the weight
+            const bool bad = k < 0 || k >= fd.n;
+            if (bad) k = 0;
+            // 3(c): the slot takes its ancestor's x_j, shrunk parameters and
+            // predictor likelihood
+            const R* xb = (const R*)fd.x[cur];
+#pragma unroll
+            for (int i = 0; i < D; ++i) x[i] = xb[(size_t)i * fd.npad + k];
+            const double a = fd.a;
+            double m[P];
+#pragma unroll
+            for (int i = 0; i < P; ++i)
+                m[i] = a * fd.theta[cur][(size_t)i * fd.npad + k] + (1.0 - a) * st.theta_bar[i];
+            const double lb = fd.lbar[k];
+            // 4(a): theta_{j+1} = m + s L z
+            double z[P];
+            normals<P>(fd.seed, st.step, (uint64_t)n, PUR_PROLIF, z);
+#pragma unroll
+            for (int i = 0; i < P; ++i) {
+                double v = 0.0;
+#pragma unroll
+                for (int c = 0; c <= i; ++c) v += st.L[i * fd.p + c] * z[c];
+                th[i] = m[i] + fd.s * v;
+            }
+            // 4(b)-(d): Psi with the local-error variance, then the innovation
+            Model md;
+            md.set_params(th, fd);
+            R gam[D];
+            R xw[D];
+#pragma unroll
+            for (int i = 0; i < D; ++i) xw[i] = x[i];
+            const R* fl = sizeof(R) == 4 ? (const R*)fd.floor_f : (const R*)fd.floor_;
+            integrate<Model, R, KORD, true>(md, xw, gam, st.h, fd.substeps, (R)fd.rtol, fl, fd.kmax,
+                                            iters, fails);
+            double zi[D];
+            normals<D>(fd.seed, st.step, (uint64_t)n, PUR_INNOV, zi);
+            R* xo = (R*)fd.x[nxt];
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                x[i] = (R)((double)xw[i] + sqrt((double)gam[i]) * zi[i]);
+                xo[(size_t)i * fd.npad + n] = x[i];
+            }
+#pragma unroll
+            for (int i = 0; i < P; ++i) fd.theta[nxt][(size_t)i * fd.npad + n] = th[i];
+            // 5: w = pi(y | x_{j+1}) / pi(y | xbar)
+            l = loglik<R>(x, fd.obs, st.y, st.sigma, fd.m) - lb;
+            if (!(l > -INFINITY) || bad) { l = -INFINITY; nonf = 1; }
+            fd.logw[nxt][n] = l;
+        }
+        const unsigned long long it_sum = block_sum_u64(iters, shu);
+        const unsigned long long fl_sum = block_sum_u64(fails, shu);
+        const unsigned long long nf_sum = block_sum_u64(nonf, shu);
+        if (threadIdx.x == 0) {
+            atomicAdd(&st.newton_iters, it_sum);
+            if (fl_sum) atomicAdd(&st.newton_fails, fl_sum);
+            if (nf_sum) atomicAdd(&st.nonfinite, nf_sum);
+        }
+        // 6: tile moments with shift theta_bar_j
+        tile_moments<R, P, D>(l, valid, th, x, st.theta_bar, P, D,
+                        fd.part2 + (size_t)itm.tile * fd.nacc, sh);
+        if (last_tile(&fd.done[2], fd.ntiles, &flag)) finalize_moments(fd, st, true, sh);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// test-only kernels
+// ---------------------------------------------------------------------------
+__global__ void k_test_philox(uint64_t n, const uint64_t* ctr, const uint64_t* key, uint64_t* out)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint64_t w[4];
+    Philox::block(ctr[4 * i], ctr[4 * i + 1], ctr[4 * i + 2], ctr[4 * i + 3], key[2 * i],
+                  key[2 * i + 1], w);
+    for (int s = 0; s < 4; ++s) out[4 * i + s] = w[s];
+}
+
+template <int COUNT>
+__global__ void k_test_normals(uint64_t n, uint64_t seed, uint64_t step, uint64_t purpose, double* out)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double z[COUNT];
+    normals<COUNT>(seed, step, i, purpose, z);
+    for (int s = 0; s < COUNT; ++s) out[i * COUNT + s] = z[s];
+}
+
+template <class Model, class R, int KORD, bool LTE>
+__global__ __launch_bounds__(TILE) void k_test_propagate(const FilterDesc* fdp, uint64_t n, const double* xin,
+                                                         const double* theta, double h, double* xout,
+                                                         double* gamma, unsigned long long* iters_out)
+{
+    constexpr int D = Model::D, P = Model::P;
+    __shared__ unsigned long long shu[NWAVE];
+    const FilterDesc& fd = *fdp;
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t iters = 0, fails = 0;
+    if (i < n) {
+        R x[D], gam[D];
+        double th[P];
+        for (int c = 0; c < D; ++c) x[c] = (R)xin[c * n + i];
+        for (int c = 0; c < P; ++c) th[c] = theta[c * n + i];
+        Model md;
+        md.set_params(th, fd);
+        const R* fl = sizeof(R) == 4 ? (const R*)fd.floor_f : (const R*)fd.floor_;
+        integrate<Model, R, KORD, LTE>(md, x, gam, h, fd.substeps, (R)fd.rtol, fl, fd.kmax, iters,
+                                       fails);
+        for (int c = 0; c < D; ++c) {
+            xout[c * n + i] = (double)x[c];
+            if (LTE && gamma) gamma[c * n + i] = (double)gam[c];
+        }
+    }
+    const unsigned long long s = block_sum_u64(iters, shu);
+    if (threadIdx.x == 0 && iters_out) atomicAdd(iters_out, s);
+}
+
+}  // namespace pf

@@ -1,0 +1,920 @@
+// pf_runtime.hip -- host runtime behind the C ABI of include/pf.h and
+// include/pf_test.h: context (device, stream, memory pool, filter table),
+// filter creation (prior draw), step submission for one filter or a batch,
+// tickets, posterior read-back, and the step-level test entry points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/pf.h"
+#include "../../include/pf_test.h"
+#include "pf_kernels.hip"
+
+using namespace pf;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_last_error;
+
+static pf_status fail(pf_status s, const std::string& msg)
+{
+    g_last_error = msg;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                      \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(PF_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));    \
+    } while (0)
+
+extern "C" const char* pf_status_str(pf_status s)
+{
+    switch (s) {
+    case PF_OK: return "ok";
+    case PF_EINVAL: return "invalid argument";
+    case PF_ENOMEM: return "device pool exhausted";
+    case PF_EADMIT: return "not admitted";
+    case PF_EDEGENERATE: return "degenerate weights or covariance; step skipped";
+    case PF_ENONFINITE: return "non-finite values";
+    case PF_EDEVICE: return "HIP runtime error";
+    case PF_EBUSY: return "too many steps in flight";
+    case PF_EORDER: return "observation time not after the current time";
+    }
+    return "unknown status";
+}
+
+extern "C" const char* pf_last_error(void) { return g_last_error.c_str(); }
+
+// ---------------------------------------------------------------------------
+// device pool: one allocation, first-fit free list with coalescing
+// ---------------------------------------------------------------------------
+struct Pool {
+    char* base = nullptr;
+    uint64_t cap = 0, used = 0;
+    std::map<uint64_t, uint64_t> free_;   // offset -> size
+
+    static uint64_t align(uint64_t v) { return (v + 255) & ~uint64_t(255); }
+
+    bool alloc(uint64_t bytes, uint64_t* off)
+    {
+        bytes = align(bytes);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                *off = it->first;
+                const uint64_t rest = it->second - bytes, roff = it->first + bytes;
+                free_.erase(it);
+                if (rest) free_[roff] = rest;
+                used += bytes;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(uint64_t off, uint64_t bytes)
+    {
+        bytes = align(bytes);
+        used -= bytes;
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
+// context and filter
+// ---------------------------------------------------------------------------
+constexpr int MAX_SLOTS = 4096;
+constexpr int NSTAGE = 4;
+constexpr int MAX_BATCH = 4096;
+constexpr int MAX_ITEMS = 1 << 20;   // tiles per submission
+
+struct Ticket {
+    uint64_t seq;
+    std::shared_ptr<hipEvent_t> ev;
+};
+
+struct pf_filter {
+    pf_context* ctx = nullptr;
+    int slot = -1;
+    uint64_t pool_off = 0, pool_bytes = 0;
+    FilterDesc desc{};
+    double t_submitted = 0.0;
+    uint64_t next_seq = 1;
+    std::deque<Ticket> pending;
+    std::map<uint64_t, int32_t> done_status;   // tickets completed and not yet waited on
+    int cls = 0;
+};
+
+struct Stage {
+    char* host = nullptr;    // pinned: [MAX_BATCH StepRec][MAX_ITEMS uint32]
+    char* dev = nullptr;
+    hipEvent_t ev = nullptr;
+};
+
+struct pf_context {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    Pool pool;
+    FilterDesc* d_desc = nullptr;
+    FilterState* d_state = nullptr;
+    int32_t* h_ring = nullptr;   // pinned, mapped: [MAX_SLOTS][RING]
+    int32_t* d_ring = nullptr;
+    std::vector<char> slot_used;
+    Stage stage[NSTAGE];
+    int stage_next = 0;
+    int grid_cap = 2048;
+    std::mutex mu;
+};
+
+// k_end that also mirrors the status to host-mapped memory
+namespace pf {
+__global__ void k_end_host(const StepRec* recs, int count, FilterState* states, int32_t* host_ring)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= count) return;
+    const StepRec& r = recs[b];
+    FilterState& st = states[r.slot];
+    st.ring[r.seq % RING] = st.status;
+    host_ring[(size_t)r.slot * RING + r.seq % RING] = st.status;
+    __threadfence_system();
+}
+}  // namespace pf
+
+// ---------------------------------------------------------------------------
+// kernel dispatch by (model, precision, order)
+// ---------------------------------------------------------------------------
+typedef void (*StepKernel)(const uint32_t*, int, const StepRec*, const FilterDesc*, FilterState*);
+
+template <template <class> class Mdl, class R>
+static StepKernel pick_predict(int order)
+{
+    switch (order) {
+    case 1: return k_predict<Mdl<R>, R, 1>;
+    case 2: return k_predict<Mdl<R>, R, 2>;
+    default: return k_predict<Mdl<R>, R, 3>;
+    }
+}
+template <template <class> class Mdl, class R>
+static StepKernel pick_update(int order)
+{
+    switch (order) {
+    case 1: return k_update<Mdl<R>, R, 1>;
+    case 2: return k_update<Mdl<R>, R, 2>;
+    default: return k_update<Mdl<R>, R, 3>;
+    }
+}
+
+static StepKernel predict_kernel(int model, int prec, int order)
+{
+    if (model == MODEL_ROBERTSON)
+        return prec == PREC_FP32 ? pick_predict<Robertson, float>(order) : pick_predict<Robertson, double>(order);
+    return prec == PREC_FP32 ? pick_predict<Chain16, float>(order) : pick_predict<Chain16, double>(order);
+}
+static StepKernel update_kernel(int model, int prec, int order)
+{
+    if (model == MODEL_ROBERTSON)
+        return prec == PREC_FP32 ? pick_update<Robertson, float>(order) : pick_update<Robertson, double>(order);
+    return prec == PREC_FP32 ? pick_update<Chain16, float>(order) : pick_update<Chain16, double>(order);
+}
+
+static int class_of(const FilterDesc& d) { return (d.model - 1) * 8 + d.prec * 4 + d.order; }
+
+// ---------------------------------------------------------------------------
+// configuration checks
+// ---------------------------------------------------------------------------
+static pf_status check_config(const pf_config* c)
+{
+    if (!c) return fail(PF_EINVAL, "config is NULL");
+    if (c->struct_size != sizeof(pf_config)) return fail(PF_EINVAL, "pf_config.struct_size mismatch");
+    if (c->model == PF_MODEL_ROBERTSON) {
+        if (c->d != 3 || c->p != 3) return fail(PF_EINVAL, "Robertson needs d = 3, p = 3");
+    } else if (c->model == PF_MODEL_CHAIN16) {
+        if (c->d != 16 || c->p != 12) return fail(PF_EINVAL, "chain16 needs d = 16, p = 12");
+        if (!c->model_consts || c->n_model_consts != 32) return fail(PF_EINVAL, "chain16 needs 32 model constants");
+        if (!c->rates_fixed || c->n_rates_fixed != 16) return fail(PF_EINVAL, "chain16 needs 16 rates");
+    } else {
+        return fail(PF_EINVAL, "unknown model");
+    }
+    if (c->m < 1 || c->m > (uint32_t)MMAX || !c->obs_index) return fail(PF_EINVAL, "m must be 1..4 with obs_index");
+    for (uint32_t i = 0; i < c->m; ++i)
+        if (c->obs_index[i] >= c->d) return fail(PF_EINVAL, "obs_index out of range");
+    if (c->n_particles < 1 || c->n_particles > (1ull << 24)) return fail(PF_EINVAL, "n_particles must be 1..2^24");
+    if (!c->x0 || !c->prior_mean || !c->prior_sd || !c->state_floor) return fail(PF_EINVAL, "NULL array in config");
+    if (!(c->shrink_a > 0.0 && c->shrink_a < 1.0)) return fail(PF_EINVAL, "shrink_a must be in (0,1)");
+    if (c->lmm != PF_LMM_BDF) return fail(PF_EINVAL, "only BDF is implemented");
+    if (c->order < 1 || c->order > 3) return fail(PF_EINVAL, "order must be 1..3");
+    if (c->substeps < 1 || c->newton_max_iter < 1) return fail(PF_EINVAL, "substeps and newton_max_iter must be >= 1");
+    if (!(c->newton_rtol > 0.0)) return fail(PF_EINVAL, "newton_rtol must be > 0");
+    if (c->precision != PF_PREC_FP64 && c->precision != PF_PREC_FP32_PROP) return fail(PF_EINVAL, "bad precision");
+    for (uint32_t i = 0; i < c->p; ++i)
+        if (!std::isfinite(c->prior_mean[i]) || !(c->prior_sd[i] >= 0.0)) return fail(PF_EINVAL, "bad prior");
+    return PF_OK;
+}
+
+static void fill_static(FilterDesc& d, const pf_config* c)
+{
+    std::memset(&d, 0, sizeof(d));
+    d.model = c->model;
+    d.d = (int)c->d;
+    d.p = (int)c->p;
+    d.m = (int)c->m;
+    d.order = (int)c->order;
+    d.substeps = (int)c->substeps;
+    d.kmax = (int)c->newton_max_iter;
+    d.prec = c->precision == PF_PREC_FP32_PROP ? PREC_FP32 : PREC_FP64;
+    for (uint32_t i = 0; i < c->m; ++i) d.obs[i] = (int)c->obs_index[i];
+    d.n = (int)c->n_particles;
+    d.ntiles = (d.n + TILE - 1) / TILE;
+    d.npad = d.ntiles * TILE;
+    int cl = 0;
+    while ((1ll << cl) < (long long)d.n) ++cl;
+    d.shift = 62 - cl;
+    d.nacc = 3 + d.p + d.p * (d.p + 1) / 2 + d.d;
+    d.seed = c->seed;
+    d.a = c->shrink_a;
+    d.s = std::sqrt(1.0 - c->shrink_a * c->shrink_a);
+    d.rtol = c->newton_rtol;
+    for (uint32_t i = 0; i < c->p; ++i) {
+        d.prior_mean[i] = c->prior_mean[i];
+        d.prior_sd[i] = c->prior_sd[i];
+    }
+    for (uint32_t i = 0; i < c->d; ++i) {
+        d.x0[i] = c->x0[i];
+        d.floor_[i] = c->state_floor[i];
+        d.floor_f[i] = (float)c->state_floor[i];
+    }
+    for (uint32_t i = 0; i < c->n_model_consts && i < 2 * DMAX; ++i) {
+        d.mc[i] = c->model_consts[i];
+        d.mc_f[i] = (float)c->model_consts[i];
+    }
+    for (uint32_t i = 0; i < c->n_rates_fixed && i < DMAX; ++i) d.rates_fixed[i] = c->rates_fixed[i];
+}
+
+// bytes and offsets of one filter's buffers inside its pool block
+struct Layout {
+    uint64_t x[2], th[2], lw[2], lbar, lg, q, anc, part1, tsum, part2, done, total;
+};
+static Layout layout_of(const FilterDesc& d)
+{
+    Layout L{};
+    const uint64_t np = (uint64_t)d.npad, rs = d.prec == PREC_FP32 ? 4 : 8;
+    uint64_t o = 0;
+    auto take = [&](uint64_t b) { const uint64_t r = o; o = Pool::align(o + b); return r; };
+    L.x[0] = take(d.d * np * rs);
+    L.x[1] = take(d.d * np * rs);
+    L.th[0] = take(d.p * np * 8);
+    L.th[1] = take(d.p * np * 8);
+    L.lw[0] = take(np * 8);
+    L.lw[1] = take(np * 8);
+    L.lbar = take(np * 8);
+    L.lg = take(np * 8);
+    L.q = take(np * 8);
+    L.anc = take(np * 4);
+    L.part1 = take((uint64_t)d.ntiles * 2 * 8);
+    L.tsum = take((uint64_t)d.ntiles * 8);
+    L.part2 = take((uint64_t)d.ntiles * d.nacc * 8);
+    L.done = take(4 * 4);
+    L.total = o;
+    return L;
+}
+
+static void bind_buffers(FilterDesc& d, char* base, const Layout& L)
+{
+    d.x[0] = base + L.x[0];
+    d.x[1] = base + L.x[1];
+    d.theta[0] = (double*)(base + L.th[0]);
+    d.theta[1] = (double*)(base + L.th[1]);
+    d.logw[0] = (double*)(base + L.lw[0]);
+    d.logw[1] = (double*)(base + L.lw[1]);
+    d.lbar = (double*)(base + L.lbar);
+    d.lg = (double*)(base + L.lg);
+    d.q = (uint64_t*)(base + L.q);
+    d.anc = (int32_t*)(base + L.anc);
+    d.part1 = (double*)(base + L.part1);
+    d.tsum = (uint64_t*)(base + L.tsum);
+    d.part2 = (double*)(base + L.part2);
+    d.done = (uint32_t*)(base + L.done);
+}
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+extern "C" pf_status pf_context_create(int device, uint64_t pool_bytes, void* hip_stream, pf_context** out)
+{
+    if (!out) return fail(PF_EINVAL, "out is NULL");
+    *out = nullptr;
+    int ndev = 0;
+    HIP_TRY(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) return fail(PF_EINVAL, "no such device");
+    HIP_TRY(hipSetDevice(device));
+    auto ctx = std::make_unique<pf_context>();
+    ctx->device = device;
+    if (hip_stream) {
+        ctx->stream = (hipStream_t)hip_stream;
+    } else {
+        HIP_TRY(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
+        ctx->own_stream = true;
+    }
+    if (pool_bytes == 0) {
+        size_t fr = 0, tot = 0;
+        HIP_TRY(hipMemGetInfo(&fr, &tot));
+        pool_bytes = fr / 4;
+    }
+    pool_bytes = Pool::align(pool_bytes);
+    void* p = nullptr;
+    if (hipMalloc(&p, pool_bytes) != hipSuccess) return fail(PF_ENOMEM, "cannot allocate the device pool");
+    ctx->pool.base = (char*)p;
+    ctx->pool.cap = pool_bytes;
+    ctx->pool.free_[0] = pool_bytes;
+    HIP_TRY(hipMalloc(&ctx->d_desc, sizeof(FilterDesc) * MAX_SLOTS));
+    HIP_TRY(hipMalloc(&ctx->d_state, sizeof(FilterState) * MAX_SLOTS));
+    HIP_TRY(hipHostMalloc(&ctx->h_ring, sizeof(int32_t) * MAX_SLOTS * RING, hipHostMallocMapped));
+    HIP_TRY(hipHostGetDevicePointer((void**)&ctx->d_ring, ctx->h_ring, 0));
+    ctx->slot_used.assign(MAX_SLOTS, 0);
+    const size_t sbytes = sizeof(StepRec) * MAX_BATCH + sizeof(uint32_t) * MAX_ITEMS;
+    for (int s = 0; s < NSTAGE; ++s) {
+        HIP_TRY(hipHostMalloc(&ctx->stage[s].host, sbytes, hipHostMallocDefault));
+        HIP_TRY(hipMalloc(&ctx->stage[s].dev, sbytes));
+        HIP_TRY(hipEventCreateWithFlags(&ctx->stage[s].ev, hipEventDisableTiming));
+        HIP_TRY(hipEventRecord(ctx->stage[s].ev, ctx->stream));
+    }
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, device));
+    ctx->grid_cap = std::max(256, prop.multiProcessorCount * 8);
+    *out = ctx.release();
+    return PF_OK;
+}
+
+extern "C" void pf_context_destroy(pf_context* ctx)
+{
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    for (int s = 0; s < NSTAGE; ++s) {
+        (void)hipEventDestroy(ctx->stage[s].ev);
+        (void)hipHostFree(ctx->stage[s].host);
+        (void)hipFree(ctx->stage[s].dev);
+    }
+    (void)hipHostFree(ctx->h_ring);
+    (void)hipFree(ctx->d_desc);
+    (void)hipFree(ctx->d_state);
+    (void)hipFree(ctx->pool.base);
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+extern "C" uint64_t pf_filter_bytes(const pf_config* cfg)
+{
+    if (check_config(cfg) != PF_OK) return 0;
+    FilterDesc d;
+    fill_static(d, cfg);
+    return Pool::align(layout_of(d).total);
+}
+
+extern "C" pf_status pf_context_memory(pf_context* ctx, uint64_t* used, uint64_t* capacity)
+{
+    if (!ctx) return fail(PF_EINVAL, "ctx is NULL");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (used) *used = ctx->pool.used;
+    if (capacity) *capacity = ctx->pool.cap;
+    return PF_OK;
+}
+
+static unsigned grid_for(const pf_context* ctx, int items)
+{
+    return (unsigned)std::max(1, std::min(items, ctx->grid_cap));
+}
+
+// ---------------------------------------------------------------------------
+// filter creation
+// ---------------------------------------------------------------------------
+extern "C" pf_status pf_create(pf_context* ctx, const pf_config* cfg, pf_filter** out)
+{
+    if (!ctx || !out) return fail(PF_EINVAL, "NULL argument");
+    *out = nullptr;
+    pf_status s = check_config(cfg);
+    if (s != PF_OK) return s;
+    HIP_TRY(hipSetDevice(ctx->device));
+    auto f = std::make_unique<pf_filter>();
+    fill_static(f->desc, cfg);
+    const Layout L = layout_of(f->desc);
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        int slot = -1;
+        for (int i = 0; i < MAX_SLOTS; ++i)
+            if (!ctx->slot_used[i]) { slot = i; break; }
+        if (slot < 0) return fail(PF_ENOMEM, "filter table full");
+        uint64_t off = 0;
+        if (!ctx->pool.alloc(L.total, &off)) return fail(PF_ENOMEM, "device pool exhausted");
+        ctx->slot_used[slot] = 1;
+        f->slot = slot;
+        f->pool_off = off;
+        f->pool_bytes = L.total;
+    }
+    f->ctx = ctx;
+    f->cls = class_of(f->desc);
+    bind_buffers(f->desc, ctx->pool.base + f->pool_off, L);
+    FilterState st;
+    std::memset(&st, 0, sizeof(st));
+    st.t = cfg->t0;
+    st.status = ST_OK;
+    for (int i = 0; i < (int)cfg->p; ++i) st.theta_bar[i] = cfg->prior_mean[i];
+    f->t_submitted = cfg->t0;
+    auto cleanup = [&](pf_status e) {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        ctx->pool.release(f->pool_off, f->pool_bytes);
+        ctx->slot_used[f->slot] = 0;
+        return e;
+    };
+    if (hipMemcpyAsync(ctx->d_desc + f->slot, &f->desc, sizeof(FilterDesc), hipMemcpyHostToDevice, ctx->stream) != hipSuccess ||
+        hipMemcpyAsync(ctx->d_state + f->slot, &st, sizeof(FilterState), hipMemcpyHostToDevice, ctx->stream) != hipSuccess ||
+        hipMemsetAsync(f->desc.done, 0, 16, ctx->stream) != hipSuccess ||
+        hipMemsetAsync(f->desc.anc, 0, sizeof(int32_t) * (size_t)f->desc.npad, ctx->stream) != hipSuccess)
+        return cleanup(fail(PF_EDEVICE, "upload of filter descriptor failed"));
+    const unsigned grid = grid_for(ctx, f->desc.ntiles);
+    if (f->desc.prec == PREC_FP32)
+        hipLaunchKernelGGL(k_init<float>, dim3(grid), dim3(TILE), 0, ctx->stream, f->slot, ctx->d_desc, ctx->d_state);
+    else
+        hipLaunchKernelGGL(k_init<double>, dim3(grid), dim3(TILE), 0, ctx->stream, f->slot, ctx->d_desc, ctx->d_state);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(ctx->stream) != hipSuccess)
+        return cleanup(fail(PF_EDEVICE, "initialisation kernel failed"));
+    int32_t status = 0;
+    if (hipMemcpy(&status, &ctx->d_state[f->slot].status, sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
+        return cleanup(fail(PF_EDEVICE, "status read failed"));
+    if (status != ST_OK) return cleanup(fail((pf_status)status, "prior covariance not factorable"));
+    *out = f.release();
+    return PF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// submission
+// ---------------------------------------------------------------------------
+static pf_status submit(pf_context* ctx, uint32_t count, pf_filter* const* fs, const double* t_obs,
+                        const double* y, const double* sigma, int ystride, uint64_t* tickets)
+{
+    if (count == 0) return PF_OK;
+    if (count > (uint32_t)MAX_BATCH) return fail(PF_EINVAL, "batch larger than 4096 filters");
+    // validate everything before touching any filter
+    uint64_t total_tiles = 0;
+    for (uint32_t b = 0; b < count; ++b) {
+        pf_filter* f = fs[b];
+        if (!f || f->ctx != ctx) return fail(PF_EINVAL, "filter not of this context");
+        for (uint32_t c = 0; c < b; ++c)
+            if (fs[c] == f) return fail(PF_EINVAL, "a filter appears twice in one batch");
+        if (!std::isfinite(t_obs[b])) return fail(PF_EINVAL, "non-finite observation time");
+        if (!(t_obs[b] > f->t_submitted)) return fail(PF_EORDER, "observation time not increasing");
+        for (int i = 0; i < f->desc.m; ++i) {
+            const double yy = y[(size_t)b * ystride + i], ss = sigma[(size_t)b * ystride + i];
+            if (!std::isfinite(yy) || !std::isfinite(ss) || !(ss > 0.0))
+                return fail(PF_EINVAL, "observation or sigma not finite and positive");
+        }
+        if (f->pending.size() >= RING) return fail(PF_EBUSY, "64 steps of this filter already pending");
+        total_tiles += (uint64_t)f->desc.ntiles;
+    }
+    if (total_tiles > (uint64_t)MAX_ITEMS) return fail(PF_EINVAL, "batch has too many tiles");
+
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    Stage& sg = ctx->stage[ctx->stage_next];
+    ctx->stage_next = (ctx->stage_next + 1) % NSTAGE;
+    HIP_TRY(hipEventSynchronize(sg.ev));   // previous use of this staging block is done
+    StepRec* recs = (StepRec*)sg.host;
+    uint32_t* items = (uint32_t*)(sg.host + sizeof(StepRec) * MAX_BATCH);
+    // group tiles by kernel class so each class is one contiguous list
+    std::map<int, std::vector<uint32_t>> by_class;
+    for (uint32_t b = 0; b < count; ++b) {
+        pf_filter* f = fs[b];
+        StepRec& r = recs[b];
+        std::memset(&r, 0, sizeof(r));
+        r.slot = f->slot;
+        r.seq = f->next_seq;
+        r.t_next = t_obs[b];
+        for (int i = 0; i < f->desc.m; ++i) {
+            r.y[i] = y[(size_t)b * ystride + i];
+            r.sigma[i] = sigma[(size_t)b * ystride + i];
+        }
+        auto& v = by_class[f->cls];
+        for (int t = 0; t < f->desc.ntiles; ++t) v.push_back((b << 16) | (uint32_t)t);
+    }
+    struct Range { int cls, off, cnt; };
+    std::vector<Range> ranges;
+    int off = 0;
+    for (auto& kv : by_class) {
+        std::memcpy(items + off, kv.second.data(), kv.second.size() * sizeof(uint32_t));
+        ranges.push_back({kv.first, off, (int)kv.second.size()});
+        off += (int)kv.second.size();
+    }
+    const int n_all = off;
+    StepRec* d_recs = (StepRec*)sg.dev;
+    uint32_t* d_items = (uint32_t*)(sg.dev + sizeof(StepRec) * MAX_BATCH);
+    HIP_TRY(hipMemcpyAsync(d_recs, recs, sizeof(StepRec) * count, hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(hipMemcpyAsync(d_items, items, sizeof(uint32_t) * n_all, hipMemcpyHostToDevice, ctx->stream));
+
+    const unsigned gb = (count + 255) / 256;
+    hipLaunchKernelGGL(k_begin, dim3(gb), dim3(256), 0, ctx->stream, d_recs, (int)count, ctx->d_desc, ctx->d_state);
+    for (const Range& r : ranges) {
+        const int model = r.cls / 8 + 1, prec = (r.cls % 8) / 4, order = r.cls % 4;
+        hipLaunchKernelGGL(predict_kernel(model, prec, order), dim3(grid_for(ctx, r.cnt)), dim3(TILE), 0,
+                           ctx->stream, d_items + r.off, r.cnt, d_recs, ctx->d_desc, ctx->d_state);
+    }
+    hipLaunchKernelGGL(k_count, dim3(grid_for(ctx, n_all)), dim3(TILE), 0, ctx->stream, d_items, n_all, d_recs,
+                       ctx->d_desc, ctx->d_state);
+    hipLaunchKernelGGL(k_scatter, dim3(grid_for(ctx, n_all)), dim3(TILE), 0, ctx->stream, d_items, n_all, d_recs,
+                       ctx->d_desc, ctx->d_state);
+    for (const Range& r : ranges) {
+        const int model = r.cls / 8 + 1, prec = (r.cls % 8) / 4, order = r.cls % 4;
+        hipLaunchKernelGGL(update_kernel(model, prec, order), dim3(grid_for(ctx, r.cnt)), dim3(TILE), 0,
+                           ctx->stream, d_items + r.off, r.cnt, d_recs, ctx->d_desc, ctx->d_state);
+    }
+    hipLaunchKernelGGL(k_end_host, dim3(gb), dim3(256), 0, ctx->stream, d_recs, (int)count, ctx->d_state,
+                       ctx->d_ring);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipEventRecord(sg.ev, ctx->stream));
+    auto ev = std::shared_ptr<hipEvent_t>(new hipEvent_t, [](hipEvent_t* e) { (void)hipEventDestroy(*e); delete e; });
+    HIP_TRY(hipEventCreateWithFlags(ev.get(), hipEventDisableTiming));
+    HIP_TRY(hipEventRecord(*ev, ctx->stream));
+    for (uint32_t b = 0; b < count; ++b) {
+        pf_filter* f = fs[b];
+        const uint64_t seq = f->next_seq++;
+        f->t_submitted = t_obs[b];
+        f->pending.push_back({seq, ev});
+        if (tickets) tickets[b] = seq;
+    }
+    return PF_OK;
+}
+
+// completes every pending ticket up to and including `upto`
+static pf_status drain(pf_filter* f, uint64_t upto)
+{
+    while (!f->pending.empty() && f->pending.front().seq <= upto) {
+        Ticket t = f->pending.front();
+        HIP_TRY(hipEventSynchronize(*t.ev));
+        f->done_status[t.seq] = f->ctx->h_ring[(size_t)f->slot * RING + t.seq % RING];
+        f->pending.pop_front();
+    }
+    return PF_OK;
+}
+
+extern "C" pf_status pf_assimilate_async(pf_filter* f, double t_obs, const double* y, const double* sigma,
+                                         uint64_t* ticket)
+{
+    if (!f || !y || !sigma) return fail(PF_EINVAL, "NULL argument");
+    HIP_TRY(hipSetDevice(f->ctx->device));
+    return submit(f->ctx, 1, &f, &t_obs, y, sigma, MMAX, ticket);
+}
+
+extern "C" pf_status pf_wait(pf_filter* f, uint64_t ticket)
+{
+    if (!f) return fail(PF_EINVAL, "NULL filter");
+    if (ticket == 0 || ticket >= f->next_seq) return fail(PF_EINVAL, "unknown ticket");
+    HIP_TRY(hipSetDevice(f->ctx->device));
+    pf_status s = drain(f, ticket);
+    if (s != PF_OK) return s;
+    auto it = f->done_status.find(ticket);
+    if (it == f->done_status.end()) return fail(PF_EINVAL, "ticket already waited on");
+    const pf_status st = (pf_status)it->second;
+    f->done_status.erase(it);
+    if (st != PF_OK) g_last_error = pf_status_str(st);
+    return st;
+}
+
+extern "C" pf_status pf_assimilate(pf_filter* f, double t_obs, const double* y, const double* sigma)
+{
+    uint64_t t = 0;
+    pf_status s = pf_assimilate_async(f, t_obs, y, sigma, &t);
+    if (s != PF_OK) return s;
+    return pf_wait(f, t);
+}
+
+extern "C" pf_status pf_assimilate_batch(pf_context* ctx, uint32_t count, pf_filter* const* filters,
+                                         const double* t_obs, const double* y, const double* sigma,
+                                         uint64_t* tickets)
+{
+    if (!ctx || (count && (!filters || !t_obs || !y || !sigma))) return fail(PF_EINVAL, "NULL argument");
+    HIP_TRY(hipSetDevice(ctx->device));
+    return submit(ctx, count, filters, t_obs, y, sigma, MMAX, tickets);
+}
+
+static pf_status read_state(pf_filter* f, FilterState* st)
+{
+    HIP_TRY(hipSetDevice(f->ctx->device));
+    pf_status s = drain(f, f->next_seq - 1);
+    if (s != PF_OK) return s;
+    // the context stream may still run other filters' steps: read on the
+    // same stream so this filter's last step is ordered before the copy
+    HIP_TRY(hipMemcpyAsync(st, f->ctx->d_state + f->slot, sizeof(FilterState), hipMemcpyDeviceToHost,
+                           f->ctx->stream));
+    HIP_TRY(hipStreamSynchronize(f->ctx->stream));
+    return PF_OK;
+}
+
+extern "C" pf_status pf_posterior(pf_filter* f, double* mean, double* cov, double* state_mean, double* ess,
+                                  uint64_t* step)
+{
+    if (!f) return fail(PF_EINVAL, "NULL filter");
+    FilterState st;
+    pf_status s = read_state(f, &st);
+    if (s != PF_OK) return s;
+    const int p = f->desc.p, d = f->desc.d;
+    if (mean) for (int i = 0; i < p; ++i) mean[i] = st.theta_bar[i];
+    if (cov) for (int i = 0; i < p * p; ++i) cov[i] = st.C[i];
+    if (state_mean) for (int i = 0; i < d; ++i) state_mean[i] = st.state_mean[i];
+    if (ess) *ess = st.ess;
+    if (step) *step = st.j;
+    return PF_OK;
+}
+
+extern "C" pf_status pf_stats(pf_filter* f, uint64_t* newton_iters, uint64_t* newton_fails, uint64_t* nonfinite,
+                              uint64_t* jitters)
+{
+    if (!f) return fail(PF_EINVAL, "NULL filter");
+    FilterState st;
+    pf_status s = read_state(f, &st);
+    if (s != PF_OK) return s;
+    if (newton_iters) *newton_iters = st.newton_iters;
+    if (newton_fails) *newton_fails = st.newton_fails;
+    if (nonfinite) *nonfinite = st.nonfinite;
+    if (jitters) *jitters = st.jitters;
+    return PF_OK;
+}
+
+extern "C" void pf_destroy(pf_filter* f)
+{
+    if (!f) return;
+    pf_context* ctx = f->ctx;
+    (void)hipSetDevice(ctx->device);
+    drain(f, f->next_seq - 1);
+    (void)hipStreamSynchronize(ctx->stream);
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        ctx->pool.release(f->pool_off, f->pool_bytes);
+        ctx->slot_used[f->slot] = 0;
+    }
+    delete f;
+}
+
+// ---------------------------------------------------------------------------
+// test-only entry points
+// ---------------------------------------------------------------------------
+extern "C" pf_status pf_test_philox(uint64_t n, const uint64_t* ctr, const uint64_t* key, uint64_t* out,
+                                    void* hip_stream)
+{
+    if (!ctr || !key || !out) return fail(PF_EINVAL, "NULL argument");
+    if (n == 0) return PF_OK;
+    hipStream_t s = (hipStream_t)hip_stream;
+    hipLaunchKernelGGL(k_test_philox, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, ctr, key, out);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(s));
+    return PF_OK;
+}
+
+extern "C" pf_status pf_test_normals(uint64_t n, uint64_t seed, uint64_t step, uint64_t purpose, uint32_t count,
+                                     double* out, void* hip_stream)
+{
+    if (!out) return fail(PF_EINVAL, "NULL argument");
+    if (n == 0) return PF_OK;
+    hipStream_t s = (hipStream_t)hip_stream;
+    const dim3 g((unsigned)((n + 255) / 256)), b(256);
+    switch (count) {
+    case 1: hipLaunchKernelGGL(k_test_normals<1>, g, b, 0, s, n, seed, step, purpose, out); break;
+    case 2: hipLaunchKernelGGL(k_test_normals<2>, g, b, 0, s, n, seed, step, purpose, out); break;
+    case 3: hipLaunchKernelGGL(k_test_normals<3>, g, b, 0, s, n, seed, step, purpose, out); break;
+    case 4: hipLaunchKernelGGL(k_test_normals<4>, g, b, 0, s, n, seed, step, purpose, out); break;
+    case 5: hipLaunchKernelGGL(k_test_normals<5>, g, b, 0, s, n, seed, step, purpose, out); break;
+    case 12: hipLaunchKernelGGL(k_test_normals<12>, g, b, 0, s, n, seed, step, purpose, out); break;
+    case 16: hipLaunchKernelGGL(k_test_normals<16>, g, b, 0, s, n, seed, step, purpose, out); break;
+    default: return fail(PF_EINVAL, "count must be one of 1,2,3,4,5,12,16");
+    }
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(s));
+    return PF_OK;
+}
+
+typedef void (*PropKernel)(const FilterDesc*, uint64_t, const double*, const double*, double, double*, double*,
+                           unsigned long long*);
+
+template <template <class> class Mdl, class R, bool LTE>
+static PropKernel pick_prop(int order)
+{
+    switch (order) {
+    case 1: return k_test_propagate<Mdl<R>, R, 1, LTE>;
+    case 2: return k_test_propagate<Mdl<R>, R, 2, LTE>;
+    default: return k_test_propagate<Mdl<R>, R, 3, LTE>;
+    }
+}
+
+extern "C" pf_status pf_test_propagate(const pf_config* cfg, uint64_t n, const double* x_in, const double* theta,
+                                       double h, int lte, double* x_out, double* gamma, uint64_t* iters,
+                                       void* hip_stream)
+{
+    pf_status s = check_config(cfg);
+    if (s != PF_OK) return s;
+    if (!x_in || !theta || !x_out || (lte && !gamma)) return fail(PF_EINVAL, "NULL buffer");
+    if (!(h > 0.0) || !std::isfinite(h)) return fail(PF_EINVAL, "h must be positive");
+    if (n == 0) return PF_OK;
+    FilterDesc d;
+    fill_static(d, cfg);
+    hipStream_t st = (hipStream_t)hip_stream;
+    FilterDesc* dd = nullptr;
+    HIP_TRY(hipMalloc(&dd, sizeof(FilterDesc)));
+    hipError_t e = hipMemcpyAsync(dd, &d, sizeof(FilterDesc), hipMemcpyHostToDevice, st);
+    PropKernel k;
+    const bool f32 = d.prec == PREC_FP32;
+    if (d.model == MODEL_ROBERTSON)
+        k = f32 ? (lte ? pick_prop<Robertson, float, true>(d.order) : pick_prop<Robertson, float, false>(d.order))
+                : (lte ? pick_prop<Robertson, double, true>(d.order) : pick_prop<Robertson, double, false>(d.order));
+    else
+        k = f32 ? (lte ? pick_prop<Chain16, float, true>(d.order) : pick_prop<Chain16, float, false>(d.order))
+                : (lte ? pick_prop<Chain16, double, true>(d.order) : pick_prop<Chain16, double, false>(d.order));
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k, dim3((unsigned)((n + TILE - 1) / TILE)), dim3(TILE), 0, st, dd, n, x_in, theta, h, x_out,
+                           lte ? gamma : nullptr, (unsigned long long*)iters);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(dd);
+    if (e != hipSuccess) return fail(PF_EDEVICE, std::string("propagate: ") + hipGetErrorString(e));
+    return PF_OK;
+}
+
+extern "C" pf_status pf_test_resample(uint64_t n, const double* g, uint64_t r, int32_t* anc, void* hip_stream)
+{
+    if (!g || !anc) return fail(PF_EINVAL, "NULL buffer");
+    if (n == 0 || n > (1ull << 24)) return fail(PF_EINVAL, "n must be 1..2^24");
+    hipStream_t st = (hipStream_t)hip_stream;
+    FilterDesc d;
+    std::memset(&d, 0, sizeof(d));
+    d.n = (int)n;
+    d.ntiles = (d.n + TILE - 1) / TILE;
+    d.npad = d.ntiles * TILE;
+    int cl = 0;
+    while ((1ll << cl) < (long long)d.n) ++cl;
+    d.shift = 62 - cl;
+    d.g_direct = 1;
+    // scratch: desc, state, rec, items, q, tsum, done
+    const size_t nb = sizeof(FilterDesc) + sizeof(FilterState) + sizeof(StepRec) + 4 * (size_t)d.ntiles +
+                      8 * (size_t)d.npad + 8 * (size_t)d.ntiles + 64 + 6 * 256;
+    char* buf = nullptr;
+    HIP_TRY(hipMalloc(&buf, nb));
+    size_t o = 0;
+    auto take = [&](size_t b) { char* p = buf + o; o = (o + b + 255) & ~size_t(255); return p; };
+    FilterDesc* dd = (FilterDesc*)take(sizeof(FilterDesc));
+    FilterState* ds = (FilterState*)take(sizeof(FilterState));
+    StepRec* dr = (StepRec*)take(sizeof(StepRec));
+    uint32_t* di = (uint32_t*)take(4 * (size_t)d.ntiles);
+    d.q = (uint64_t*)take(8 * (size_t)d.npad);
+    d.tsum = (uint64_t*)take(8 * (size_t)d.ntiles);
+    d.done = (uint32_t*)take(64);
+    d.lg = const_cast<double*>(g);
+    d.anc = anc;
+    FilterState hs;
+    std::memset(&hs, 0, sizeof(hs));
+    hs.status = ST_OK;
+    hs.V = r;
+    StepRec rec;
+    std::memset(&rec, 0, sizeof(rec));
+    std::vector<uint32_t> items(d.ntiles);
+    for (int t = 0; t < d.ntiles; ++t) items[t] = (uint32_t)t;
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = hipMemcpyAsync(dd, &d, sizeof(d), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(ds, &hs, sizeof(hs), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(dr, &rec, sizeof(rec), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(di, items.data(), 4 * items.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemsetAsync(d.done, 0, 64, st);
+    if (e == hipSuccess) {
+        const unsigned grid = (unsigned)std::min(d.ntiles, 2048);
+        hipLaunchKernelGGL(k_count, dim3(grid), dim3(TILE), 0, st, di, d.ntiles, dr, dd, ds);
+        hipLaunchKernelGGL(k_scatter, dim3(grid), dim3(TILE), 0, st, di, d.ntiles, dr, dd, ds);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(&hs, ds, sizeof(hs), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(buf);
+    if (e != hipSuccess) return fail(PF_EDEVICE, std::string("resample: ") + hipGetErrorString(e));
+    if (hs.status != ST_OK) return fail((pf_status)hs.status, "all scaled weights are zero");
+    return PF_OK;
+}
+
+namespace pf {
+template <class R>
+__global__ void k_test_get(const FilterDesc* descs, const FilterState* states, int slot, double* x, double* th,
+                           double* lw)
+{
+    const FilterDesc& fd = descs[slot];
+    const int cur = states[slot].cur;
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= fd.n) return;
+    const R* xb = (const R*)fd.x[cur];
+    if (x) for (int i = 0; i < fd.d; ++i) x[(size_t)i * fd.n + n] = (double)xb[(size_t)i * fd.npad + n];
+    if (th) for (int i = 0; i < fd.p; ++i) th[(size_t)i * fd.n + n] = fd.theta[cur][(size_t)i * fd.npad + n];
+    if (lw) lw[n] = fd.logw[cur][n];
+}
+template <class R>
+__global__ void k_test_set(const FilterDesc* descs, const FilterState* states, int slot, const double* x,
+                           const double* th, const double* lw)
+{
+    const FilterDesc& fd = descs[slot];
+    const int cur = states[slot].cur;
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= fd.n) return;
+    R* xb = (R*)fd.x[cur];
+    for (int i = 0; i < fd.d; ++i) xb[(size_t)i * fd.npad + n] = (R)x[(size_t)i * fd.n + n];
+    for (int i = 0; i < fd.p; ++i) fd.theta[cur][(size_t)i * fd.npad + n] = th[(size_t)i * fd.n + n];
+    fd.logw[cur][n] = lw[n];
+}
+}  // namespace pf
+
+extern "C" pf_status pf_test_get_ensemble(pf_filter* f, double* x, double* theta, double* logw)
+{
+    if (!f) return fail(PF_EINVAL, "NULL filter");
+    pf_context* ctx = f->ctx;
+    HIP_TRY(hipSetDevice(ctx->device));
+    pf_status s = drain(f, f->next_seq - 1);
+    if (s != PF_OK) return s;
+    const unsigned g = (unsigned)((f->desc.n + 255) / 256);
+    if (f->desc.prec == PREC_FP32)
+        hipLaunchKernelGGL(k_test_get<float>, dim3(g), dim3(256), 0, ctx->stream, ctx->d_desc, ctx->d_state, f->slot, x,
+                           theta, logw);
+    else
+        hipLaunchKernelGGL(k_test_get<double>, dim3(g), dim3(256), 0, ctx->stream, ctx->d_desc, ctx->d_state, f->slot, x,
+                           theta, logw);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    if (logw) {
+        // normalise on the host (test path only)
+        std::vector<double> h(f->desc.n);
+        HIP_TRY(hipMemcpy(h.data(), logw, sizeof(double) * h.size(), hipMemcpyDeviceToHost));
+        double mx = -INFINITY;
+        for (double v : h) mx = std::max(mx, v);
+        double sum = 0.0;
+        for (double v : h) sum += v > -INFINITY ? std::exp(v - mx) : 0.0;
+        const double lz = mx + std::log(sum);
+        for (double& v : h) v = v > -INFINITY ? v - lz : -INFINITY;
+        HIP_TRY(hipMemcpy(logw, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice));
+    }
+    return PF_OK;
+}
+
+extern "C" pf_status pf_test_set_ensemble(pf_filter* f, const double* x, const double* theta, const double* logw,
+                                          const double* theta_bar, const double* L, uint64_t step, double t)
+{
+    if (!f || !x || !theta || !logw || !theta_bar || !L) return fail(PF_EINVAL, "NULL argument");
+    pf_context* ctx = f->ctx;
+    HIP_TRY(hipSetDevice(ctx->device));
+    pf_status s = drain(f, f->next_seq - 1);
+    if (s != PF_OK) return s;
+    const unsigned g = (unsigned)((f->desc.n + 255) / 256);
+    if (f->desc.prec == PREC_FP32)
+        hipLaunchKernelGGL(k_test_set<float>, dim3(g), dim3(256), 0, ctx->stream, ctx->d_desc, ctx->d_state, f->slot, x,
+                           theta, logw);
+    else
+        hipLaunchKernelGGL(k_test_set<double>, dim3(g), dim3(256), 0, ctx->stream, ctx->d_desc, ctx->d_state, f->slot, x,
+                           theta, logw);
+    HIP_TRY(hipGetLastError());
+    FilterState st;
+    HIP_TRY(hipMemcpyAsync(&st, ctx->d_state + f->slot, sizeof(st), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    const int p = f->desc.p;
+    for (int i = 0; i < p; ++i) st.theta_bar[i] = theta_bar[i];
+    for (int i = 0; i < p * p; ++i) st.L[i] = L[i];
+    st.j = step;
+    st.t = t;
+    HIP_TRY(hipMemcpyAsync(ctx->d_state + f->slot, &st, sizeof(st), hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    f->t_submitted = t;
+    return PF_OK;
+}
+
+extern "C" pf_status pf_test_last_ancestors(pf_filter* f, int32_t* anc)
+{
+    if (!f || !anc) return fail(PF_EINVAL, "NULL argument");
+    HIP_TRY(hipSetDevice(f->ctx->device));
+    pf_status s = drain(f, f->next_seq - 1);
+    if (s != PF_OK) return s;
+    HIP_TRY(hipMemcpyAsync(anc, f->desc.anc, sizeof(int32_t) * f->desc.n, hipMemcpyDeviceToDevice, f->ctx->stream));
+    HIP_TRY(hipStreamSynchronize(f->ctx->stream));
+    return PF_OK;
+}

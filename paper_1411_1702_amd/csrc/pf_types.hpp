@@ -1,0 +1,90 @@
+// pf_types.hpp -- data shared by the host runtime and the kernels: the
+// per-filter descriptor (configuration + buffer pointers), the per-filter
+// dynamic state, and the per-step submission records.
+#pragma once
+#include <stdint.h>
+
+namespace pf {
+
+constexpr int TILE = 256;      // particles per workgroup tile (4 wavefronts)
+constexpr int DMAX = 16;       // largest state dimension
+constexpr int PMAX = 12;       // largest parameter dimension
+constexpr int MMAX = 4;        // largest number of observed components
+constexpr int RING = 64;       // per-filter status ring (steps in flight)
+// moment accumulators per tile: s0, s00, sum w (theta - c), sum w (theta-c)(theta-c)^T
+// (upper triangle), sum w x, and the tile's max log-weight
+constexpr int NACC_MAX = 3 + PMAX + PMAX * (PMAX + 1) / 2 + DMAX;
+
+enum Status : int32_t {
+    ST_OK = 0, ST_EINVAL = 1, ST_ENOMEM = 2, ST_EADMIT = 3, ST_EDEGENERATE = 4,
+    ST_ENONFINITE = 5, ST_EDEVICE = 6, ST_EBUSY = 7, ST_EORDER = 8
+};
+
+enum Model : int32_t { MODEL_ROBERTSON = 1, MODEL_CHAIN16 = 2 };
+enum Prec : int32_t { PREC_FP64 = 0, PREC_FP32 = 1 };
+
+// RNG purposes: third word of the Philox counter (step, particle, purpose, block)
+enum Purpose : uint64_t { PUR_PRIOR = 1, PUR_RESAMPLE = 2, PUR_PROLIF = 3, PUR_INNOV = 4 };
+
+// Static configuration and buffers of one filter (device resident, written
+// by the host at creation).
+struct FilterDesc {
+    int32_t model, d, p, m;
+    int32_t order, substeps, kmax, prec;
+    int32_t obs[MMAX];
+    int32_t n, npad, ntiles, shift;     // shift: resampling scale 2^shift
+    int32_t nacc, g_direct, pad0, pad1;
+    uint64_t seed;
+    double a, s, rtol;                  // shrink factor, jitter sqrt(1-a^2), Newton rtol
+    double prior_mean[PMAX], prior_sd[PMAX];
+    double x0[DMAX];
+    double floor_[DMAX];
+    float floor_f[DMAX];
+    double mc[2 * DMAX];                // chain: V[16], K[16]
+    float mc_f[2 * DMAX];
+    double rates_fixed[DMAX];
+    // buffers (structure of arrays, leading dimension npad)
+    void* x[2];                         // [d][npad] state, float or double
+    double* theta[2];                   // [p][npad] log-parameters
+    double* logw[2];                    // [npad] unnormalised log-weights
+    double* lbar;                       // [npad] log pi(y | predictor)
+    double* lg;                         // [npad] first-stage log-weights
+    uint64_t* q;                        // [npad] scaled integer weights
+    int32_t* anc;                       // [npad] ancestors
+    double* part1;                      // [ntiles][2] (max, sum exp)
+    uint64_t* tsum;                     // [ntiles] integer weight per tile (then offsets)
+    double* part2;                      // [ntiles][nacc] moment partials
+    uint32_t* done;                     // [4] last-tile counters
+};
+
+// Dynamic state of one filter (device resident, updated by the kernels).
+struct FilterState {
+    double theta_bar[PMAX];
+    double C[PMAX * PMAX];
+    double L[PMAX * PMAX];
+    double state_mean[DMAX];
+    double ess;
+    double t;                           // time of the current ensemble
+    uint64_t j;                         // observations assimilated
+    int32_t cur;                        // current ping-pong buffer
+    int32_t status;                     // status of the step in progress / last step
+    // step in progress
+    double t_next, h;
+    double y[MMAX], sigma[MMAX];
+    uint64_t step;                      // j + 1
+    uint64_t seq;                       // host ticket
+    double lse_max, lse_sum;            // first-stage log-sum-exp
+    uint64_t T, V;                      // resampling total and offset
+    unsigned long long newton_iters, newton_fails, nonfinite, jitters;
+    int32_t ring[RING];                 // status by ticket % RING
+};
+
+// One filter's entry in a submitted batch.
+struct StepRec {
+    int32_t slot, pad;
+    uint64_t seq;
+    double t_next;
+    double y[MMAX], sigma[MMAX];
+};
+
+}  // namespace pf

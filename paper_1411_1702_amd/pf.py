@@ -1,0 +1,251 @@
+"""Python binding of the C ABI in include/pf.h and include/pf_test.h.
+
+Argument marshalling only: every step of the filter runs in the HIP library.
+The library must be built (paper_1411_1702_amd/build.py); loading fails
+loudly otherwise -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpf_hip.so")
+
+PF_OK, PF_EINVAL, PF_ENOMEM, PF_EADMIT, PF_EDEGENERATE = 0, 1, 2, 3, 4
+PF_ENONFINITE, PF_EDEVICE, PF_EBUSY, PF_EORDER = 5, 6, 7, 8
+PF_MODEL_ROBERTSON, PF_MODEL_CHAIN16 = 1, 2
+PF_LMM_BDF = 0
+PF_PREC_FP64, PF_PREC_FP32_PROP = 0, 1
+
+EXPORTS = [
+    "pf_context_create", "pf_context_destroy", "pf_filter_bytes", "pf_context_memory",
+    "pf_create", "pf_assimilate", "pf_assimilate_async", "pf_wait", "pf_assimilate_batch",
+    "pf_posterior", "pf_stats", "pf_destroy", "pf_status_str", "pf_last_error",
+    "pf_test_philox", "pf_test_normals", "pf_test_propagate", "pf_test_resample",
+    "pf_test_get_ensemble", "pf_test_set_ensemble", "pf_test_last_ancestors",
+]
+
+
+class PfError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+class pf_config(C.Structure):
+    _fields_ = [
+        ("struct_size", C.c_uint32), ("model", C.c_int), ("d", C.c_uint32), ("p", C.c_uint32),
+        ("m", C.c_uint32), ("obs_index", C.POINTER(C.c_uint32)),
+        ("model_consts", C.POINTER(C.c_double)), ("n_model_consts", C.c_uint32),
+        ("rates_fixed", C.POINTER(C.c_double)), ("n_rates_fixed", C.c_uint32),
+        ("n_particles", C.c_uint64), ("seed", C.c_uint64), ("t0", C.c_double),
+        ("x0", C.POINTER(C.c_double)), ("prior_mean", C.POINTER(C.c_double)),
+        ("prior_sd", C.POINTER(C.c_double)), ("shrink_a", C.c_double), ("lmm", C.c_int),
+        ("order", C.c_uint32), ("substeps", C.c_uint32), ("newton_max_iter", C.c_uint32),
+        ("newton_rtol", C.c_double), ("state_floor", C.POINTER(C.c_double)),
+        ("precision", C.c_int),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load the HIP library (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"HIP library not built: {LIB_PATH} (run paper_1411_1702_amd/build.py)")
+        L = C.CDLL(LIB_PATH)
+        vp, dp, u64 = C.c_void_p, C.POINTER(C.c_double), C.c_uint64
+        L.pf_context_create.argtypes = [C.c_int, u64, vp, C.POINTER(vp)]
+        L.pf_context_destroy.argtypes = [vp]
+        L.pf_context_destroy.restype = None
+        L.pf_filter_bytes.argtypes = [C.POINTER(pf_config)]
+        L.pf_filter_bytes.restype = u64
+        L.pf_context_memory.argtypes = [vp, C.POINTER(u64), C.POINTER(u64)]
+        L.pf_create.argtypes = [vp, C.POINTER(pf_config), C.POINTER(vp)]
+        L.pf_assimilate.argtypes = [vp, C.c_double, dp, dp]
+        L.pf_assimilate_async.argtypes = [vp, C.c_double, dp, dp, C.POINTER(u64)]
+        L.pf_wait.argtypes = [vp, u64]
+        L.pf_assimilate_batch.argtypes = [vp, C.c_uint32, C.POINTER(vp), dp, dp, dp, C.POINTER(u64)]
+        L.pf_posterior.argtypes = [vp, dp, dp, dp, dp, C.POINTER(u64)]
+        L.pf_stats.argtypes = [vp] + [C.POINTER(u64)] * 4
+        L.pf_destroy.argtypes = [vp]
+        L.pf_destroy.restype = None
+        L.pf_status_str.argtypes = [C.c_int]
+        L.pf_status_str.restype = C.c_char_p
+        L.pf_last_error.restype = C.c_char_p
+        L.pf_test_philox.argtypes = [u64, vp, vp, vp, vp]
+        L.pf_test_normals.argtypes = [u64, u64, u64, u64, C.c_uint32, vp, vp]
+        L.pf_test_propagate.argtypes = [C.POINTER(pf_config), u64, vp, vp, C.c_double, C.c_int, vp, vp,
+                                        vp, vp]
+        L.pf_test_resample.argtypes = [u64, vp, u64, vp, vp]
+        L.pf_test_get_ensemble.argtypes = [vp, vp, vp, vp]
+        L.pf_test_set_ensemble.argtypes = [vp, vp, vp, vp, dp, dp, u64, C.c_double]
+        L.pf_test_last_ancestors.argtypes = [vp, vp]
+        _lib = L
+    return _lib
+
+
+def check(status, what=""):
+    if status != PF_OK:
+        raise PfError(status, f"{what}: {lib().pf_last_error().decode()}")
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+class Config:
+    """pf_config plus the host arrays it points to (kept alive here)."""
+
+    def __init__(self, prob, precision=PF_PREC_FP32_PROP, n_particles=None, seed=None,
+                 newton_rtol=None):
+        self.prob = prob
+        f64 = lambda a: np.ascontiguousarray(a, dtype=np.float64)
+        self.obs = np.ascontiguousarray(prob.obs_index, dtype=np.uint32)
+        self.mc = f64(prob.model_consts if len(prob.model_consts) else np.zeros(1))
+        self.rf = f64(prob.rates_fixed if len(prob.rates_fixed) else np.zeros(1))
+        self.x0 = f64(prob.x0)
+        self.pm = f64(prob.prior_mean)
+        self.ps = f64(prob.prior_sd)
+        self.fl = f64(prob.state_floor)
+        c = pf_config()
+        c.struct_size = C.sizeof(pf_config)
+        c.model = int(prob.model)
+        c.d, c.p, c.m = prob.d, prob.p, prob.m
+        c.obs_index = self.obs.ctypes.data_as(C.POINTER(C.c_uint32))
+        chain = prob.model == PF_MODEL_CHAIN16
+        c.model_consts = _dp(self.mc) if chain else None
+        c.n_model_consts = len(prob.model_consts) if chain else 0
+        c.rates_fixed = _dp(self.rf) if chain else None
+        c.n_rates_fixed = len(prob.rates_fixed) if chain else 0
+        c.n_particles = int(prob.n_particles if n_particles is None else n_particles)
+        c.seed = int(prob.seed if seed is None else seed)
+        c.t0 = float(prob.t0)
+        c.x0, c.prior_mean, c.prior_sd = _dp(self.x0), _dp(self.pm), _dp(self.ps)
+        c.shrink_a = float(prob.shrink_a)
+        c.lmm = PF_LMM_BDF
+        c.order, c.substeps = int(prob.order), int(prob.substeps)
+        c.newton_max_iter = int(prob.newton_max_iter)
+        if newton_rtol is None:
+            newton_rtol = prob.newton_rtol_fp32 if precision == PF_PREC_FP32_PROP else prob.newton_rtol_fp64
+        c.newton_rtol = float(newton_rtol)
+        c.state_floor = _dp(self.fl)
+        c.precision = int(precision)
+        self.c = c
+
+    def ptr(self):
+        return C.byref(self.c)
+
+
+class Context:
+    def __init__(self, device=0, pool_bytes=0, stream=None):
+        h = C.c_void_p()
+        check(lib().pf_context_create(device, int(pool_bytes), stream, C.byref(h)), "pf_context_create")
+        self.h = h
+
+    def memory(self):
+        u, c = C.c_uint64(), C.c_uint64()
+        check(lib().pf_context_memory(self.h, C.byref(u), C.byref(c)), "pf_context_memory")
+        return u.value, c.value
+
+    def assimilate_batch(self, filters, t_obs, y, sigma):
+        n = len(filters)
+        hs = (C.c_void_p * n)(*[f.h.value for f in filters])
+        t = np.ascontiguousarray(t_obs, dtype=np.float64)
+        yy = np.zeros((n, 4))
+        ss = np.ones((n, 4))
+        for i, f in enumerate(filters):
+            yy[i, : f.m] = y[i][: f.m]
+            ss[i, : f.m] = sigma[i][: f.m]
+        tk = (C.c_uint64 * n)()
+        check(lib().pf_assimilate_batch(self.h, n, hs, _dp(t), _dp(yy), _dp(ss), tk), "pf_assimilate_batch")
+        return list(tk)
+
+    def close(self):
+        if self.h:
+            lib().pf_context_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+class Filter:
+    def __init__(self, ctx: Context, cfg: Config):
+        self.ctx, self.cfg = ctx, cfg
+        self.d, self.p, self.m = cfg.c.d, cfg.c.p, cfg.c.m
+        self.N = cfg.c.n_particles
+        h = C.c_void_p()
+        check(lib().pf_create(ctx.h, cfg.ptr(), C.byref(h)), "pf_create")
+        self.h = h
+
+    def assimilate(self, t, y, sigma):
+        """Returns the step's status (PF_OK or PF_EDEGENERATE); raises on other errors."""
+        yy = np.ascontiguousarray(y, dtype=np.float64)
+        ss = np.ascontiguousarray(sigma, dtype=np.float64)
+        st = lib().pf_assimilate(self.h, float(t), _dp(yy), _dp(ss))
+        if st not in (PF_OK, PF_EDEGENERATE):
+            check(st, "pf_assimilate")
+        return st
+
+    def assimilate_async(self, t, y, sigma):
+        yy = np.zeros(4)
+        ss = np.ones(4)
+        yy[: self.m] = y[: self.m]
+        ss[: self.m] = sigma[: self.m]
+        tk = C.c_uint64()
+        check(lib().pf_assimilate_async(self.h, float(t), _dp(yy), _dp(ss), C.byref(tk)), "pf_assimilate_async")
+        return tk.value
+
+    def wait(self, ticket):
+        return lib().pf_wait(self.h, int(ticket))
+
+    def posterior(self):
+        mean = np.zeros(self.p)
+        cov = np.zeros(self.p * self.p)
+        xm = np.zeros(self.d)
+        ess = C.c_double()
+        step = C.c_uint64()
+        check(lib().pf_posterior(self.h, _dp(mean), _dp(cov), _dp(xm), C.byref(ess), C.byref(step)),
+              "pf_posterior")
+        return {"mean": mean, "cov": cov.reshape(self.p, self.p), "state_mean": xm, "ess": ess.value,
+                "step": step.value}
+
+    def stats(self):
+        v = [C.c_uint64() for _ in range(4)]
+        check(lib().pf_stats(self.h, *[C.byref(x) for x in v]), "pf_stats")
+        return dict(zip(["newton_iters", "newton_fails", "nonfinite", "jitters"], [x.value for x in v]))
+
+    def close(self):
+        if self.h:
+            lib().pf_destroy(self.h)
+            self.h = None
+
+
+def run_filter(ctx, prob, precision=PF_PREC_FP32_PROP, T=None, n_particles=None, seed=None):
+    """Assimilate the first T observations; returns per-step posterior means, sds, ess."""
+    cfg = Config(prob, precision, n_particles=n_particles, seed=seed)
+    f = Filter(ctx, cfg)
+    T = prob.T if T is None else int(T)
+    means, sds, ess = [], [], []
+    try:
+        for j in range(T):
+            st = f.assimilate(prob.times[j], prob.y[j], prob.sigma[j])
+            if st != PF_OK:
+                raise PfError(st, f"step {j}")
+            post = f.posterior()
+            means.append(post["mean"])
+            sds.append(np.sqrt(np.diag(post["cov"])))
+            ess.append(post["ess"])
+    finally:
+        f.close()
+    return np.array(means), np.array(sds), np.array(ess)

@@ -1,0 +1,264 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Bars (from the method's precision split): RNG words and resampling indices
+bit-exact given identical inputs; per-step states within 1e-10 relative in
+FP64 and 1e-4 relative in FP32 propagation, relative to max(|x|, floor) with
+floor = 1e-6 of each component's scale; normals within a few ulp (device vs
+host libm).
+"""
+import numpy as np
+import pytest
+
+from paper_1411_1702_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {0: 1e-10, 1: 1e-4}   # by precision: FP64, FP32 propagation
+
+
+@pytest.fixture(scope="module")
+def pf():
+    from paper_1411_1702_amd import pf as _pf
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    _pf.lib()
+    return _pf
+
+
+@pytest.fixture(scope="module")
+def ctx(pf):
+    c = pf.Context(0, 1 << 30)
+    yield c
+    c.close()
+
+
+def dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+def relerr(a, b, floor):
+    return np.abs(a - b) / np.maximum(np.abs(b), floor)
+
+
+# ---------------------------------------------------------------- RNG
+def test_philox_bitexact(pf, oracle):
+    rng = np.random.default_rng(11)
+    n = 3000
+    ctr = rng.integers(0, 2**63, (n, 4), dtype=np.int64).astype(np.uint64) * np.uint64(2) + \
+        rng.integers(0, 2, (n, 4), dtype=np.int64).astype(np.uint64)
+    ctr[:10] = np.arange(40, dtype=np.uint64).reshape(10, 4)
+    key = rng.integers(0, 2**63, (n, 2), dtype=np.int64).astype(np.uint64)
+    c_d = torch.from_numpy(ctr.view(np.int64)).cuda()
+    k_d = torch.from_numpy(key.view(np.int64)).cuda()
+    o_d = torch.zeros((n, 4), dtype=torch.int64, device="cuda")
+    pf.check(pf.lib().pf_test_philox(n, c_d.data_ptr(), k_d.data_ptr(), o_d.data_ptr(), None), "philox")
+    got = o_d.cpu().numpy().view(np.uint64)
+    for i in range(n):
+        assert np.array_equal(got[i], oracle.philox(ctr[i], key[i])), i
+
+
+@pytest.mark.parametrize("count,purpose", [(3, 3), (12, 3), (16, 4), (1, 2), (5, 1)])
+def test_normals_match_oracle(pf, oracle, count, purpose):
+    n, seed, step = 777, 12345, 17
+    out = torch.zeros((n, count), dtype=torch.float64, device="cuda")
+    pf.check(pf.lib().pf_test_normals(n, seed, step, purpose, count, out.data_ptr(), None), "normals")
+    got = out.cpu().numpy()
+    want = np.array([oracle.normals(seed, step, i, purpose, count) for i in range(n)])
+    assert np.allclose(got, want, rtol=1e-13, atol=1e-13)
+
+
+# ---------------------------------------------------------------- propagation
+def _robertson_inputs(oracle, n=1000, j_list=(1, 10, 25, 45)):
+    """(x_j, theta, h) sets from a short oracle run on the small Robertson config."""
+    prob = inputs.robertson(n, 50)
+    F = oracle.Filter(prob)
+    out = []
+    for j in range(max(j_list) + 1):
+        if j in j_list:
+            h = (prob.times[j] - F.t) / prob.substeps
+            out.append((F.x.copy(), F.theta.copy(), h))
+        F.step(prob.times[j], prob.y[j], prob.sigma[j])
+    return prob, out
+
+
+def _propagate_gpu(pf, prob, prec, x, theta, h, lte):
+    n = x.shape[0]
+    cfg = pf.Config(prob, prec)
+    xi, ti = dev(x.T), dev(theta.T)
+    xo = torch.zeros_like(xi)
+    go = torch.zeros_like(xi)
+    it = torch.zeros(1, dtype=torch.int64, device="cuda")
+    pf.check(pf.lib().pf_test_propagate(cfg.ptr(), n, xi.data_ptr(), ti.data_ptr(), h, int(lte),
+                                        xo.data_ptr(), go.data_ptr(), it.data_ptr(), None), "propagate")
+    return xo.cpu().numpy().T, go.cpu().numpy().T, int(it.item())
+
+
+def _propagate_oracle(oracle, prob, x, theta, h, lte, rtol):
+    xs, gs, its = [], [], 0
+    for i in range(x.shape[0]):
+        xo, go, st = oracle.psi(prob.model, x[i], theta[i], h, prob.substeps, prob.order, lte=lte,
+                                rtol=rtol, kmax=prob.newton_max_iter, floor=prob.state_floor,
+                                mc=prob.model_consts, rates_fixed=prob.rates_fixed)
+        xs.append(xo)
+        gs.append(go)
+        its += st["newton_iters"]
+    return np.array(xs), np.array(gs), its
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("lte", [False, True])
+def test_propagate_robertson(pf, oracle, prec, lte):
+    prob, sets = _robertson_inputs(oracle)
+    rtol = prob.newton_rtol_fp64 if prec == 0 else prob.newton_rtol_fp32
+    for x, th, h in sets:
+        xg, gg, itg = _propagate_gpu(pf, prob, prec, x, th, h, lte)
+        xo, go, ito = _propagate_oracle(oracle, prob, x, th, h, lte, rtol)
+        err = relerr(xg, xo, prob.state_floor)
+        assert err.max() < TOL[prec], (h, err.max())
+        if lte:
+            serr = relerr(np.sqrt(gg), np.sqrt(go), prob.state_floor)
+            assert serr.max() < (1e-7 if prec == 0 else 2e-3), (h, serr.max())
+        if prec == 0:
+            assert abs(itg - ito) <= 0.01 * ito + 5
+
+
+def _chain_inputs(n=600, seed=3):
+    prob = inputs.chain16(n, 10)
+    rng = np.random.default_rng(seed)
+    sets = []
+    for j in (0, 3, 8):
+        x0 = prob.x0 if j == 0 else prob.x_true[j - 1]
+        t0 = 0.0 if j == 0 else prob.times[j - 1]
+        x = np.tile(x0, (n, 1)) * np.exp(0.01 * rng.standard_normal((n, prob.d)))
+        th = prob.prior_mean + 0.3 * rng.standard_normal((n, prob.p))
+        sets.append((x, th, (prob.times[j] - t0) / prob.substeps))
+    return prob, sets
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_propagate_chain(pf, oracle, prec):
+    prob, sets = _chain_inputs()
+    rtol = prob.newton_rtol_fp64 if prec == 0 else prob.newton_rtol_fp32
+    for x, th, h in sets:
+        xg, gg, _ = _propagate_gpu(pf, prob, prec, x, th, h, True)
+        xo, go, _ = _propagate_oracle(oracle, prob, x, th, h, True, rtol)
+        err = relerr(xg, xo, prob.state_floor)
+        assert err.max() < TOL[prec], (h, err.max())
+
+
+# ---------------------------------------------------------------- resampling
+@pytest.mark.parametrize("N", [1, 7, 256, 257, 1000, 4097, 65536 + 13])
+def test_resample_bitexact(pf, oracle, N):
+    rng = np.random.default_rng(N)
+    for trial in range(3):
+        g = rng.exponential(size=N) ** (1 + 2 * trial)
+        g[rng.random(N) < 0.2] = 0.0
+        if g.sum() == 0:
+            g[0] = 1.0
+        g /= g.sum()
+        r = int(rng.integers(0, 2**63)) * 2 + trial
+        gd = dev(g)
+        ad = torch.zeros(N, dtype=torch.int32, device="cuda")
+        pf.check(pf.lib().pf_test_resample(N, gd.data_ptr(), r, ad.data_ptr(), None), "resample")
+        st, want = oracle.resample(g, r)
+        assert st == 0
+        assert np.array_equal(ad.cpu().numpy(), want)
+
+
+def test_resample_degenerate(pf):
+    gd = dev(np.zeros(300))
+    ad = torch.zeros(300, dtype=torch.int32, device="cuda")
+    assert pf.lib().pf_test_resample(300, gd.data_ptr(), 5, ad.data_ptr(), None) == pf.PF_EDEGENERATE
+
+
+# ---------------------------------------------------------------- init and one step
+def _get(pf, f):
+    x = torch.zeros((f.d, f.N), dtype=torch.float64, device="cuda")
+    th = torch.zeros((f.p, f.N), dtype=torch.float64, device="cuda")
+    lw = torch.zeros(f.N, dtype=torch.float64, device="cuda")
+    pf.check(pf.lib().pf_test_get_ensemble(f.h, x.data_ptr(), th.data_ptr(), lw.data_ptr()), "get")
+    return x.cpu().numpy().T, th.cpu().numpy().T, lw.cpu().numpy()
+
+
+def _set(pf, f, ora):
+    x, th, lw = dev(ora.x.T), dev(ora.theta.T), dev(ora.logw)
+    mean, _ = ora.moments()
+    L = np.ascontiguousarray(ora.chol())
+    pf.check(pf.lib().pf_test_set_ensemble(f.h, x.data_ptr(), th.data_ptr(), lw.data_ptr(),
+                                           pf._dp(np.ascontiguousarray(mean)), pf._dp(L), ora.j, ora.t),
+             "set")
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_init_matches_oracle(pf, ctx, oracle, prec):
+    prob = inputs.robertson(1000, 5, seed=4)
+    f = pf.Filter(ctx, pf.Config(prob, prec))
+    ora = oracle.Filter(prob)
+    x, th, lw = _get(pf, f)
+    assert np.allclose(th, ora.theta, rtol=1e-13, atol=1e-13)
+    assert np.array_equal(x, ora.x)
+    assert np.allclose(lw, ora.logw, rtol=1e-14)
+    post = f.posterior()
+    mean, cov = ora.moments()
+    assert np.allclose(post["mean"], mean, rtol=1e-12, atol=1e-13)
+    assert np.allclose(post["cov"], cov, rtol=1e-10, atol=1e-14)
+    assert post["ess"] == pytest.approx(1000, rel=1e-12)
+    f.close()
+
+
+def _step_case(pf, ctx, oracle, prob, prec, j0):
+    ora = oracle.Filter(prob)
+    for j in range(j0):
+        assert ora.step(prob.times[j], prob.y[j], prob.sigma[j])["status"] == 0
+    f = pf.Filter(ctx, pf.Config(prob, prec))
+    _set(pf, f, ora)
+    rc, g, anc_o = ora.stage1(prob.times[j0], prob.y[j0], prob.sigma[j0])
+    assert rc == 0
+    st = f.assimilate(prob.times[j0], prob.y[j0], prob.sigma[j0])
+    assert st == pf.PF_OK
+    out = ora.step(prob.times[j0], prob.y[j0], prob.sigma[j0])
+    assert out["status"] == 0
+    anc = torch.zeros(f.N, dtype=torch.int32, device="cuda")
+    pf.check(pf.lib().pf_test_last_ancestors(f.h, anc.data_ptr()), "anc")
+    anc_g = anc.cpu().numpy()
+    x, th, lw = _get(pf, f)
+    post = f.posterior()
+    f.close()
+    return ora, out, anc_o, anc_g, x, th, lw, post
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("j0", [0, 7, 30])
+def test_step_parity_robertson(pf, ctx, oracle, prec, j0):
+    prob = inputs.robertson(1000, 50, seed=2)
+    ora, out, anc_o, anc_g, x, th, lw, post = _step_case(pf, ctx, oracle, prob, prec, j0)
+    same = anc_o == anc_g
+    if prec == 0:
+        assert same.all()
+    else:
+        assert same.mean() > 0.98
+    err = relerr(x[same], ora.x[same], prob.state_floor)
+    assert err.max() < TOL[prec], err.max()
+    assert np.allclose(th[same], ora.theta[same], rtol=1e-12 if prec == 0 else 1e-9, atol=1e-12)
+    if prec == 0:
+        fin = np.isfinite(ora.logw)
+        assert np.allclose(lw[fin], ora.logw[fin], rtol=0, atol=1e-8)
+        mean, cov = ora.moments()
+        assert np.allclose(post["mean"], mean, rtol=1e-10, atol=1e-12)
+        assert np.allclose(post["cov"], cov, rtol=1e-7, atol=1e-12)
+        assert post["ess"] == pytest.approx(out["ess"], rel=1e-8)
+        assert np.allclose(post["state_mean"], out["state_mean"], rtol=1e-9, atol=1e-15)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_step_parity_chain(pf, ctx, oracle, prec):
+    prob = inputs.chain16(700, 10, seed=1)
+    ora, out, anc_o, anc_g, x, th, lw, post = _step_case(pf, ctx, oracle, prob, prec, 2)
+    same = anc_o == anc_g
+    assert same.mean() > (0.999 if prec == 0 else 0.95)
+    err = relerr(x[same], ora.x[same], prob.state_floor)
+    assert err.max() < TOL[prec], err.max()
+    if prec == 0:
+        mean, cov = ora.moments()
+        assert np.allclose(post["mean"], mean, rtol=1e-9, atol=1e-11)
