@@ -1,0 +1,211 @@
+"""Benchmark of the LMM PF-SMC sampler's hot path on one MI355X.
+
+A step is one observation step of Algorithm 1 (steps 2-6) for every particle
+of the filter: shrink + predictor integration, first-stage weights, integer
+systematic resampling, gather + proliferation + repropagation with the
+local-error innovation, second-stage weights, weighted mean / covariance /
+Cholesky.  The workload is the large Robertson configuration: N = 2^17
+particles, 200 observation times log-spaced in [1e-3, 1e3], BDF2 with 20 fixed
+steps per interval, served form = FP32 propagation with FP64 weights and
+moments; the plain FP64 path is timed in the same run for comparison.
+
+Prints one JSON line.  Inputs are synthetic (seeded), resident in HBM before
+the timed region starts.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+from paper_1411_1702_amd import inputs  # noqa: E402
+
+METRIC = "particle-steps/sec FP32 vs FP64 at stated error; p50/p99 assimilate latency"
+
+# Algorithmic floating-point operations of the integrator, counted from the
+# formulas the kernels evaluate (add/sub/mul = 1, fma = 2, reciprocal = 1):
+# per Newton iteration, and per integration step outside Newton (history
+# combination, predictor, and for the repropagation pass the local-error
+# solve and accumulation).  RNG, likelihood and moment arithmetic are not
+# counted (a few percent of the total).
+FLOPS = {
+    inputs.MODEL_ROBERTSON: {"iter": 60, "sub_predict": 22, "sub_update": 47},
+    inputs.MODEL_CHAIN: {"iter": 384, "sub_predict": 177, "sub_update": 305},
+}
+# MI355X vector ALU peak: 256 CU x 4 SIMD x 16 lanes x 2 flop (fma) x 2.4 GHz
+PEAK_VALU_NONPACKED = 256 * 4 * 16 * 2 * 2.4e9 / 1e12      # 78.6 TFLOP/s (fp32 and fp64)
+PEAK_FP32_PUBLISHED = 157.3                                   # TFLOP/s, packed fp32
+
+
+def _percentile(v, q):
+    return float(np.percentile(np.asarray(v), q)) if len(v) else None
+
+
+def time_path(pf, ctx, prob, prec, steps, warmup):
+    """Warm up on one filter, then time `steps` observation steps of a fresh one."""
+    if warmup:
+        fw = pf.Filter(ctx, pf.Config(prob, prec))
+        tk = [fw.assimilate_async(prob.times[j], prob.y[j], prob.sigma[j]) for j in range(warmup)]
+        for t in tk:
+            fw.wait(t)
+        fw.close()
+    f = pf.Filter(ctx, pf.Config(prob, prec))
+    s0 = f.stats()
+    ctx.profile(True)
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tickets = []
+    for j in range(steps):
+        tickets.append(f.assimilate_async(prob.times[j], prob.y[j], prob.sigma[j]))
+        if len(tickets) >= 48:      # keep within the per-filter ring of pending steps
+            st = f.wait(tickets.pop(0))
+            if st != pf.PF_OK:
+                raise RuntimeError(f"step failed: {st}")
+    for t in tickets:
+        st = f.wait(t)
+        if st != pf.PF_OK:
+            raise RuntimeError(f"step failed: {st}")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    times = {k: ctx.kernel_time(w) for k, w in
+             (("step", pf.PF_TIME_STEP), ("predict", pf.PF_TIME_PREDICT),
+              ("resample", pf.PF_TIME_RESAMPLE), ("update", pf.PF_TIME_UPDATE))}
+    ctx.profile(False)
+    s1 = f.stats()
+    post = f.posterior()
+    f.close()
+    n = prob.n_particles
+    fl = FLOPS[prob.model]
+    iters_upd = s1["newton_update"] - s0["newton_update"]
+    iters_pred = s1["newton_predict"] - s0["newton_predict"]
+    flop_upd = iters_upd * fl["iter"] + steps * n * prob.substeps * fl["sub_update"]
+    flop_pred = iters_pred * fl["iter"] + steps * n * prob.substeps * fl["sub_predict"]
+    wall = t1 - t0
+    return {
+        "wall_s": wall,
+        "particle_steps_per_s": n * steps / wall,
+        "ms_per_step": 1e3 * wall / steps,
+        "kernel_ms": {k: v[1] / max(v[0], 1) for k, v in times.items()},
+        "launches": times["update"][0],
+        "newton_per_substep": (iters_upd + iters_pred) / (2.0 * steps * n * prob.substeps),
+        "flop_update_per_launch": flop_upd / steps,
+        "flop_predict_per_launch": flop_pred / steps,
+        "newton_fails": s1["newton_fails"] - s0["newton_fails"],
+        "nonfinite": s1["nonfinite"] - s0["nonfinite"],
+        "final_mean": post["mean"].tolist(),
+        "final_ess": post["ess"],
+    }
+
+
+def latency(pf, ctx, prob, prec, count):
+    """Wall time of synchronous pf_assimilate calls (call to result ready)."""
+    f = pf.Filter(ctx, pf.Config(prob, prec))
+    lat = []
+    for j in range(count):
+        t0 = time.perf_counter()
+        st = f.assimilate(prob.times[j], prob.y[j], prob.sigma[j])
+        lat.append(1e3 * (time.perf_counter() - t0))
+        if st != pf.PF_OK:
+            raise RuntimeError(f"step failed: {st}")
+    f.close()
+    return {"p50_ms": _percentile(lat, 50), "p99_ms": _percentile(lat, 99), "calls": count}
+
+
+def cpu_baseline(prob, target_s):
+    """The FP64 oracle on the host cores: the first S observation steps of the
+    same workload, S chosen so the sample takes about target_s seconds."""
+    from oracle import oracle as O
+    O.lib()
+    threads = O.num_threads()
+    F = O.Filter(prob)
+    t0 = time.perf_counter()
+    F.step(prob.times[0], prob.y[0], prob.sigma[0])
+    one = time.perf_counter() - t0
+    S = 1
+    while S < prob.T and (time.perf_counter() - t0) + one < target_s:
+        out = F.step(prob.times[S], prob.y[S], prob.sigma[S])
+        if out["status"]:
+            break
+        S += 1
+    el = time.perf_counter() - t0
+    return {"value": prob.n_particles * S / el, "unit": "particle-steps/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"first {S} of {prob.T} observation steps at N={prob.n_particles} "
+                      f"(FP64 C oracle, OpenMP over particles, {el:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); independent filters shard "
+              "by whole filters across GPUs, see DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1411_1702_amd import pf
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.init()
+    prob = inputs.config_robertson_large()
+    if args.steps < 1 or args.steps > prob.T:
+        print(f"--steps must be 1..{prob.T} (observation times of the workload)", file=sys.stderr)
+        sys.exit(2)
+    warm = min(args.warmup, prob.T)
+    with pf.Context(0, 4 << 30) as ctx:
+        r32 = time_path(pf, ctx, prob, pf.PF_PREC_FP32_PROP, args.steps, warm)
+        r64 = None if args.no_fp64 else time_path(pf, ctx, prob, pf.PF_PREC_FP64, args.steps, warm)
+        lat = latency(pf, ctx, prob, pf.PF_PREC_FP32_PROP, min(60, prob.T))
+    upd_ms = r32["kernel_ms"]["update"]
+    achieved = r32["flop_update_per_launch"] / (upd_ms * 1e-3) / 1e12
+    roofline = {
+        "bound": "alu", "kernel": "k_update (steps 3c-6: gather, proliferate, BDF2 repropagation "
+                                  "with Newton + local-error innovation, weights, moments)",
+        "achieved": achieved, "peak": PEAK_VALU_NONPACKED, "unit": "TFLOP/s",
+        "frac": achieved / PEAK_VALU_NONPACKED,
+        "frac_of_published_fp32": achieved / PEAK_FP32_PUBLISHED,
+        "traffic": None,
+        "avg_launch_ms": upd_ms,
+        "flop_per_launch": r32["flop_update_per_launch"],
+    }
+    out = {
+        "metric": METRIC,
+        "value": r32["particle_steps_per_s"],
+        "unit": "particle-steps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": warm,
+        "ms_per_step": r32["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"robertson N={prob.n_particles} T={prob.T} BDF{prob.order} "
+                               f"M={prob.substeps} fp32-propagation, fp64 weights/moments",
+                   "particles": prob.n_particles, "observations": prob.T, "bdf_order": prob.order,
+                   "substeps": prob.substeps},
+        "fp32": r32,
+        "fp64": r64,
+        "fp32_over_fp64": (r32["particle_steps_per_s"] / r64["particle_steps_per_s"]) if r64 else None,
+        "latency": lat,
+        "roofline": roofline,
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -145,10 +145,33 @@ pf_status pf_assimilate_batch(pf_context* ctx, uint32_t count, pf_filter* const*
 pf_status pf_posterior(pf_filter* f, double* mean, double* cov, double* state_mean, double* ess,
                        uint64_t* step);
 
-/* Counters since creation: Newton iterations, steps that hit the iteration
- * cap, particles given weight zero for a non-finite state, Cholesky jitters. */
-pf_status pf_stats(pf_filter* f, uint64_t* newton_iters, uint64_t* newton_fails,
-                   uint64_t* nonfinite, uint64_t* jitters);
+/* Counters since creation, written to counters[0..n) (n <= PF_STAT_COUNT):
+ * Newton iterations of the predictor pass (step 2), Newton iterations of
+ * the repropagation pass (step 4), integration steps that hit the Newton
+ * iteration cap, particles given weight zero for a non-finite state, and
+ * Cholesky jitter retries.  Waits for pending steps. */
+enum {
+    PF_STAT_NEWTON_PREDICT = 0,
+    PF_STAT_NEWTON_UPDATE = 1,
+    PF_STAT_NEWTON_FAILS = 2,
+    PF_STAT_NONFINITE = 3,
+    PF_STAT_JITTERS = 4,
+    PF_STAT_COUNT = 5
+};
+pf_status pf_stats(pf_filter* f, uint64_t* counters, uint32_t n);
+
+/*
+ * Kernel timing for benchmarks.  With profiling on, each submission records
+ * HIP events on the context's stream between its kernel groups;
+ * pf_context_kernel_time waits for the recorded submissions and returns the
+ * number of timed submissions and their summed milliseconds for one group:
+ * PF_TIME_STEP (whole step), PF_TIME_PREDICT (step 2 and 3a kernels),
+ * PF_TIME_RESAMPLE (step 3b kernels), PF_TIME_UPDATE (steps 3c-6 kernels).
+ * pf_context_profile(ctx, on) clears the totals.
+ */
+enum { PF_TIME_STEP = 0, PF_TIME_PREDICT = 1, PF_TIME_RESAMPLE = 2, PF_TIME_UPDATE = 3 };
+pf_status pf_context_profile(pf_context* ctx, int enable);
+pf_status pf_context_kernel_time(pf_context* ctx, int which, uint64_t* count, double* ms);
 
 /* Releases the filter's pool memory after its pending steps complete. */
 void pf_destroy(pf_filter* f);

@@ -134,9 +134,11 @@ __device__ inline bool last_tile(uint32_t* ctr, uint32_t ntiles, int* sh_flag)
 
 // Combine per-tile log-domain partials part[t*stride + 0] = tile max,
 // part[t*stride + 1 + a] = sums scaled by exp(-tile max), a < nsum, in a
-// fixed order: out[a] = sum_t exp(max_t - M) part[t][1+a].  Returns M.
+// fixed order: out[a] = sum_t exp(max_t - M) part[t][1+a].  The sum with
+// index sq (a sum of squared weights) scales with exp(2 (max_t - M)).
+// Returns M.
 __device__ double combine_tiles(const double* part, int stride, int ntiles, int nsum, double* out,
-                                double* sh /* >= TILE doubles */)
+                                double* sh /* >= TILE doubles */, int sq = -1)
 {
     // global max: fixed strided pass then the fixed block tree
     double mx = -INFINITY;
@@ -148,7 +150,10 @@ __device__ double combine_tiles(const double* part, int stride, int ntiles, int 
     if (g < groups && M > -INFINITY) {
         for (int t = g; t < ntiles; t += groups) {
             const double mt = part[(size_t)t * stride];
-            if (mt > -INFINITY) acc += exp(mt - M) * part[(size_t)t * stride + 1 + a];
+            if (mt > -INFINITY) {
+                const double sc = exp(mt - M);
+                acc += (a == sq ? sc * sc : sc) * part[(size_t)t * stride + 1 + a];
+            }
         }
     }
     __syncthreads();
@@ -249,7 +254,7 @@ __device__ void finalize_moments(const FilterDesc& fd, FilterState& st, bool fli
     __shared__ double tot[NACC_MAX];
     __shared__ double mean[PMAX], dm[PMAX], Cm[PMAX * PMAX], Lm[PMAX * PMAX];
     const int p = fd.p, d = fd.d;
-    combine_tiles(fd.part2, fd.nacc, fd.ntiles, fd.nacc - 1, tot, sh);
+    combine_tiles(fd.part2, fd.nacc, fd.ntiles, fd.nacc - 1, tot, sh, 1);
     if (threadIdx.x == 0) {
         const double s0 = tot[0], s00 = tot[1];
         if (!(s0 > 0.0) || !isfinite(s0)) {
@@ -434,7 +439,7 @@ __global__ __launch_bounds__(TILE) void k_predict(const uint32_t* items, int n_i
         if (threadIdx.x == 0) {
             fd.part1[2 * itm.tile] = Mt;
             fd.part1[2 * itm.tile + 1] = s;
-            atomicAdd(&st.newton_iters, it_sum);
+            atomicAdd(&st.newton_pred, it_sum);
             if (fl_sum) atomicAdd(&st.newton_fails, fl_sum);
         }
         if (last_tile(&fd.done[0], fd.ntiles, &flag)) {
@@ -626,7 +631,7 @@ __global__ __launch_bounds__(TILE) void k_update(const uint32_t* items, int n_it
         const unsigned long long fl_sum = block_sum_u64(fails, shu);
         const unsigned long long nf_sum = block_sum_u64(nonf, shu);
         if (threadIdx.x == 0) {
-            atomicAdd(&st.newton_iters, it_sum);
+            atomicAdd(&st.newton_upd, it_sum);
             if (fl_sum) atomicAdd(&st.newton_fails, fl_sum);
             if (nf_sum) atomicAdd(&st.nonfinite, nf_sum);
         }

@@ -134,8 +134,19 @@ struct Stage {
     hipEvent_t ev = nullptr;
 };
 
+// one profiled submission: events before begin, after predict, after
+// resampling, after update, after end
+struct ProfRec {
+    hipEvent_t ev[5];
+};
+
 struct pf_context {
     int device = 0;
+    bool profiling = false;
+    std::vector<ProfRec> prof_pending;
+    std::vector<hipEvent_t> ev_pool;
+    uint64_t prof_count = 0;
+    double prof_ms[4] = {0, 0, 0, 0};
     hipStream_t stream = nullptr;
     bool own_stream = false;
     Pool pool;
@@ -149,6 +160,8 @@ struct pf_context {
     int grid_cap = 2048;
     std::mutex mu;
 };
+
+static pf_status prof_collect(pf_context* ctx);
 
 // k_end that also mirrors the status to host-mapped memory
 namespace pf {
@@ -380,6 +393,8 @@ extern "C" void pf_context_destroy(pf_context* ctx)
         (void)hipFree(ctx->stage[s].dev);
     }
     (void)hipHostFree(ctx->h_ring);
+    (void)prof_collect(ctx);
+    for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     (void)hipFree(ctx->d_desc);
     (void)hipFree(ctx->d_state);
     (void)hipFree(ctx->pool.base);
@@ -471,6 +486,63 @@ extern "C" pf_status pf_create(pf_context* ctx, const pf_config* cfg, pf_filter*
 }
 
 // ---------------------------------------------------------------------------
+// profiling (events on the context stream)
+// ---------------------------------------------------------------------------
+static hipEvent_t prof_event(pf_context* ctx)
+{
+    if (!ctx->ev_pool.empty()) {
+        hipEvent_t e = ctx->ev_pool.back();
+        ctx->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+}
+
+static pf_status prof_collect(pf_context* ctx)
+{
+    for (ProfRec& r : ctx->prof_pending) {
+        HIP_TRY(hipEventSynchronize(r.ev[4]));
+        float ms[4];
+        HIP_TRY(hipEventElapsedTime(&ms[0], r.ev[0], r.ev[4]));
+        HIP_TRY(hipEventElapsedTime(&ms[1], r.ev[0], r.ev[1]));
+        HIP_TRY(hipEventElapsedTime(&ms[2], r.ev[1], r.ev[2]));
+        HIP_TRY(hipEventElapsedTime(&ms[3], r.ev[2], r.ev[3]));
+        for (int i = 0; i < 4; ++i) ctx->prof_ms[i] += ms[i];
+        ctx->prof_count++;
+        for (int i = 0; i < 5; ++i) ctx->ev_pool.push_back(r.ev[i]);
+    }
+    ctx->prof_pending.clear();
+    return PF_OK;
+}
+
+extern "C" pf_status pf_context_profile(pf_context* ctx, int enable)
+{
+    if (!ctx) return fail(PF_EINVAL, "ctx is NULL");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    HIP_TRY(hipSetDevice(ctx->device));
+    pf_status s = prof_collect(ctx);
+    if (s != PF_OK) return s;
+    ctx->profiling = enable != 0;
+    ctx->prof_count = 0;
+    for (double& v : ctx->prof_ms) v = 0.0;
+    return PF_OK;
+}
+
+extern "C" pf_status pf_context_kernel_time(pf_context* ctx, int which, uint64_t* count, double* ms)
+{
+    if (!ctx || which < 0 || which > 3) return fail(PF_EINVAL, "bad argument");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    HIP_TRY(hipSetDevice(ctx->device));
+    pf_status s = prof_collect(ctx);
+    if (s != PF_OK) return s;
+    if (count) *count = ctx->prof_count;
+    if (ms) *ms = ctx->prof_ms[which];
+    return PF_OK;
+}
+
+// ---------------------------------------------------------------------------
 // submission
 // ---------------------------------------------------------------------------
 static pf_status submit(pf_context* ctx, uint32_t count, pf_filter* const* fs, const double* t_obs,
@@ -534,24 +606,36 @@ static pf_status submit(pf_context* ctx, uint32_t count, pf_filter* const* fs, c
     HIP_TRY(hipMemcpyAsync(d_items, items, sizeof(uint32_t) * n_all, hipMemcpyHostToDevice, ctx->stream));
 
     const unsigned gb = (count + 255) / 256;
+    ProfRec pr{};
+    if (ctx->profiling) {
+        for (int i = 0; i < 5; ++i) pr.ev[i] = prof_event(ctx);
+        HIP_TRY(hipEventRecord(pr.ev[0], ctx->stream));
+    }
     hipLaunchKernelGGL(k_begin, dim3(gb), dim3(256), 0, ctx->stream, d_recs, (int)count, ctx->d_desc, ctx->d_state);
     for (const Range& r : ranges) {
         const int model = r.cls / 8 + 1, prec = (r.cls % 8) / 4, order = r.cls % 4;
         hipLaunchKernelGGL(predict_kernel(model, prec, order), dim3(grid_for(ctx, r.cnt)), dim3(TILE), 0,
                            ctx->stream, d_items + r.off, r.cnt, d_recs, ctx->d_desc, ctx->d_state);
     }
+    if (ctx->profiling) HIP_TRY(hipEventRecord(pr.ev[1], ctx->stream));
     hipLaunchKernelGGL(k_count, dim3(grid_for(ctx, n_all)), dim3(TILE), 0, ctx->stream, d_items, n_all, d_recs,
                        ctx->d_desc, ctx->d_state);
     hipLaunchKernelGGL(k_scatter, dim3(grid_for(ctx, n_all)), dim3(TILE), 0, ctx->stream, d_items, n_all, d_recs,
                        ctx->d_desc, ctx->d_state);
+    if (ctx->profiling) HIP_TRY(hipEventRecord(pr.ev[2], ctx->stream));
     for (const Range& r : ranges) {
         const int model = r.cls / 8 + 1, prec = (r.cls % 8) / 4, order = r.cls % 4;
         hipLaunchKernelGGL(update_kernel(model, prec, order), dim3(grid_for(ctx, r.cnt)), dim3(TILE), 0,
                            ctx->stream, d_items + r.off, r.cnt, d_recs, ctx->d_desc, ctx->d_state);
     }
+    if (ctx->profiling) HIP_TRY(hipEventRecord(pr.ev[3], ctx->stream));
     hipLaunchKernelGGL(k_end_host, dim3(gb), dim3(256), 0, ctx->stream, d_recs, (int)count, ctx->d_state,
                        ctx->d_ring);
     HIP_TRY(hipGetLastError());
+    if (ctx->profiling) {
+        HIP_TRY(hipEventRecord(pr.ev[4], ctx->stream));
+        ctx->prof_pending.push_back(pr);
+    }
     HIP_TRY(hipEventRecord(sg.ev, ctx->stream));
     auto ev = std::shared_ptr<hipEvent_t>(new hipEvent_t, [](hipEvent_t* e) { (void)hipEventDestroy(*e); delete e; });
     HIP_TRY(hipEventCreateWithFlags(ev.get(), hipEventDisableTiming));
@@ -647,17 +731,15 @@ extern "C" pf_status pf_posterior(pf_filter* f, double* mean, double* cov, doubl
     return PF_OK;
 }
 
-extern "C" pf_status pf_stats(pf_filter* f, uint64_t* newton_iters, uint64_t* newton_fails, uint64_t* nonfinite,
-                              uint64_t* jitters)
+extern "C" pf_status pf_stats(pf_filter* f, uint64_t* counters, uint32_t n)
 {
-    if (!f) return fail(PF_EINVAL, "NULL filter");
+    if (!f || (n && !counters)) return fail(PF_EINVAL, "NULL argument");
+    if (n > PF_STAT_COUNT) return fail(PF_EINVAL, "n larger than PF_STAT_COUNT");
     FilterState st;
     pf_status s = read_state(f, &st);
     if (s != PF_OK) return s;
-    if (newton_iters) *newton_iters = st.newton_iters;
-    if (newton_fails) *newton_fails = st.newton_fails;
-    if (nonfinite) *nonfinite = st.nonfinite;
-    if (jitters) *jitters = st.jitters;
+    const uint64_t v[PF_STAT_COUNT] = {st.newton_pred, st.newton_upd, st.newton_fails, st.nonfinite, st.jitters};
+    for (uint32_t i = 0; i < n; ++i) counters[i] = v[i];
     return PF_OK;
 }
 

@@ -75,7 +75,7 @@ struct FilterState {
     uint64_t seq;                       // host ticket
     double lse_max, lse_sum;            // first-stage log-sum-exp
     uint64_t T, V;                      // resampling total and offset
-    unsigned long long newton_iters, newton_fails, nonfinite, jitters;
+    unsigned long long newton_pred, newton_upd, newton_fails, nonfinite, jitters;
     int32_t ring[RING];                 // status by ticket % RING
 };
 

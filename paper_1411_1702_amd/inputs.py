@@ -173,12 +173,15 @@ def chain_constants(model_seed: int):
     return k, V, K
 
 
+CHAIN_X0 = 0.1   # every compartment starts at 0.1
+
+
 @functools.lru_cache(maxsize=64)
 def _chain_truth(model_seed: int, T: int, dt: float):
     k, V, K = chain_constants(model_seed)
     times = dt * np.arange(1, T + 1)
     f, jac = _chain_rhs(k, V, K)
-    x_true = _truth(f, jac, np.ones(CHAIN_D), times, atol=1e-24)
+    x_true = _truth(f, jac, np.full(CHAIN_D, CHAIN_X0), times, atol=1e-30)
     return times, x_true
 
 
@@ -190,11 +193,11 @@ def chain16(n_particles: int = 65536, T: int = 100, seed: int = 0, model_seed: i
     obs = np.array([7, 15], dtype=np.int32)
     y, sigma = _noise(x_true, obs, seed)
     theta = np.log(k[:CHAIN_P])
-    scale = np.maximum(np.abs(x_true).max(axis=0), 1.0)
+    scale = np.abs(x_true).max(axis=0)
     return Problem(
         name=f"chain16_N{n_particles}_T{T}", model=MODEL_CHAIN, d=CHAIN_D, p=CHAIN_P, m=2,
         obs_index=obs, model_consts=np.concatenate([V, K]), rates_fixed=k.copy(),
-        x0=np.ones(CHAIN_D), prior_mean=theta.copy(), prior_sd=np.full(CHAIN_P, 0.5),
+        x0=np.full(CHAIN_D, CHAIN_X0), prior_mean=theta.copy(), prior_sd=np.full(CHAIN_P, 0.5),
         theta_true=theta, t0=0.0, times=times, x_true=x_true, y=y, sigma=sigma,
         order=order, substeps=substeps, n_particles=int(n_particles), seed=int(seed),
         state_floor=1e-6 * scale)

@@ -19,11 +19,13 @@ PF_ENONFINITE, PF_EDEVICE, PF_EBUSY, PF_EORDER = 5, 6, 7, 8
 PF_MODEL_ROBERTSON, PF_MODEL_CHAIN16 = 1, 2
 PF_LMM_BDF = 0
 PF_PREC_FP64, PF_PREC_FP32_PROP = 0, 1
+PF_TIME_STEP, PF_TIME_PREDICT, PF_TIME_RESAMPLE, PF_TIME_UPDATE = 0, 1, 2, 3
 
 EXPORTS = [
     "pf_context_create", "pf_context_destroy", "pf_filter_bytes", "pf_context_memory",
     "pf_create", "pf_assimilate", "pf_assimilate_async", "pf_wait", "pf_assimilate_batch",
     "pf_posterior", "pf_stats", "pf_destroy", "pf_status_str", "pf_last_error",
+    "pf_context_profile", "pf_context_kernel_time",
     "pf_test_philox", "pf_test_normals", "pf_test_propagate", "pf_test_resample",
     "pf_test_get_ensemble", "pf_test_set_ensemble", "pf_test_last_ancestors",
 ]
@@ -73,7 +75,9 @@ def lib():
         L.pf_wait.argtypes = [vp, u64]
         L.pf_assimilate_batch.argtypes = [vp, C.c_uint32, C.POINTER(vp), dp, dp, dp, C.POINTER(u64)]
         L.pf_posterior.argtypes = [vp, dp, dp, dp, dp, C.POINTER(u64)]
-        L.pf_stats.argtypes = [vp] + [C.POINTER(u64)] * 4
+        L.pf_stats.argtypes = [vp, C.POINTER(u64), C.c_uint32]
+        L.pf_context_profile.argtypes = [vp, C.c_int]
+        L.pf_context_kernel_time.argtypes = [vp, C.c_int, C.POINTER(u64), C.POINTER(C.c_double)]
         L.pf_destroy.argtypes = [vp]
         L.pf_destroy.restype = None
         L.pf_status_str.argtypes = [C.c_int]
@@ -167,6 +171,15 @@ class Context:
         check(lib().pf_assimilate_batch(self.h, n, hs, _dp(t), _dp(yy), _dp(ss), tk), "pf_assimilate_batch")
         return list(tk)
 
+    def profile(self, enable=True):
+        check(lib().pf_context_profile(self.h, int(enable)), "pf_context_profile")
+
+    def kernel_time(self, which):
+        """(timed submissions, total ms) for PF_TIME_* group `which`."""
+        n, ms = C.c_uint64(), C.c_double()
+        check(lib().pf_context_kernel_time(self.h, int(which), C.byref(n), C.byref(ms)), "kernel_time")
+        return n.value, ms.value
+
     def close(self):
         if self.h:
             lib().pf_context_destroy(self.h)
@@ -221,9 +234,9 @@ class Filter:
                 "step": step.value}
 
     def stats(self):
-        v = [C.c_uint64() for _ in range(4)]
-        check(lib().pf_stats(self.h, *[C.byref(x) for x in v]), "pf_stats")
-        return dict(zip(["newton_iters", "newton_fails", "nonfinite", "jitters"], [x.value for x in v]))
+        v = (C.c_uint64 * 5)()
+        check(lib().pf_stats(self.h, v, 5), "pf_stats")
+        return dict(zip(["newton_predict", "newton_update", "newton_fails", "nonfinite", "jitters"], list(v)))
 
     def close(self):
         if self.h:

@@ -117,8 +117,12 @@ def test_propagate_robertson(pf, oracle, prec, lte):
         err = relerr(xg, xo, prob.state_floor)
         assert err.max() < TOL[prec], (h, err.max())
         if lte:
-            serr = relerr(np.sqrt(gg), np.sqrt(go), prob.state_floor)
-            assert serr.max() < (1e-7 if prec == 0 else 2e-3), (h, serr.max())
+            # FP32: a local error below the state's own resolution is seen as
+            # rounding noise of order sqrt(M) ulp(x); bound it by that
+            noise = 0.0 if prec == 0 else 4 * np.sqrt(prob.substeps) * 2.0**-23 * np.abs(xo)
+            dev_ = np.abs(np.sqrt(gg) - np.sqrt(go))
+            bound = (1e-7 if prec == 0 else 2e-3) * np.maximum(np.sqrt(go), prob.state_floor) + noise
+            assert np.all(dev_ <= bound), (h, (dev_ / bound).max())
         if prec == 0:
             assert abs(itg - ito) <= 0.01 * ito + 5
 
@@ -207,10 +211,27 @@ def test_init_matches_oracle(pf, ctx, oracle, prec):
     f.close()
 
 
+def _innovation_scale(oracle, prob, x_in, t_in, anc, theta_new, step):
+    """Per slot and component, the largest term of x_{j+1} = Psi(x_j) + v:
+    max(|Psi|, sqrt(Gamma)|z|).  A state formed by cancellation of the two is
+    judged against the terms that formed it."""
+    h = (prob.times[step - 1] - t_in) / prob.substeps
+    out = np.zeros((len(anc), prob.d))
+    for n, k in enumerate(anc):
+        xt, gam, _ = oracle.psi(prob.model, x_in[k], theta_new[n], h, prob.substeps, prob.order,
+                                lte=True, rtol=prob.newton_rtol_fp64, kmax=prob.newton_max_iter,
+                                floor=prob.state_floor, mc=prob.model_consts,
+                                rates_fixed=prob.rates_fixed)
+        z = oracle.normals(prob.seed, step, n, oracle.PUR_INNOV, prob.d)
+        out[n] = np.maximum(np.abs(xt), np.sqrt(gam) * np.abs(z))
+    return out
+
+
 def _step_case(pf, ctx, oracle, prob, prec, j0):
     ora = oracle.Filter(prob)
     for j in range(j0):
         assert ora.step(prob.times[j], prob.y[j], prob.sigma[j])["status"] == 0
+    x_in, t_in = ora.x.copy(), ora.t
     f = pf.Filter(ctx, pf.Config(prob, prec))
     _set(pf, f, ora)
     rc, g, anc_o = ora.stage1(prob.times[j0], prob.y[j0], prob.sigma[j0])
@@ -225,20 +246,22 @@ def _step_case(pf, ctx, oracle, prob, prec, j0):
     x, th, lw = _get(pf, f)
     post = f.posterior()
     f.close()
-    return ora, out, anc_o, anc_g, x, th, lw, post
+    scale = np.maximum(_innovation_scale(oracle, prob, x_in, t_in, anc_o, ora.theta, j0 + 1),
+                       prob.state_floor)
+    return ora, out, anc_o, anc_g, x, th, lw, post, scale
 
 
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("j0", [0, 7, 30])
 def test_step_parity_robertson(pf, ctx, oracle, prec, j0):
     prob = inputs.robertson(1000, 50, seed=2)
-    ora, out, anc_o, anc_g, x, th, lw, post = _step_case(pf, ctx, oracle, prob, prec, j0)
+    ora, out, anc_o, anc_g, x, th, lw, post, scale = _step_case(pf, ctx, oracle, prob, prec, j0)
     same = anc_o == anc_g
     if prec == 0:
         assert same.all()
     else:
         assert same.mean() > 0.98
-    err = relerr(x[same], ora.x[same], prob.state_floor)
+    err = np.abs(x[same] - ora.x[same]) / scale[same]
     assert err.max() < TOL[prec], err.max()
     assert np.allclose(th[same], ora.theta[same], rtol=1e-12 if prec == 0 else 1e-9, atol=1e-12)
     if prec == 0:
@@ -253,11 +276,11 @@ def test_step_parity_robertson(pf, ctx, oracle, prec, j0):
 
 @pytest.mark.parametrize("prec", [0, 1])
 def test_step_parity_chain(pf, ctx, oracle, prec):
-    prob = inputs.chain16(700, 10, seed=1)
-    ora, out, anc_o, anc_g, x, th, lw, post = _step_case(pf, ctx, oracle, prob, prec, 2)
+    prob = inputs.chain16(2000, 10, seed=1)
+    ora, out, anc_o, anc_g, x, th, lw, post, scale = _step_case(pf, ctx, oracle, prob, prec, 3)
     same = anc_o == anc_g
     assert same.mean() > (0.999 if prec == 0 else 0.95)
-    err = relerr(x[same], ora.x[same], prob.state_floor)
+    err = np.abs(x[same] - ora.x[same]) / scale[same]
     assert err.max() < TOL[prec], err.max()
     if prec == 0:
         mean, cov = ora.moments()
