@@ -44,36 +44,60 @@ struct Philox {
 // (0,1) uniform from the top 53 bits of a word
 __device__ inline double unit_open(uint64_t w) { return ((double)(w >> 11) + 0.5) * 0x1p-53; }
 
-// `count` standard normals of one (step, particle, purpose): block b gives
-// words w0..w3 and the Box-Muller pairs (w0, w1) and (w2, w3).
-template <int COUNT>
-__device__ inline void normals(uint64_t seed, uint64_t step, uint64_t particle, uint64_t purpose,
-                               double z[COUNT])
+// Box-Muller pair from two uniforms, in the precision of the caller's
+// propagation (FP32 inputs are the FP64 uniforms rounded to float; the angle
+// goes through sincospi, whose argument 2u needs no range reduction).
+__device__ inline void box_muller(double u0, double u1, double& z0, double& z1)
 {
     constexpr double kTwoPi = 6.283185307179586476925286766559;
+    const double rad = sqrt(-2.0 * log(u0));
+    double sn, cs;
+    sincos(kTwoPi * u1, &sn, &cs);
+    z0 = rad * cs;
+    z1 = rad * sn;
+}
+__device__ inline void box_muller(float u0, float u1, float& z0, float& z1)
+{
+    const float rad = sqrtf(-2.0f * logf(u0));
+    float sn, cs;
+    sincospif(2.0f * u1, &sn, &cs);
+    z0 = rad * cs;
+    z1 = rad * sn;
+}
+
+// `count` standard normals of one (step, particle, purpose): block b gives
+// words w0..w3 and the Box-Muller pairs (w0, w1) and (w2, w3).
+template <int COUNT, class RT = double>
+__device__ inline void normals(uint64_t seed, uint64_t step, uint64_t particle, uint64_t purpose,
+                               RT z[COUNT])
+{
 #pragma unroll
     for (int b = 0; b < (COUNT + 3) / 4; ++b) {
         uint64_t w[4];
         Philox::block(step, particle, purpose, (uint64_t)b, seed, 0, w);
-        const double rad0 = sqrt(-2.0 * log(unit_open(w[0])));
-        const double rad1 = sqrt(-2.0 * log(unit_open(w[2])));
-        double s0, c0, s1, c1;
-        sincos(kTwoPi * unit_open(w[1]), &s0, &c0);
-        sincos(kTwoPi * unit_open(w[3]), &s1, &c1);
-        const double v[4] = {rad0 * c0, rad0 * s0, rad1 * c1, rad1 * s1};
+        RT v[4];
+        box_muller((RT)unit_open(w[0]), (RT)unit_open(w[1]), v[0], v[1]);
+        box_muller((RT)unit_open(w[2]), (RT)unit_open(w[3]), v[2], v[3]);
 #pragma unroll
         for (int s = 0; s < 4; ++s)
             if (4 * b + s < COUNT) z[4 * b + s] = v[s];
     }
 }
 
+// rate constant from a log-parameter: exponential in FP64 (the parameters
+// are FP64), rounded once to the propagation precision
+template <class R> __device__ inline R exp_rate(double th, R) { return (R)exp(th); }
+
 // reciprocal: single-instruction v_rcp_f32 in FP32 (about 1 ulp), correctly
 // rounded division in FP64
 __device__ inline float recip(float v) { return __builtin_amdgcn_rcpf(v); }
 __device__ inline double recip(double v) { return 1.0 / v; }
 
-template <class R> __device__ inline R rabs(R v) { return v < R(0) ? -v : v; }
-template <class R> __device__ inline R rmax(R a, R b) { return a > b ? a : b; }
+// |v| and max(a, b) as single instructions (max returns the non-NaN operand)
+__device__ inline float rabs(float v) { return fabsf(v); }
+__device__ inline double rabs(double v) { return fabs(v); }
+__device__ inline float rmax(float a, float b) { return fmaxf(a, b); }
+__device__ inline double rmax(double a, double b) { return fmax(a, b); }
 
 // ---------------------------------------------------------------------------
 // Models.  `eval` returns f(x) and the factorisation of the Newton matrix
@@ -93,9 +117,9 @@ struct Robertson {
 
     __device__ inline void set_params(const double th[P], const FilterDesc&)
     {
-        k1 = (R)exp(th[0]);
-        k2 = (R)exp(th[1]);
-        k3 = (R)exp(th[2]);
+        k1 = exp_rate(th[0], R(0));
+        k2 = exp_rate(th[1], R(0));
+        k3 = exp_rate(th[2], R(0));
     }
 
     __device__ inline void eval(const R x[D], R c, R f[D], LU& lu) const
@@ -149,7 +173,7 @@ struct Chain16 {
     __device__ inline void set_params(const double th[P], const FilterDesc& fd)
     {
 #pragma unroll
-        for (int i = 0; i < D; ++i) k[i] = i < P ? (R)exp(th[i]) : (R)fd.rates_fixed[i];
+        for (int i = 0; i < D; ++i) k[i] = i < P ? exp_rate(th[i], R(0)) : (R)fd.rates_fixed[i];
         if constexpr (sizeof(R) == 4) VK = (const R*)fd.mc_f;
         else VK = (const R*)fd.mc;
     }
@@ -205,6 +229,9 @@ __device__ inline void integrate(const Model& md, R x[Model::D], R gam[Model::D]
 {
     constexpr int D = Model::D;
     const R h = (R)h_d;
+    R fl[D];                 // scale floors of the stopping test, in registers
+#pragma unroll
+    for (int i = 0; i < D; ++i) fl[i] = floor_[i];
     R h1[D], h2[D], h3[D];   // x_{m-2}, x_{m-3}, x_{m-4}
     if constexpr (LTE) {
 #pragma unroll
@@ -249,7 +276,7 @@ __device__ inline void integrate(const Model& md, R x[Model::D], R gam[Model::D]
 #pragma unroll
             for (int i = 0; i < D; ++i) {
                 xn[i] += b[i];
-                ok = ok && (rabs(b[i]) <= rtol * rmax(rabs(xn[i]), floor_[i]));
+                ok &= rabs(b[i]) <= rtol * rmax(rabs(xn[i]), fl[i]);
             }
             if (ok) { conv = true; break; }
         }

@@ -4,21 +4,24 @@
 // Work is a list of (batch entry, tile) items; a workgroup of TILE lanes
 // owns one tile of TILE particles, one particle per lane.  Kernels loop over
 // the list (grid-stride), so one launch covers every filter in the batch.
-// Per-filter reductions use fixed tiles combined in a fixed order by the last
-// tile to finish (an atomic counter per filter and kernel), so a filter's
-// arithmetic never depends on what else is in the batch.
+// Per-filter reductions use fixed tiles combined in a fixed order, so a
+// filter's arithmetic never depends on what else is in the batch.  No kernel
+// waits on another workgroup: whatever a tile needs from the whole filter
+// (the first-stage log-sum-exp, the integer CDF offset of its tile) it
+// recomputes from the previous kernel's per-tile partials, in the same fixed
+// order in every workgroup.
 //
-//   k_begin    : validate the step, compute h, copy y and sigma
-//   k_predict  : shrink, predictor Psi, first-stage log-weights, tile LSE
-//                (last tile: the filter's log-sum-exp)            steps 2, 3a
-//   k_count    : integer weights q = floor(g 2^S), tile sums
-//                (last tile: scan of tile sums, T and offset V)   step 3b
-//   k_scatter  : ancestors by scatter of the integer CDF           step 3b
+//   k_predict  : shrink, predictor Psi, first-stage log-weights, tile
+//                (max, sum exp)                                    steps 2, 3a
+//   k_count    : filter log-sum-exp from the tile partials; integer weights
+//                q = floor(g 2^S); tile sums                       step 3b
+//   k_scatter  : tile offset and total of the integer CDF, systematic
+//                offset V, ancestors by scatter                    step 3b
 //   k_update   : gather, proliferate, Psi with local-error estimate,
 //                innovation, second-stage log-weights, tile moments
-//                (last tile: mean, covariance, ESS, Cholesky,
-//                commit)                                           steps 3c-6
-//   k_end      : record the step's status by ticket
+//                                                                  steps 3c-5
+//   k_moments  : one workgroup per filter: mean, covariance, ESS, Cholesky,
+//                commit, status by ticket                          step 6
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -32,25 +35,75 @@ constexpr int WAVE = 64;
 constexpr int NWAVE = TILE / WAVE;
 
 // ---------------------------------------------------------------------------
-// block reductions (fixed butterfly + fixed wave order: deterministic)
+// wavefront reductions with DPP lane moves (VALU operand modifiers, no LDS
+// round trip): pairs, quads, half rows, rows, then the two row broadcasts of
+// wave64.  A fixed tree, so results are deterministic; the full result lands
+// in lane 63 and is broadcast with readlane.
 // ---------------------------------------------------------------------------
-__device__ inline double wave_max(double v)
+constexpr int DPP_QUAD_1032 = 0xB1;      // quad_perm [1,0,3,2]
+constexpr int DPP_QUAD_2301 = 0x4E;      // quad_perm [2,3,0,1]
+constexpr int DPP_ROW_MIRROR = 0x140;
+constexpr int DPP_ROW_HALF_MIRROR = 0x141;
+constexpr int DPP_ROW_BCAST15 = 0x142;
+constexpr int DPP_ROW_BCAST31 = 0x143;
+
+template <int CTRL, int ROWS>
+__device__ inline uint64_t dpp64(uint64_t v)
 {
-#pragma unroll
-    for (int o = WAVE / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
-    return v;
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, CTRL, ROWS, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), CTRL, ROWS, 0xF, false);
+    return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
 }
+template <int CTRL, int ROWS>
+__device__ inline double dppd(double v)
+{
+    return __longlong_as_double((long long)dpp64<CTRL, ROWS>((uint64_t)__double_as_longlong(v)));
+}
+__device__ inline uint64_t lane63_u64(uint64_t v)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 63);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 63);
+    return ((uint64_t)hi << 32) | lo;
+}
+__device__ inline double lane63(double v)
+{
+    return __longlong_as_double((long long)lane63_u64((uint64_t)__double_as_longlong(v)));
+}
+
 __device__ inline double wave_sum(double v)
 {
-#pragma unroll
-    for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
+    v += dppd<DPP_QUAD_1032, 0xF>(v);
+    v += dppd<DPP_QUAD_2301, 0xF>(v);
+    v += dppd<DPP_ROW_HALF_MIRROR, 0xF>(v);
+    v += dppd<DPP_ROW_MIRROR, 0xF>(v);
+    v += dppd<DPP_ROW_BCAST15, 0xA>(v);
+    v += dppd<DPP_ROW_BCAST31, 0xC>(v);
+    return lane63(v);
+}
+// max: lanes outside the broadcast rows receive 0 from the move, so the
+// broadcast steps use the -inf-padded form max(v, move(v) or v)
+__device__ inline double wave_max(double v)
+{
+    v = fmax(v, dppd<DPP_QUAD_1032, 0xF>(v));
+    v = fmax(v, dppd<DPP_QUAD_2301, 0xF>(v));
+    v = fmax(v, dppd<DPP_ROW_HALF_MIRROR, 0xF>(v));
+    v = fmax(v, dppd<DPP_ROW_MIRROR, 0xF>(v));
+    const uint32_t row = (__lane_id() >> 4);
+    const double b15 = dppd<DPP_ROW_BCAST15, 0xA>(v);
+    if (row & 1) v = fmax(v, b15);
+    const double b31 = dppd<DPP_ROW_BCAST31, 0xC>(v);
+    if (row >= 2) v = fmax(v, b31);
+    return lane63(v);
 }
 __device__ inline unsigned long long wave_sum_u64(unsigned long long v)
 {
-#pragma unroll
-    for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
+    v += dpp64<DPP_QUAD_1032, 0xF>(v);
+    v += dpp64<DPP_QUAD_2301, 0xF>(v);
+    v += dpp64<DPP_ROW_HALF_MIRROR, 0xF>(v);
+    v += dpp64<DPP_ROW_MIRROR, 0xF>(v);
+    v += dpp64<DPP_ROW_BCAST15, 0xA>(v);
+    v += dpp64<DPP_ROW_BCAST31, 0xC>(v);
+    return lane63_u64(v);
 }
 
 __device__ inline double block_max(double v, double* sh)
@@ -114,40 +167,45 @@ __device__ inline unsigned long long block_exscan_u64(unsigned long long v, unsi
     return total;
 }
 
-// The calling block is the last of `ntiles` to arrive at counter `ctr`?
-// Release this tile's partial results, then acquire everybody's.
-__device__ inline bool last_tile(uint32_t* ctr, uint32_t ntiles, int* sh_flag)
-{
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const uint32_t prev = atomicAdd(ctr, 1u);
-        const int last = prev == ntiles - 1;
-        if (last) *ctr = 0;   // every tile has arrived: reset for the next step
-        *sh_flag = last;
-    }
-    __syncthreads();
-    const bool last = *sh_flag != 0;
-    if (last) __threadfence();
-    return last;
-}
-
 // Combine per-tile log-domain partials part[t*stride + 0] = tile max,
 // part[t*stride + 1 + a] = sums scaled by exp(-tile max), a < nsum, in a
 // fixed order: out[a] = sum_t exp(max_t - M) part[t][1+a].  The sum with
 // index sq (a sum of squared weights) scales with exp(2 (max_t - M)).
-// Returns M.
+// With an LDS staging buffer (buf, buf_len doubles), tiles are read in
+// coalesced chunks; the order of the sums depends only on ntiles, stride and
+// buf_len.  Returns M.
 __device__ double combine_tiles(const double* part, int stride, int ntiles, int nsum, double* out,
-                                double* sh /* >= TILE doubles */, int sq = -1)
+                                double* sh /* >= TILE doubles */, int sq = -1, double* buf = nullptr,
+                                int buf_len = 0)
 {
-    // global max: fixed strided pass then the fixed block tree
     double mx = -INFINITY;
     for (int t = threadIdx.x; t < ntiles; t += TILE) mx = fmax(mx, part[(size_t)t * stride]);
     const double M = block_max(mx, sh);
     const int groups = TILE / nsum;
     const int a = threadIdx.x % nsum, g = threadIdx.x / nsum;
     double acc = 0.0;
-    if (g < groups && M > -INFINITY) {
+    if (buf) {
+        const int ch = buf_len / stride;
+        for (int t0 = 0; t0 < ntiles; t0 += ch) {
+            const int nt = min(ch, ntiles - t0);
+            __syncthreads();
+            const double* src = part + (size_t)t0 * stride;
+            for (int i = threadIdx.x; i < nt * stride; i += TILE) buf[i] = src[i];
+            __syncthreads();
+            // the tile max slot becomes the tile's scale factor
+            for (int t = threadIdx.x; t < nt; t += TILE) {
+                const double mt = buf[t * stride];
+                buf[t * stride] = (mt > -INFINITY && M > -INFINITY) ? exp(mt - M) : 0.0;
+            }
+            __syncthreads();
+            if (g < groups) {
+                for (int t = g; t < nt; t += groups) {
+                    const double sc = buf[t * stride];
+                    acc += (a == sq ? sc * sc : sc) * buf[t * stride + 1 + a];
+                }
+            }
+        }
+    } else if (g < groups && M > -INFINITY) {
         for (int t = g; t < ntiles; t += groups) {
             const double mt = part[(size_t)t * stride];
             if (mt > -INFINITY) {
@@ -249,12 +307,14 @@ __device__ int chol_jitter(const double* C, double* L, int p)
 // Last tile of a moment pass: combine partials, form mean / covariance /
 // ESS / state mean, factor, and commit (flip = switch to the new buffers and
 // advance the step counter).
-__device__ void finalize_moments(const FilterDesc& fd, FilterState& st, bool flip, double* sh)
+constexpr int STAGE_LEN = 8192;   // doubles of LDS staging for the tile combine
+
+__device__ void finalize_moments(const FilterDesc& fd, FilterState& st, bool flip, double* sh, double* buf)
 {
     __shared__ double tot[NACC_MAX];
     __shared__ double mean[PMAX], dm[PMAX], Cm[PMAX * PMAX], Lm[PMAX * PMAX];
     const int p = fd.p, d = fd.d;
-    combine_tiles(fd.part2, fd.nacc, fd.ntiles, fd.nacc - 1, tot, sh, 1);
+    combine_tiles(fd.part2, fd.nacc, fd.ntiles, fd.nacc - 1, tot, sh, 1, buf, STAGE_LEN);
     if (threadIdx.x == 0) {
         const double s0 = tot[0], s00 = tot[1];
         if (!(s0 > 0.0) || !isfinite(s0)) {
@@ -294,75 +354,45 @@ __device__ void finalize_moments(const FilterDesc& fd, FilterState& st, bool fli
 }
 
 // ---------------------------------------------------------------------------
-// common item decode
+// common item decode and step validity
 // ---------------------------------------------------------------------------
 struct Item {
-    int slot, tile;
+    int b, slot, tile;
 };
+// items, batch entries and slots are uniform over the workgroup; saying so
+// lets the compiler use scalar loads for every descriptor field
+__device__ inline int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
 __device__ inline Item decode(uint32_t it, const StepRec* recs)
 {
     Item r;
-    r.slot = recs[it >> 16].slot;
+    it = (uint32_t)uniform((int)it);
+    r.b = (int)(it >> 16);
+    r.slot = uniform(recs[r.b].slot);
     r.tile = (int)(it & 0xFFFFu);
     return r;
 }
 
-// status broadcast from one lane: the whole block takes the same branch
-__device__ inline int block_status(const FilterState& st, int* sh)
-{
-    __syncthreads();
-    if (threadIdx.x == 0) *sh = st.status;
-    __syncthreads();
-    return *sh;
-}
+// The step of batch entry b may run: its observation time is after the
+// filter's current time (checked again, identically, by every kernel; the
+// final kernel reports PF_EORDER).
+__device__ inline bool step_valid(const StepRec& r, const FilterState& st) { return r.t_next > st.t; }
 
 // ---------------------------------------------------------------------------
-// begin / end of a step
-// ---------------------------------------------------------------------------
-__global__ void k_begin(const StepRec* recs, int count, const FilterDesc* descs, FilterState* states)
-{
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= count) return;
-    const StepRec& r = recs[b];
-    const FilterDesc& fd = descs[r.slot];
-    FilterState& st = states[r.slot];
-    st.seq = r.seq;
-    st.t_next = r.t_next;
-    for (int i = 0; i < MMAX; ++i) { st.y[i] = r.y[i]; st.sigma[i] = r.sigma[i]; }
-    st.step = st.j + 1;
-    if (!(r.t_next > st.t)) {
-        st.status = ST_EORDER;
-        return;
-    }
-    st.h = (r.t_next - st.t) / fd.substeps;
-    st.status = ST_OK;
-}
-
-__global__ void k_end(const StepRec* recs, int count, FilterState* states)
-{
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= count) return;
-    const StepRec& r = recs[b];
-    FilterState& st = states[r.slot];
-    st.ring[r.seq % RING] = st.status;
-}
-
-// ---------------------------------------------------------------------------
-// step 1: prior draw and initial moments
+// step 1: prior draw and initial moment partials
 // ---------------------------------------------------------------------------
 template <class R>
 __global__ __launch_bounds__(TILE) void k_init(int slot, const FilterDesc* descs, FilterState* states)
 {
     __shared__ double sh[TILE];
-    __shared__ int flag;
     const FilterDesc& fd = descs[slot];
-    FilterState& st = states[slot];
     for (int tile = blockIdx.x; tile < fd.ntiles; tile += gridDim.x) {
         const int n = tile * TILE + threadIdx.x;
         const bool valid = n < fd.n;
         double th[PMAX];
         R xs[DMAX];
         for (int i = 0; i < PMAX; ++i) th[i] = 0.0;
+        for (int i = 0; i < DMAX; ++i) xs[i] = R(0);
         if (valid) {
             double z[PMAX];
             normals<PMAX>(fd.seed, 0, (uint64_t)n, PUR_PRIOR, z);
@@ -376,17 +406,19 @@ __global__ __launch_bounds__(TILE) void k_init(int slot, const FilterDesc* descs
                 x[(size_t)i * fd.npad + n] = xs[i];
             }
             fd.logw[0][n] = -log((double)fd.n);
-        } else {
-            for (int i = 0; i < DMAX; ++i) xs[i] = R(0);
         }
         tile_moments<R, PMAX, DMAX>(-log((double)fd.n), valid, th, xs, fd.prior_mean, fd.p, fd.d,
-                        fd.part2 + (size_t)tile * fd.nacc, sh);
-        if (last_tile(&fd.done[3], fd.ntiles, &flag)) {
-            if (threadIdx.x < PMAX) st.theta_bar[threadIdx.x] = fd.prior_mean[threadIdx.x];
-            __syncthreads();
-            finalize_moments(fd, st, false, sh);
-        }
+                                    fd.part2 + (size_t)tile * fd.nacc, sh);
     }
+}
+
+// one workgroup: moments of the prior draw (the shift is the prior mean, which
+// the host stored as theta_bar)
+__global__ __launch_bounds__(TILE) void k_init_moments(int slot, const FilterDesc* descs, FilterState* states)
+{
+    __shared__ double sh[TILE];
+    __shared__ double buf[STAGE_LEN];
+    finalize_moments(descs[slot], states[slot], false, sh, buf);
 }
 
 // ---------------------------------------------------------------------------
@@ -399,12 +431,13 @@ __global__ __launch_bounds__(TILE) void k_predict(const uint32_t* items, int n_i
     constexpr int D = Model::D, P = Model::P;
     __shared__ double sh[TILE];
     __shared__ unsigned long long shu[NWAVE];
-    __shared__ int flag;
     for (int itx = blockIdx.x; itx < n_items; itx += gridDim.x) {
         const Item itm = decode(items[itx], recs);
+        const StepRec& rec = recs[itm.b];
         const FilterDesc& fd = descs[itm.slot];
         FilterState& st = states[itm.slot];
-        if (block_status(st, &flag) != ST_OK) continue;
+        if (!step_valid(rec, st)) continue;
+        const double h = (rec.t_next - st.t) / fd.substeps;
         const int n = itm.tile * TILE + threadIdx.x;
         const bool valid = n < fd.n;
         const int cur = st.cur;
@@ -423,9 +456,9 @@ __global__ __launch_bounds__(TILE) void k_predict(const uint32_t* items, int n_i
             Model md;
             md.set_params(m, fd);
             const R* fl = sizeof(R) == 4 ? (const R*)fd.floor_f : (const R*)fd.floor_;
-            integrate<Model, R, KORD, false>(md, x, nullptr, st.h, fd.substeps, (R)fd.rtol, fl,
-                                             fd.kmax, iters, fails);
-            const double lb = loglik<R>(x, fd.obs, st.y, st.sigma, fd.m);
+            integrate<Model, R, KORD, false>(md, x, nullptr, h, fd.substeps, (R)fd.rtol, fl, fd.kmax,
+                                             iters, fails);
+            const double lb = loglik<R>(x, fd.obs, rec.y, rec.sigma, fd.m);
             lg = fd.logw[cur][n] + lb;
             if (!(lg > -INFINITY)) lg = -INFINITY;   // NaN -> zero weight
             fd.lbar[n] = lb;
@@ -442,18 +475,6 @@ __global__ __launch_bounds__(TILE) void k_predict(const uint32_t* items, int n_i
             atomicAdd(&st.newton_pred, it_sum);
             if (fl_sum) atomicAdd(&st.newton_fails, fl_sum);
         }
-        if (last_tile(&fd.done[0], fd.ntiles, &flag)) {
-            double tot[1];
-            __shared__ double tsh[1];
-            const double M = combine_tiles(fd.part1, 2, fd.ntiles, 1, tsh, sh);
-            tot[0] = tsh[0];
-            if (threadIdx.x == 0) {
-                st.lse_max = M;
-                st.lse_sum = tot[0];
-                if (!(M > -INFINITY) || !(tot[0] > 0.0) || !isfinite(M)) st.status = ST_EDEGENERATE;
-            }
-            __syncthreads();
-        }
     }
 }
 
@@ -463,54 +484,31 @@ __global__ __launch_bounds__(TILE) void k_predict(const uint32_t* items, int n_i
 __global__ __launch_bounds__(TILE) void k_count(const uint32_t* items, int n_items, const StepRec* recs,
                                                 const FilterDesc* descs, FilterState* states)
 {
+    __shared__ double sh[TILE];
+    __shared__ double tot[1];
     __shared__ unsigned long long shu[NWAVE];
-    __shared__ int flag;
     for (int itx = blockIdx.x; itx < n_items; itx += gridDim.x) {
         const Item itm = decode(items[itx], recs);
         const FilterDesc& fd = descs[itm.slot];
-        FilterState& st = states[itm.slot];
-        if (block_status(st, &flag) != ST_OK) continue;
+        const FilterState& st = states[itm.slot];
+        if (!fd.g_direct && !step_valid(recs[itm.b], st)) continue;
+        double M = 0.0, S = 1.0;
+        if (!fd.g_direct) {
+            // the filter's first-stage log-sum-exp, from the tile partials
+            M = combine_tiles(fd.part1, 2, fd.ntiles, 1, tot, sh);
+            S = tot[0];
+        }
+        const bool ok = fd.g_direct || (M > -INFINITY && isfinite(M) && S > 0.0);
         const int n = itm.tile * TILE + threadIdx.x;
         unsigned long long q = 0;
         if (n < fd.n) {
             const double l = fd.lg[n];
-            const double g = fd.g_direct ? l : (l > -INFINITY ? exp(l - st.lse_max) / st.lse_sum : 0.0);
+            const double g = fd.g_direct ? l : (ok && l > -INFINITY ? exp(l - M) / S : 0.0);
             if (g > 0.0) q = (unsigned long long)floor(ldexp(g, fd.shift));
             fd.q[n] = q;
         }
         const unsigned long long ts = block_sum_u64(q, shu);
         if (threadIdx.x == 0) fd.tsum[itm.tile] = ts;
-        if (last_tile(&fd.done[1], fd.ntiles, &flag)) {
-            // exclusive scan of the tile sums, in chunks of TILE
-            unsigned long long carry = 0;
-            for (int base = 0; base < fd.ntiles; base += TILE) {
-                const int t = base + threadIdx.x;
-                const unsigned long long v = t < fd.ntiles ? fd.tsum[t] : 0ull;
-                unsigned long long ex;
-                const unsigned long long tot = block_exscan_u64(v, ex, shu);
-                if (t < fd.ntiles) fd.tsum[t] = carry + ex;
-                carry += tot;
-                __syncthreads();
-            }
-            if (threadIdx.x == 0) {
-                const unsigned long long T = carry;
-                if (T == 0) {
-                    st.status = ST_EDEGENERATE;
-                } else {
-                    uint64_t r;
-                    if (fd.g_direct) {
-                        r = st.V;
-                    } else {
-                        uint64_t w[4];
-                        Philox::block(st.step, 0, PUR_RESAMPLE, 0, fd.seed, 0, w);
-                        r = w[0];
-                    }
-                    st.T = T;
-                    st.V = __umul64hi(r, T);
-                }
-            }
-            __syncthreads();
-        }
     }
 }
 
@@ -528,19 +526,41 @@ __global__ __launch_bounds__(TILE) void k_scatter(const uint32_t* items, int n_i
                                                   const FilterDesc* descs, FilterState* states)
 {
     __shared__ unsigned long long shu[NWAVE];
-    __shared__ int flag;
     for (int itx = blockIdx.x; itx < n_items; itx += gridDim.x) {
         const Item itm = decode(items[itx], recs);
         const FilterDesc& fd = descs[itm.slot];
         FilterState& st = states[itm.slot];
-        if (block_status(st, &flag) != ST_OK) continue;
+        if (!fd.g_direct && !step_valid(recs[itm.b], st)) continue;
+        // exclusive offset of this tile and total T of the integer weights
+        unsigned long long pre = 0, all = 0;
+        for (int t = threadIdx.x; t < fd.ntiles; t += TILE) {
+            const unsigned long long v = fd.tsum[t];
+            all += v;
+            if (t < itm.tile) pre += v;
+        }
+        pre = block_sum_u64(pre, shu);
+        const unsigned long long T = block_sum_u64(all, shu);
+        uint64_t r;
+        if (fd.g_direct) {
+            r = st.V;   // test mode: the uniform word was stored by the host
+        } else {
+            uint64_t w[4];
+            Philox::block(st.j + 1, 0, PUR_RESAMPLE, 0, fd.seed, 0, w);
+            r = w[0];
+        }
+        const uint64_t V = T ? __umul64hi(r, T) : 0;
+        if (itm.tile == 0 && threadIdx.x == 0) {
+            st.T = T;
+            if (!fd.g_direct) st.V = V;
+        }
+        if (T == 0) continue;
         const int n = itm.tile * TILE + threadIdx.x;
         const unsigned long long q = n < fd.n ? fd.q[n] : 0ull;
         unsigned long long ex;
         block_exscan_u64(q, ex, shu);
         if (q > 0) {
-            const uint64_t N = (uint64_t)fd.n, T = st.T, V = st.V;
-            const uint64_t lo_c = fd.tsum[itm.tile] + ex;
+            const uint64_t N = (uint64_t)fd.n;
+            const uint64_t lo_c = pre + ex;
             const uint64_t lo = first_slot(lo_c, N, T, V);
             const uint64_t hi = first_slot(lo_c + q, N, T, V);
             for (uint64_t i = lo; i < hi; ++i) fd.anc[i] = n;
@@ -549,7 +569,7 @@ __global__ __launch_bounds__(TILE) void k_scatter(const uint32_t* items, int n_i
 }
 
 // ---------------------------------------------------------------------------
-// steps 3(c)-6 per output slot
+// steps 3(c)-5 per output slot
 // ---------------------------------------------------------------------------
 template <class Model, class R, int KORD>
 __global__ __launch_bounds__(TILE) void k_update(const uint32_t* items, int n_items, const StepRec* recs,
@@ -558,12 +578,14 @@ __global__ __launch_bounds__(TILE) void k_update(const uint32_t* items, int n_it
     constexpr int D = Model::D, P = Model::P;
     __shared__ double sh[TILE];
     __shared__ unsigned long long shu[NWAVE];
-    __shared__ int flag;
     for (int itx = blockIdx.x; itx < n_items; itx += gridDim.x) {
         const Item itm = decode(items[itx], recs);
+        const StepRec& rec = recs[itm.b];
         const FilterDesc& fd = descs[itm.slot];
         FilterState& st = states[itm.slot];
-        if (block_status(st, &flag) != ST_OK) continue;
+        if (!step_valid(rec, st) || st.T == 0) continue;
+        const double h = (rec.t_next - st.t) / fd.substeps;
+        const uint64_t step = st.j + 1;
         const int n = itm.tile * TILE + threadIdx.x;
         const bool valid = n < fd.n;
         const int cur = st.cur, nxt = cur ^ 1;
@@ -592,14 +614,14 @@ __global__ __launch_bounds__(TILE) void k_update(const uint32_t* items, int n_it
             for (int i = 0; i < P; ++i)
                 m[i] = a * fd.theta[cur][(size_t)i * fd.npad + k] + (1.0 - a) * st.theta_bar[i];
             const double lb = fd.lbar[k];
-            // 4(a): theta_{j+1} = m + s L z
-            double z[P];
-            normals<P>(fd.seed, st.step, (uint64_t)n, PUR_PROLIF, z);
+            // 4(a): theta_{j+1} = m + s L z (normals in the propagation precision)
+            R z[P];
+            normals<P, R>(fd.seed, step, (uint64_t)n, PUR_PROLIF, z);
 #pragma unroll
             for (int i = 0; i < P; ++i) {
                 double v = 0.0;
 #pragma unroll
-                for (int c = 0; c <= i; ++c) v += st.L[i * fd.p + c] * z[c];
+                for (int c = 0; c <= i; ++c) v += st.L[i * fd.p + c] * (double)z[c];
                 th[i] = m[i] + fd.s * v;
             }
             // 4(b)-(d): Psi with the local-error variance, then the innovation
@@ -610,20 +632,19 @@ __global__ __launch_bounds__(TILE) void k_update(const uint32_t* items, int n_it
 #pragma unroll
             for (int i = 0; i < D; ++i) xw[i] = x[i];
             const R* fl = sizeof(R) == 4 ? (const R*)fd.floor_f : (const R*)fd.floor_;
-            integrate<Model, R, KORD, true>(md, xw, gam, st.h, fd.substeps, (R)fd.rtol, fl, fd.kmax,
-                                            iters, fails);
-            double zi[D];
-            normals<D>(fd.seed, st.step, (uint64_t)n, PUR_INNOV, zi);
+            integrate<Model, R, KORD, true>(md, xw, gam, h, fd.substeps, (R)fd.rtol, fl, fd.kmax, iters, fails);
+            R zi[D];
+            normals<D, R>(fd.seed, step, (uint64_t)n, PUR_INNOV, zi);
             R* xo = (R*)fd.x[nxt];
 #pragma unroll
             for (int i = 0; i < D; ++i) {
-                x[i] = (R)((double)xw[i] + sqrt((double)gam[i]) * zi[i]);
+                x[i] = xw[i] + sqrt(gam[i]) * zi[i];
                 xo[(size_t)i * fd.npad + n] = x[i];
             }
 #pragma unroll
             for (int i = 0; i < P; ++i) fd.theta[nxt][(size_t)i * fd.npad + n] = th[i];
             // 5: w = pi(y | x_{j+1}) / pi(y | xbar)
-            l = loglik<R>(x, fd.obs, st.y, st.sigma, fd.m) - lb;
+            l = loglik<R>(x, fd.obs, rec.y, rec.sigma, fd.m) - lb;
             if (!(l > -INFINITY) || bad) { l = -INFINITY; nonf = 1; }
             fd.logw[nxt][n] = l;
         }
@@ -635,10 +656,47 @@ __global__ __launch_bounds__(TILE) void k_update(const uint32_t* items, int n_it
             if (fl_sum) atomicAdd(&st.newton_fails, fl_sum);
             if (nf_sum) atomicAdd(&st.nonfinite, nf_sum);
         }
-        // 6: tile moments with shift theta_bar_j
+        // 6 (partials): tile moments with shift theta_bar_j
         tile_moments<R, P, D>(l, valid, th, x, st.theta_bar, P, D,
-                        fd.part2 + (size_t)itm.tile * fd.nacc, sh);
-        if (last_tile(&fd.done[2], fd.ntiles, &flag)) finalize_moments(fd, st, true, sh);
+                              fd.part2 + (size_t)itm.tile * fd.nacc, sh);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// step 6: one workgroup per batch entry -- mean, covariance, ESS, Cholesky,
+// commit, and the step's status by ticket (device ring and host-mapped ring)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(TILE) void k_moments(const StepRec* recs, int count, const FilterDesc* descs,
+                                                  FilterState* states, int32_t* host_ring)
+{
+    __shared__ double sh[TILE];
+    __shared__ double buf[STAGE_LEN];
+    for (int b = blockIdx.x; b < count; b += gridDim.x) {
+        const StepRec& rec = recs[b];
+        const int slot = uniform(rec.slot);
+        const FilterDesc& fd = descs[slot];
+        FilterState& st = states[slot];
+        int32_t status;
+        if (!step_valid(rec, st)) {
+            status = ST_EORDER;
+        } else if (st.T == 0) {
+            status = ST_EDEGENERATE;
+        } else {
+            if (threadIdx.x == 0) {
+                st.step = st.j + 1;
+                st.t_next = rec.t_next;
+            }
+            __syncthreads();
+            finalize_moments(fd, st, true, sh, buf);
+            status = st.status;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            st.status = status;
+            st.ring[rec.seq % RING] = status;
+            host_ring[(size_t)slot * RING + rec.seq % RING] = status;
+        }
+        __syncthreads();
     }
 }
 

@@ -163,20 +163,6 @@ struct pf_context {
 
 static pf_status prof_collect(pf_context* ctx);
 
-// k_end that also mirrors the status to host-mapped memory
-namespace pf {
-__global__ void k_end_host(const StepRec* recs, int count, FilterState* states, int32_t* host_ring)
-{
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= count) return;
-    const StepRec& r = recs[b];
-    FilterState& st = states[r.slot];
-    st.ring[r.seq % RING] = st.status;
-    host_ring[(size_t)r.slot * RING + r.seq % RING] = st.status;
-    __threadfence_system();
-}
-}  // namespace pf
-
 // ---------------------------------------------------------------------------
 // kernel dispatch by (model, precision, order)
 // ---------------------------------------------------------------------------
@@ -289,7 +275,7 @@ static void fill_static(FilterDesc& d, const pf_config* c)
 
 // bytes and offsets of one filter's buffers inside its pool block
 struct Layout {
-    uint64_t x[2], th[2], lw[2], lbar, lg, q, anc, part1, tsum, part2, done, total;
+    uint64_t x[2], th[2], lw[2], lbar, lg, q, anc, part1, tsum, part2, total;
 };
 static Layout layout_of(const FilterDesc& d)
 {
@@ -310,7 +296,6 @@ static Layout layout_of(const FilterDesc& d)
     L.part1 = take((uint64_t)d.ntiles * 2 * 8);
     L.tsum = take((uint64_t)d.ntiles * 8);
     L.part2 = take((uint64_t)d.ntiles * d.nacc * 8);
-    L.done = take(4 * 4);
     L.total = o;
     return L;
 }
@@ -330,7 +315,6 @@ static void bind_buffers(FilterDesc& d, char* base, const Layout& L)
     d.part1 = (double*)(base + L.part1);
     d.tsum = (uint64_t*)(base + L.tsum);
     d.part2 = (double*)(base + L.part2);
-    d.done = (uint32_t*)(base + L.done);
 }
 
 // ---------------------------------------------------------------------------
@@ -467,7 +451,6 @@ extern "C" pf_status pf_create(pf_context* ctx, const pf_config* cfg, pf_filter*
     };
     if (hipMemcpyAsync(ctx->d_desc + f->slot, &f->desc, sizeof(FilterDesc), hipMemcpyHostToDevice, ctx->stream) != hipSuccess ||
         hipMemcpyAsync(ctx->d_state + f->slot, &st, sizeof(FilterState), hipMemcpyHostToDevice, ctx->stream) != hipSuccess ||
-        hipMemsetAsync(f->desc.done, 0, 16, ctx->stream) != hipSuccess ||
         hipMemsetAsync(f->desc.anc, 0, sizeof(int32_t) * (size_t)f->desc.npad, ctx->stream) != hipSuccess)
         return cleanup(fail(PF_EDEVICE, "upload of filter descriptor failed"));
     const unsigned grid = grid_for(ctx, f->desc.ntiles);
@@ -475,6 +458,7 @@ extern "C" pf_status pf_create(pf_context* ctx, const pf_config* cfg, pf_filter*
         hipLaunchKernelGGL(k_init<float>, dim3(grid), dim3(TILE), 0, ctx->stream, f->slot, ctx->d_desc, ctx->d_state);
     else
         hipLaunchKernelGGL(k_init<double>, dim3(grid), dim3(TILE), 0, ctx->stream, f->slot, ctx->d_desc, ctx->d_state);
+    hipLaunchKernelGGL(k_init_moments, dim3(1), dim3(TILE), 0, ctx->stream, f->slot, ctx->d_desc, ctx->d_state);
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(ctx->stream) != hipSuccess)
         return cleanup(fail(PF_EDEVICE, "initialisation kernel failed"));
     int32_t status = 0;
@@ -600,18 +584,19 @@ static pf_status submit(pf_context* ctx, uint32_t count, pf_filter* const* fs, c
         off += (int)kv.second.size();
     }
     const int n_all = off;
+    // one copy: [recs | items]
+    const size_t rec_bytes = (sizeof(StepRec) * count + 255) & ~size_t(255);
+    std::memmove(sg.host + rec_bytes, items, sizeof(uint32_t) * n_all);
     StepRec* d_recs = (StepRec*)sg.dev;
-    uint32_t* d_items = (uint32_t*)(sg.dev + sizeof(StepRec) * MAX_BATCH);
-    HIP_TRY(hipMemcpyAsync(d_recs, recs, sizeof(StepRec) * count, hipMemcpyHostToDevice, ctx->stream));
-    HIP_TRY(hipMemcpyAsync(d_items, items, sizeof(uint32_t) * n_all, hipMemcpyHostToDevice, ctx->stream));
+    uint32_t* d_items = (uint32_t*)(sg.dev + rec_bytes);
+    HIP_TRY(hipMemcpyAsync(sg.dev, sg.host, rec_bytes + sizeof(uint32_t) * n_all, hipMemcpyHostToDevice,
+                           ctx->stream));
 
-    const unsigned gb = (count + 255) / 256;
     ProfRec pr{};
     if (ctx->profiling) {
         for (int i = 0; i < 5; ++i) pr.ev[i] = prof_event(ctx);
         HIP_TRY(hipEventRecord(pr.ev[0], ctx->stream));
     }
-    hipLaunchKernelGGL(k_begin, dim3(gb), dim3(256), 0, ctx->stream, d_recs, (int)count, ctx->d_desc, ctx->d_state);
     for (const Range& r : ranges) {
         const int model = r.cls / 8 + 1, prec = (r.cls % 8) / 4, order = r.cls % 4;
         hipLaunchKernelGGL(predict_kernel(model, prec, order), dim3(grid_for(ctx, r.cnt)), dim3(TILE), 0,
@@ -629,8 +614,8 @@ static pf_status submit(pf_context* ctx, uint32_t count, pf_filter* const* fs, c
                            ctx->stream, d_items + r.off, r.cnt, d_recs, ctx->d_desc, ctx->d_state);
     }
     if (ctx->profiling) HIP_TRY(hipEventRecord(pr.ev[3], ctx->stream));
-    hipLaunchKernelGGL(k_end_host, dim3(gb), dim3(256), 0, ctx->stream, d_recs, (int)count, ctx->d_state,
-                       ctx->d_ring);
+    hipLaunchKernelGGL(k_moments, dim3(std::min<uint32_t>(count, (uint32_t)ctx->grid_cap)), dim3(TILE), 0,
+                       ctx->stream, d_recs, (int)count, ctx->d_desc, ctx->d_state, ctx->d_ring);
     HIP_TRY(hipGetLastError());
     if (ctx->profiling) {
         HIP_TRY(hipEventRecord(pr.ev[4], ctx->stream));
@@ -858,7 +843,7 @@ extern "C" pf_status pf_test_resample(uint64_t n, const double* g, uint64_t r, i
     d.g_direct = 1;
     // scratch: desc, state, rec, items, q, tsum, done
     const size_t nb = sizeof(FilterDesc) + sizeof(FilterState) + sizeof(StepRec) + 4 * (size_t)d.ntiles +
-                      8 * (size_t)d.npad + 8 * (size_t)d.ntiles + 64 + 6 * 256;
+                      8 * (size_t)d.npad + 8 * (size_t)d.ntiles + 6 * 256;
     char* buf = nullptr;
     HIP_TRY(hipMalloc(&buf, nb));
     size_t o = 0;
@@ -869,7 +854,6 @@ extern "C" pf_status pf_test_resample(uint64_t n, const double* g, uint64_t r, i
     uint32_t* di = (uint32_t*)take(4 * (size_t)d.ntiles);
     d.q = (uint64_t*)take(8 * (size_t)d.npad);
     d.tsum = (uint64_t*)take(8 * (size_t)d.ntiles);
-    d.done = (uint32_t*)take(64);
     d.lg = const_cast<double*>(g);
     d.anc = anc;
     FilterState hs;
@@ -885,7 +869,6 @@ extern "C" pf_status pf_test_resample(uint64_t n, const double* g, uint64_t r, i
     if (e == hipSuccess) e = hipMemcpyAsync(ds, &hs, sizeof(hs), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemcpyAsync(dr, &rec, sizeof(rec), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemcpyAsync(di, items.data(), 4 * items.size(), hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipMemsetAsync(d.done, 0, 64, st);
     if (e == hipSuccess) {
         const unsigned grid = (unsigned)std::min(d.ntiles, 2048);
         hipLaunchKernelGGL(k_count, dim3(grid), dim3(TILE), 0, st, di, d.ntiles, dr, dd, ds);
@@ -896,7 +879,7 @@ extern "C" pf_status pf_test_resample(uint64_t n, const double* g, uint64_t r, i
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     (void)hipFree(buf);
     if (e != hipSuccess) return fail(PF_EDEVICE, std::string("resample: ") + hipGetErrorString(e));
-    if (hs.status != ST_OK) return fail((pf_status)hs.status, "all scaled weights are zero");
+    if (hs.T == 0) return fail(PF_EDEGENERATE, "all scaled weights are zero");
     return PF_OK;
 }
 

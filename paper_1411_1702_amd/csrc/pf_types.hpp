@@ -54,7 +54,6 @@ struct FilterDesc {
     double* part1;                      // [ntiles][2] (max, sum exp)
     uint64_t* tsum;                     // [ntiles] integer weight per tile (then offsets)
     double* part2;                      // [ntiles][nacc] moment partials
-    uint32_t* done;                     // [4] last-tile counters
 };
 
 // Dynamic state of one filter (device resident, updated by the kernels).
@@ -69,11 +68,8 @@ struct FilterState {
     int32_t cur;                        // current ping-pong buffer
     int32_t status;                     // status of the step in progress / last step
     // step in progress
-    double t_next, h;
-    double y[MMAX], sigma[MMAX];
+    double t_next;
     uint64_t step;                      // j + 1
-    uint64_t seq;                       // host ticket
-    double lse_max, lse_sum;            // first-stage log-sum-exp
     uint64_t T, V;                      // resampling total and offset
     unsigned long long newton_pred, newton_upd, newton_fails, nonfinite, jitters;
     int32_t ring[RING];                 // status by ticket % RING

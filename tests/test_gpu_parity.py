@@ -212,9 +212,10 @@ def test_init_matches_oracle(pf, ctx, oracle, prec):
 
 
 def _innovation_scale(oracle, prob, x_in, t_in, anc, theta_new, step):
-    """Per slot and component, the largest term of x_{j+1} = Psi(x_j) + v:
-    max(|Psi|, sqrt(Gamma)|z|).  A state formed by cancellation of the two is
-    judged against the terms that formed it."""
+    """Per slot and component, the scale of the terms of x_{j+1} = Psi(x_j) + v:
+    max(|Psi|, sqrt(Gamma) max(|z|, 1)).  A state formed by cancellation of the
+    two is judged against the terms that formed it, and the innovation against
+    its own standard deviation (an FP32 normal is accurate to ~1e-6 absolute)."""
     h = (prob.times[step - 1] - t_in) / prob.substeps
     out = np.zeros((len(anc), prob.d))
     for n, k in enumerate(anc):
@@ -223,7 +224,7 @@ def _innovation_scale(oracle, prob, x_in, t_in, anc, theta_new, step):
                                 floor=prob.state_floor, mc=prob.model_consts,
                                 rates_fixed=prob.rates_fixed)
         z = oracle.normals(prob.seed, step, n, oracle.PUR_INNOV, prob.d)
-        out[n] = np.maximum(np.abs(xt), np.sqrt(gam) * np.abs(z))
+        out[n] = np.maximum(np.abs(xt), np.sqrt(gam) * np.maximum(np.abs(z), 1.0))
     return out
 
 
@@ -263,7 +264,9 @@ def test_step_parity_robertson(pf, ctx, oracle, prec, j0):
         assert same.mean() > 0.98
     err = np.abs(x[same] - ora.x[same]) / scale[same]
     assert err.max() < TOL[prec], err.max()
-    assert np.allclose(th[same], ora.theta[same], rtol=1e-12 if prec == 0 else 1e-9, atol=1e-12)
+    # FP32 propagation draws its normals in FP32 (relative accuracy ~1e-7)
+    assert np.allclose(th[same], ora.theta[same], rtol=1e-12 if prec == 0 else 0.0,
+                       atol=1e-12 if prec == 0 else 1e-7)
     if prec == 0:
         fin = np.isfinite(ora.logw)
         assert np.allclose(lw[fin], ora.logw[fin], rtol=0, atol=1e-8)
