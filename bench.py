@@ -49,20 +49,8 @@ def _percentile(v, q):
     return float(np.percentile(np.asarray(v), q)) if len(v) else None
 
 
-def time_path(pf, ctx, prob, prec, steps, warmup):
-    """Warm up on one filter, then time `steps` observation steps of a fresh one."""
-    if warmup:
-        fw = pf.Filter(ctx, pf.Config(prob, prec))
-        tk = [fw.assimilate_async(prob.times[j], prob.y[j], prob.sigma[j]) for j in range(warmup)]
-        for t in tk:
-            fw.wait(t)
-        fw.close()
-    f = pf.Filter(ctx, pf.Config(prob, prec))
-    s0 = f.stats()
-    ctx.profile(True)
-    import torch
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
+def run_steps(pf, f, prob, steps):
+    """Submit `steps` observation steps asynchronously and wait for them all."""
     tickets = []
     for j in range(steps):
         tickets.append(f.assimilate_async(prob.times[j], prob.y[j], prob.sigma[j]))
@@ -74,14 +62,36 @@ def time_path(pf, ctx, prob, prec, steps, warmup):
         st = f.wait(t)
         if st != pf.PF_OK:
             raise RuntimeError(f"step failed: {st}")
+
+
+def time_path(pf, ctx, prob, prec, steps, warmup):
+    """Warm up on one filter, time `steps` observation steps of a fresh one
+    (captured step graphs, no instrumentation), then repeat the same steps on
+    another fresh filter with HIP events between the kernel groups (direct
+    launches) for the per-kernel durations."""
+    import torch
+    if warmup:
+        fw = pf.Filter(ctx, pf.Config(prob, prec))
+        run_steps(pf, fw, prob, warmup)
+        fw.close()
+    f = pf.Filter(ctx, pf.Config(prob, prec))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run_steps(pf, f, prob, steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    post = f.posterior()
+    f.close()
+    # instrumented pass
+    f = pf.Filter(ctx, pf.Config(prob, prec))
+    s0 = f.stats()
+    ctx.profile(True)
+    run_steps(pf, f, prob, steps)
     times = {k: ctx.kernel_time(w) for k, w in
              (("step", pf.PF_TIME_STEP), ("predict", pf.PF_TIME_PREDICT),
               ("resample", pf.PF_TIME_RESAMPLE), ("update", pf.PF_TIME_UPDATE))}
     ctx.profile(False)
     s1 = f.stats()
-    post = f.posterior()
     f.close()
     n = prob.n_particles
     fl = FLOPS[prob.model]

@@ -174,7 +174,7 @@ __device__ inline unsigned long long block_exscan_u64(unsigned long long v, unsi
 // With an LDS staging buffer (buf, buf_len doubles), tiles are read in
 // coalesced chunks; the order of the sums depends only on ntiles, stride and
 // buf_len.  Returns M.
-__device__ double combine_tiles(const double* part, int stride, int ntiles, int nsum, double* out,
+__device__ __forceinline__ double combine_tiles(const double* part, int stride, int ntiles, int nsum, double* out,
                                 double* sh /* >= TILE doubles */, int sq = -1, double* buf = nullptr,
                                 int buf_len = 0)
 {
@@ -190,7 +190,22 @@ __device__ double combine_tiles(const double* part, int stride, int ntiles, int 
             const int nt = min(ch, ntiles - t0);
             __syncthreads();
             const double* src = part + (size_t)t0 * stride;
-            for (int i = threadIdx.x; i < nt * stride; i += TILE) buf[i] = src[i];
+            const int cnt = nt * stride;
+            // issue all of this thread's loads before the first LDS store
+            constexpr int PER = 32;
+            for (int base = 0; base < cnt; base += PER * TILE) {
+                double r[PER];
+#pragma unroll
+                for (int k = 0; k < PER; ++k) {
+                    const int i = base + k * TILE + (int)threadIdx.x;
+                    r[k] = i < cnt ? src[i] : 0.0;
+                }
+#pragma unroll
+                for (int k = 0; k < PER; ++k) {
+                    const int i = base + k * TILE + (int)threadIdx.x;
+                    if (i < cnt) buf[i] = r[k];
+                }
+            }
             __syncthreads();
             // the tile max slot becomes the tile's scale factor
             for (int t = threadIdx.x; t < nt; t += TILE) {
@@ -275,80 +290,97 @@ __device__ void tile_moments(double l, bool valid, const double* th, const R* x,
     __syncthreads();
 }
 
-// Cholesky C = L L^T with the jitter rule (C + delta I, delta = 1e-10 tr/p,
-// then 10x, at most five times).  Returns the jitter count or -1.
-__device__ int chol_jitter(const double* C, double* L, int p)
+// Last step of a moment pass, in one lane with the model's P and D known at
+// compile time (so every array lives in registers): mean, covariance,
+// ESS, state mean, and the Cholesky factor with the jitter rule (retry with
+// C + delta I, delta = 1e-10 tr(C)/p, then 10x larger, at most five times).
+// The factor overwrites a packed lower triangle of C (row i at i(i+1)/2).
+// Commits unless degenerate; `flip` switches to the new ensemble buffers and
+// advances the step counter.
+template <int P, int D>
+__device__ __forceinline__ void moments_tail(const double* tot, FilterState& st, bool flip)
 {
+    constexpr int NT = P * (P + 1) / 2;
+    const double s0 = tot[0], s00 = tot[1];
+    if (!(s0 > 0.0) || !isfinite(s0)) {
+        st.status = ST_EDEGENERATE;
+        return;
+    }
+    const double inv = 1.0 / s0;
+    double dm[P];
+#pragma unroll
+    for (int i = 0; i < P; ++i) dm[i] = tot[2 + i] * inv;
+    // tot holds the upper triangle row by row: entry (i, j), j >= i, sits at
+    // 2 + P + i*P - i*(i-1)/2 + (j - i)
+    auto cov = [&](int i, int j) -> double {
+        const int r = i < j ? i : j, c = i < j ? j : i;
+        return tot[2 + P + r * P - r * (r - 1) / 2 + (c - r)] * inv - dm[i] * dm[j];
+    };
     double tr = 0.0;
-    for (int i = 0; i < p; ++i) tr += C[i * p + i];
+#pragma unroll
+    for (int i = 0; i < P; ++i) tr += cov(i, i);
+    double L[NT];
     double delta = 0.0;
-    for (int attempt = 0; attempt <= 5; ++attempt) {
-        if (attempt == 1) delta = 1e-10 * tr / p;
+    int jit = -1;
+    for (int attempt = 0; attempt <= 5 && jit < 0; ++attempt) {
+        if (attempt == 1) delta = 1e-10 * tr / P;
         else if (attempt > 1) delta *= 10.0;
         bool ok = true;
-        for (int i = 0; i < p * p; ++i) L[i] = 0.0;
-        for (int j = 0; j < p && ok; ++j) {
-            double s = C[j * p + j] + delta;
-            for (int k = 0; k < j; ++k) s -= L[j * p + k] * L[j * p + k];
-            if (!(s > 0.0) || !isfinite(s)) { ok = false; break; }
-            const double ljj = sqrt(s);
-            L[j * p + j] = ljj;
-            for (int i = j + 1; i < p; ++i) {
-                double t = C[i * p + j];
-                for (int k = 0; k < j; ++k) t -= L[i * p + k] * L[j * p + k];
-                L[i * p + j] = t / ljj;
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+            double sdiag = cov(j, j) + delta;
+#pragma unroll
+            for (int k = 0; k < j; ++k) sdiag -= L[j * (j + 1) / 2 + k] * L[j * (j + 1) / 2 + k];
+            ok = ok && sdiag > 0.0 && isfinite(sdiag);
+            const double ljj = sqrt(ok ? sdiag : 1.0);
+            const double rl = 1.0 / ljj;
+            L[j * (j + 1) / 2 + j] = ljj;
+#pragma unroll
+            for (int i = j + 1; i < P; ++i) {
+                double t = cov(i, j);
+#pragma unroll
+                for (int k = 0; k < j; ++k) t -= L[i * (i + 1) / 2 + k] * L[j * (j + 1) / 2 + k];
+                L[i * (i + 1) / 2 + j] = t * rl;
             }
         }
-        if (ok) return attempt;
+        if (ok) jit = attempt;
     }
-    return -1;
+    if (jit < 0) {
+        st.status = ST_EDEGENERATE;
+        return;
+    }
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+            st.C[i * P + j] = cov(i, j);
+            st.L[i * P + j] = j <= i ? L[i * (i + 1) / 2 + j] : 0.0;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < P; ++i) st.theta_bar[i] += dm[i];
+#pragma unroll
+    for (int i = 0; i < D; ++i) st.state_mean[i] = tot[2 + P + NT + i] * inv;
+    st.ess = s0 * s0 / s00;
+    st.jitters += (unsigned long long)jit;
+    if (flip) {
+        st.cur ^= 1;
+        st.j = st.step;
+        st.t = st.t_next;
+    }
+    st.status = ST_OK;
 }
 
-// Last tile of a moment pass: combine partials, form mean / covariance /
-// ESS / state mean, factor, and commit (flip = switch to the new buffers and
-// advance the step counter).
 constexpr int STAGE_LEN = 8192;   // doubles of LDS staging for the tile combine
 
-__device__ void finalize_moments(const FilterDesc& fd, FilterState& st, bool flip, double* sh, double* buf)
+__device__ __forceinline__ void finalize_moments(const FilterDesc& fd, FilterState& st, bool flip, double* sh,
+                                                 double* buf)
 {
     __shared__ double tot[NACC_MAX];
-    __shared__ double mean[PMAX], dm[PMAX], Cm[PMAX * PMAX], Lm[PMAX * PMAX];
-    const int p = fd.p, d = fd.d;
     combine_tiles(fd.part2, fd.nacc, fd.ntiles, fd.nacc - 1, tot, sh, 1, buf, STAGE_LEN);
     if (threadIdx.x == 0) {
-        const double s0 = tot[0], s00 = tot[1];
-        if (!(s0 > 0.0) || !isfinite(s0)) {
-            st.status = ST_EDEGENERATE;
-        } else {
-            const double inv = 1.0 / s0;
-            for (int i = 0; i < p; ++i) {
-                dm[i] = tot[2 + i] * inv;
-                mean[i] = st.theta_bar[i] + dm[i];
-            }
-            int a = 2 + p;
-            for (int i = 0; i < p; ++i)
-                for (int j = i; j < p; ++j, ++a) {
-                    const double v = tot[a] * inv - dm[i] * dm[j];
-                    Cm[i * p + j] = v;
-                    Cm[j * p + i] = v;
-                }
-            const int jit = chol_jitter(Cm, Lm, p);
-            if (jit < 0) {
-                st.status = ST_EDEGENERATE;
-            } else {
-                for (int i = 0; i < p; ++i) st.theta_bar[i] = mean[i];
-                for (int i = 0; i < p * p; ++i) { st.C[i] = Cm[i]; st.L[i] = Lm[i]; }
-                for (int i = 0; i < d; ++i) st.state_mean[i] = tot[a + i] * inv;
-                st.ess = s0 * s0 / s00;
-                st.jitters += (unsigned long long)jit;
-                if (flip) {
-                    st.cur ^= 1;
-                    st.j = st.step;
-                    st.t = st.t_next;
-                }
-                st.status = ST_OK;
-            }
-        }
+        if (fd.p == 3 && fd.d == 3) moments_tail<3, 3>(tot, st, flip);
+        else moments_tail<PMAX, DMAX>(tot, st, flip);
     }
     __syncthreads();
 }
@@ -522,10 +554,18 @@ __device__ inline uint64_t first_slot(uint64_t c, uint64_t N, uint64_t T, uint64
     return f < N ? f : N;
 }
 
+// copies of one particle written by its own lane up to this many; longer
+// runs (a few heavy particles when the weights are very uneven) are written
+// by the whole workgroup
+constexpr uint64_t LONG_RUN = 16;
+
 __global__ __launch_bounds__(TILE) void k_scatter(const uint32_t* items, int n_items, const StepRec* recs,
                                                   const FilterDesc* descs, FilterState* states)
 {
     __shared__ unsigned long long shu[NWAVE];
+    __shared__ int n_long;
+    __shared__ uint32_t run_lo[TILE], run_hi[TILE];
+    __shared__ int run_k[TILE];
     for (int itx = blockIdx.x; itx < n_items; itx += gridDim.x) {
         const Item itm = decode(items[itx], recs);
         const FilterDesc& fd = descs[itm.slot];
@@ -558,13 +598,26 @@ __global__ __launch_bounds__(TILE) void k_scatter(const uint32_t* items, int n_i
         const unsigned long long q = n < fd.n ? fd.q[n] : 0ull;
         unsigned long long ex;
         block_exscan_u64(q, ex, shu);
+        if (threadIdx.x == 0) n_long = 0;
+        __syncthreads();
         if (q > 0) {
             const uint64_t N = (uint64_t)fd.n;
             const uint64_t lo_c = pre + ex;
             const uint64_t lo = first_slot(lo_c, N, T, V);
             const uint64_t hi = first_slot(lo_c + q, N, T, V);
-            for (uint64_t i = lo; i < hi; ++i) fd.anc[i] = n;
+            if (hi - lo <= LONG_RUN) {
+                for (uint64_t i = lo; i < hi; ++i) fd.anc[i] = n;
+            } else {
+                // a heavy particle: the whole workgroup writes its copies below
+                const int e = atomicAdd(&n_long, 1);
+                run_lo[e] = (uint32_t)lo;
+                run_hi[e] = (uint32_t)hi;
+                run_k[e] = n;
+            }
         }
+        __syncthreads();
+        for (int e = 0; e < n_long; ++e)
+            for (uint32_t i = run_lo[e] + threadIdx.x; i < run_hi[e]; i += TILE) fd.anc[i] = run_k[e];
     }
 }
 
