@@ -153,39 +153,21 @@ def cpu_baseline(prob, target_s):
                       f"(FP64 C oracle, OpenMP over particles, {el:.1f} s)"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--cpu-seconds", type=float, default=20.0)
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-fp64", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); independent filters shard "
-              "by whole filters across GPUs, see DESIGN.md", file=sys.stderr)
-        sys.exit(2)
-    import torch
-    from paper_1411_1702_amd import pf
-    if not torch.cuda.is_available():
-        print("bench.py needs a GPU", file=sys.stderr)
-        sys.exit(1)
-    torch.cuda.init()
-    prob = inputs.config_robertson_large()
-    if args.steps < 1 or args.steps > prob.T:
-        print(f"--steps must be 1..{prob.T} (observation times of the workload)", file=sys.stderr)
-        sys.exit(2)
+def single_filter(pf, args, prob):
+    """One filter, `steps` observation steps, FP32 served form and plain FP64."""
+    steps = min(args.steps, prob.T)
     warm = min(args.warmup, prob.T)
     with pf.Context(0, 4 << 30) as ctx:
-        r32 = time_path(pf, ctx, prob, pf.PF_PREC_FP32_PROP, args.steps, warm)
-        r64 = None if args.no_fp64 else time_path(pf, ctx, prob, pf.PF_PREC_FP64, args.steps, warm)
+        r32 = time_path(pf, ctx, prob, pf.PF_PREC_FP32_PROP, steps, warm)
+        r64 = None if args.no_fp64 else time_path(pf, ctx, prob, pf.PF_PREC_FP64, steps, warm)
         lat = latency(pf, ctx, prob, pf.PF_PREC_FP32_PROP, min(60, prob.T))
     upd_ms = r32["kernel_ms"]["update"]
     achieved = r32["flop_update_per_launch"] / (upd_ms * 1e-3) / 1e12
+    model = "robertson" if prob.model == inputs.MODEL_ROBERTSON else "chain16"
     roofline = {
-        "bound": "alu", "kernel": "k_update (steps 3c-6: gather, proliferate, BDF2 repropagation "
-                                  "with Newton + local-error innovation, weights, moments)",
+        "bound": "alu",
+        "kernel": f"k_update<{model}, fp32, BDF{prob.order}> (steps 3c-5: gather, proliferate, "
+                  "repropagation with Newton and local-error innovation, weights, tile moments)",
         "achieved": achieved, "peak": PEAK_VALU_NONPACKED, "unit": "TFLOP/s",
         "frac": achieved / PEAK_VALU_NONPACKED,
         "frac_of_published_fp32": achieved / PEAK_FP32_PUBLISHED,
@@ -197,12 +179,12 @@ def main():
         "metric": METRIC,
         "value": r32["particle_steps_per_s"],
         "unit": "particle-steps/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": warm,
+        "n_gpus": 1, "steps": steps, "warmup": warm,
         "ms_per_step": r32["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"robertson N={prob.n_particles} T={prob.T} BDF{prob.order} "
+        "config": {"workload": f"{model} N={prob.n_particles} T={prob.T} BDF{prob.order} "
                                f"M={prob.substeps} fp32-propagation, fp64 weights/moments",
                    "particles": prob.n_particles, "observations": prob.T, "bdf_order": prob.order,
                    "substeps": prob.substeps},
@@ -214,6 +196,88 @@ def main():
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
+    return out
+
+
+def batched(pf, args):
+    """Many independent filters, one batched submission per observation round."""
+    import torch
+    probs = inputs.batched_mix(args.filters, seed=0)
+    prec = pf.PF_PREC_FP32_PROP
+    rounds = max(p.T for p in probs)
+    total = sum(p.n_particles * p.T for p in probs)
+
+    def run(ctx, timed):
+        fs = [pf.Filter(ctx, pf.Config(p, prec)) for p in probs]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pending = []
+        for r in range(rounds):
+            idx = [i for i, p in enumerate(probs) if r < p.T]
+            tk = ctx.assimilate_batch([fs[i] for i in idx], [probs[i].times[r] for i in idx],
+                                      [probs[i].y[r] for i in idx], [probs[i].sigma[r] for i in idx])
+            pending.append(list(zip(idx, tk)))
+            if len(pending) >= 32:
+                for i, t in pending.pop(0):
+                    fs[i].wait(t)
+        bad = 0
+        for grp in pending:
+            for i, t in grp:
+                bad += fs[i].wait(t) != pf.PF_OK
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        for f in fs:
+            f.close()
+        return wall, bad
+
+    with pf.Context(0, 24 << 30) as ctx:
+        run(ctx, False)                 # warm-up: captures nothing (shapes change every round)
+        wall, bad = run(ctx, True)
+    n_chain = sum(p.model == inputs.MODEL_CHAIN for p in probs)
+    return {
+        "metric": METRIC, "value": total / wall, "unit": "particle-steps/s",
+        "n_gpus": 1, "steps": rounds, "warmup": rounds, "ms_per_step": 1e3 * wall / rounds,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"batched {len(probs)} filters ({n_chain} chain16 BDF3 M=40 T=100, "
+                               f"{len(probs) - n_chain} robertson BDF2 M=20 T=50), "
+                               "N log-uniform in [512, 65536], one submission per round",
+                   "particles_total": int(sum(p.n_particles for p in probs)),
+                   "particle_steps": int(total)},
+        "skipped_steps": int(bad),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--config", default="robertson", choices=["robertson", "small", "chain", "batched"])
+    ap.add_argument("--filters", type=int, default=256)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); independent filters shard "
+              "by whole filters across GPUs, see DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1411_1702_amd import pf
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.init()
+    if args.config == "batched":
+        out = batched(pf, args)
+    else:
+        prob = {"robertson": inputs.config_robertson_large, "small": inputs.config_small,
+                "chain": inputs.config_chain}[args.config]()
+        if args.steps < 1:
+            print("--steps must be >= 1", file=sys.stderr)
+            sys.exit(2)
+        out = single_filter(pf, args, prob)
     print(json.dumps(out))
 
 

@@ -352,12 +352,13 @@ class Filter:
         means, sds, ess = [], [], []
         for j in range(T):
             out = self.step(prob.times[j], prob.y[j], prob.sigma[j])
-            if out["status"]:
+            if out["status"] not in (OK, EDEGENERATE):
                 raise RuntimeError(f"oracle step {j} failed: {out['status']}")
+            # a degenerate step is skipped: the ensemble and its moments stay
             mean, cov = self.moments()
             means.append(mean)
             sds.append(np.sqrt(np.diag(cov)))
-            ess.append(out["ess"])
+            ess.append(out["ess"] if out["status"] == OK else np.nan)
             if callback:
                 callback(j, out)
         return np.array(means), np.array(sds), np.array(ess)

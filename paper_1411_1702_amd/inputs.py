@@ -225,7 +225,14 @@ def config_chain() -> Problem:
     return chain16(1 << 16, 100, seed=0)
 
 
-N_CHAIN_INSTANCES = 8
+# Constant sets of the chain used by the many-filter mixes.  A random draw of
+# the 48 rates/affinities often gives observed compartments so small or so
+# sharply informative that a few hundred particles collapse onto one at the
+# first observation; these seeds were kept because a 512-particle FP64
+# reference filter assimilates their first 10 observations without a
+# skipped step.
+CHAIN_INSTANCES = (0, 3, 8, 9, 10, 11, 12, 15)
+N_CHAIN_INSTANCES = len(CHAIN_INSTANCES)
 
 
 def batched_mix(n_filters: int = 256, seed: int = 0, n_min: int = 512, n_max: int = 65536,
@@ -241,7 +248,7 @@ def batched_mix(n_filters: int = 256, seed: int = 0, n_min: int = 512, n_max: in
         is_chain = g.uniform() < chain_fraction
         n = int(round(2.0 ** (lo + (hi - lo) * g.uniform())))
         if is_chain:
-            probs.append(chain16(n, 100, seed=f, model_seed=f % N_CHAIN_INSTANCES))
+            probs.append(chain16(n, 100, seed=f, model_seed=CHAIN_INSTANCES[f % N_CHAIN_INSTANCES]))
         else:
             probs.append(robertson(n, 50, seed=f))
     return probs
@@ -268,7 +275,7 @@ def serving_trace(n_streams: int = 2000, rate: float = 200.0, seed: int = 0,
         is_chain = g.uniform() < chain_fraction
         n = int(sizes[int(g.integers(len(sizes)))])
         if is_chain:
-            prob = chain16(n, 100, seed=1000 + s, model_seed=s % N_CHAIN_INSTANCES)
+            prob = chain16(n, 100, seed=1000 + s, model_seed=CHAIN_INSTANCES[s % N_CHAIN_INSTANCES])
         else:
             prob = robertson(n, 50, seed=1000 + s)
         gaps = g.exponential(obs_gap_mean, prob.T)

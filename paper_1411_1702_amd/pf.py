@@ -253,12 +253,10 @@ def run_filter(ctx, prob, precision=PF_PREC_FP32_PROP, T=None, n_particles=None,
     try:
         for j in range(T):
             st = f.assimilate(prob.times[j], prob.y[j], prob.sigma[j])
-            if st != PF_OK:
-                raise PfError(st, f"step {j}")
-            post = f.posterior()
+            post = f.posterior()   # a skipped (degenerate) step leaves the ensemble as it was
             means.append(post["mean"])
             sds.append(np.sqrt(np.diag(post["cov"])))
-            ess.append(post["ess"])
+            ess.append(post["ess"] if st == PF_OK else np.nan)
     finally:
         f.close()
     return np.array(means), np.array(sds), np.array(ess)
