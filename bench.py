@@ -248,6 +248,61 @@ def batched(pf, args):
     }
 
 
+def serving(pf, args):
+    """Poisson arrivals of filtering streams replayed in real time through the
+    continuous-batching server; latency = submit -> result ready."""
+    trace = inputs.serving_trace(n_streams=args.streams, rate=200.0, seed=0)
+    cfgs = [pf.Config(r.problem, pf.PF_PREC_FP32_PROP) for r in trace]
+    events = []
+    for k, r in enumerate(trace):
+        events.append((r.arrival, 0, k, -1))
+        for j, off in enumerate(r.obs_offsets):
+            events.append((r.arrival + off, 1, k, j))
+    events.sort()
+    runs = {}
+    for label, pool in (("uncapped", 48 << 30), ("pool_256MiB", 256 << 20)):
+        with pf.Context(0, pool) as ctx:
+            srv = pf.Server(ctx, max_inflight=3)
+            sids = [None] * len(trace)
+            t0 = time.perf_counter()
+            lag = 0.0
+            for when, kind, k, j in events:
+                now = time.perf_counter() - t0
+                if when > now:
+                    time.sleep(when - now)
+                else:
+                    lag = max(lag, now - when)
+                if kind == 0:
+                    sids[k] = srv.open(cfgs[k])
+                else:
+                    prob = trace[k].problem
+                    srv.submit(sids[k], prob.times[j], prob.y[j], prob.sigma[j])
+                    if j == prob.T - 1:
+                        srv.close(sids[k])
+            srv.drain()
+            wall = time.perf_counter() - t0
+            st = srv.stats()
+            srv.destroy()
+        st["wall_s"] = wall
+        st["driver_max_lag_ms"] = 1e3 * lag
+        st["particle_steps_per_s"] = st["particle_steps"] / st["busy_s"] if st["busy_s"] > 0 else None
+        runs[label] = st
+    main_run = runs["uncapped"]
+    n_chain = sum(r.problem.model == inputs.MODEL_CHAIN for r in trace)
+    return {
+        "metric": METRIC, "value": main_run["particle_steps_per_s"], "unit": "particle-steps/s",
+        "n_gpus": 1, "steps": int(main_run["ticks"]), "warmup": 0,
+        "ms_per_step": 1e3 * main_run["busy_s"] / max(main_run["ticks"], 1),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"serving {len(trace)} streams, Poisson arrivals 200/s, "
+                               f"{n_chain} chain16 / {len(trace) - n_chain} robertson, "
+                               "N in {4096, 16384, 65536}, observation gaps Exp(10 ms), fp32 propagation"},
+        "latency_p50_ms": main_run["latency_p50_ms"], "latency_p99_ms": main_run["latency_p99_ms"],
+        "runs": runs,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -256,8 +311,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--config", default="robertson", choices=["robertson", "small", "chain", "batched"])
+    ap.add_argument("--config", default="robertson",
+                    choices=["robertson", "small", "chain", "batched", "serving"])
     ap.add_argument("--filters", type=int, default=256)
+    ap.add_argument("--streams", type=int, default=2000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); independent filters shard "
@@ -271,6 +328,8 @@ def main():
     torch.cuda.init()
     if args.config == "batched":
         out = batched(pf, args)
+    elif args.config == "serving":
+        out = serving(pf, args)
     else:
         prob = {"robertson": inputs.config_robertson_large, "small": inputs.config_small,
                 "chain": inputs.config_chain}[args.config]()

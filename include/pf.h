@@ -126,6 +126,10 @@ pf_status pf_assimilate_async(pf_filter* f, double t_obs, const double* y, const
 /* Waits for a ticket of this filter and returns that step's status. */
 pf_status pf_wait(pf_filter* f, uint64_t ticket);
 
+/* Non-blocking: PF_EBUSY while the ticket's step is still running, otherwise
+ * the step's status (the ticket is then consumed, as by pf_wait). */
+pf_status pf_query(pf_filter* f, uint64_t ticket);
+
 /*
  * Batched form: one step for `count` distinct filters of one context, as a
  * single submission.  y and sigma are [count][4] (row i uses its filter's
@@ -175,6 +179,68 @@ pf_status pf_context_kernel_time(pf_context* ctx, int which, uint64_t* count, do
 
 /* Releases the filter's pool memory after its pending steps complete. */
 void pf_destroy(pf_filter* f);
+
+/* ------------------------------------------------------------------------
+ * Serving: many filtering streams on one context with continuous batching.
+ * A scheduler thread admits streams when the context's pool can hold their
+ * ensembles (first come, first served), and repeatedly launches a tick: one
+ * batched step (pf_assimilate_batch) that takes the oldest pending
+ * observation of every admitted stream that has one.  Observations arriving
+ * while ticks run join the next tick; up to max_inflight ticks are on the
+ * GPU at once.  Each result is bit-identical to assimilating that stream
+ * alone.  Latency of a step = pf_server_submit call -> result observed
+ * complete by the scheduler.
+ * ------------------------------------------------------------------------ */
+typedef struct pf_server pf_server;
+
+typedef struct {
+    uint32_t struct_size;         /* sizeof(pf_server_config) */
+    uint32_t max_inflight;        /* ticks on the GPU at once, >= 1 (0: 3) */
+    uint32_t max_batch;           /* streams per tick, 1..4096 (0: 4096) */
+    uint32_t reserved;
+} pf_server_config;
+
+typedef struct {
+    uint64_t streams_opened, streams_admitted, streams_closed;
+    uint64_t ticks, steps_completed, steps_skipped;   /* skipped = degenerate or out of order */
+    uint64_t particle_steps;                          /* sum of N over completed steps */
+    double latency_p50_ms, latency_p99_ms, latency_max_ms;
+    double admit_wait_p50_ms, admit_wait_p99_ms;      /* open -> admitted */
+    double mean_batch;                                /* streams per tick */
+    double busy_s;                                    /* first submit -> last completion */
+} pf_server_report;
+
+pf_status pf_server_create(pf_context* ctx, const pf_server_config* cfg, pf_server** out);
+
+/* Opens a stream with configuration cfg (copied).  It is admitted as soon as
+ * the pool can hold it; observations submitted before that wait in its queue.
+ * PF_ENOMEM if the ensemble could never fit the pool. */
+pf_status pf_server_open(pf_server* s, const pf_config* cfg, uint64_t* stream);
+
+/* Queues an observation (y, sigma: [m], copied) at t_obs for the stream;
+ * returns a per-stream ticket.  Times must increase per stream. */
+pf_status pf_server_submit(pf_server* s, uint64_t stream, double t_obs, const double* y,
+                           const double* sigma, uint64_t* ticket);
+
+/* PF_EBUSY while the ticket's step is pending; otherwise the step's status
+ * and (if latency_ms != NULL) its latency. */
+pf_status pf_server_poll(pf_server* s, uint64_t stream, uint64_t ticket, double* latency_ms);
+
+/* Waits until every submitted step of the stream is done, then reads its
+ * posterior as pf_posterior does (for a closed stream: the posterior it had
+ * when its memory was released). */
+pf_status pf_server_posterior(pf_server* s, uint64_t stream, double* mean, double* cov, double* ess,
+                              uint64_t* step);
+
+/* Closes the stream: its memory returns to the pool after its submitted steps
+ * complete (results stay pollable). */
+pf_status pf_server_close(pf_server* s, uint64_t stream);
+
+/* Waits until all submitted steps are complete and closed streams released. */
+pf_status pf_server_drain(pf_server* s);
+
+pf_status pf_server_stats(pf_server* s, pf_server_report* out);
+void pf_server_destroy(pf_server* s);
 
 const char* pf_status_str(pf_status s);
 const char* pf_last_error(void);

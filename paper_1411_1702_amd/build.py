@@ -8,8 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpf_hip.so")
-SOURCES = ["pf_runtime.hip"]
-DEPS = ["pf_runtime.hip", "pf_kernels.hip", "pf_device.hpp", "pf_types.hpp"]
+SOURCES = ["pf_runtime.hip", "pf_server.cpp"]
+DEPS = ["pf_runtime.hip", "pf_kernels.hip", "pf_device.hpp", "pf_types.hpp", "pf_server.cpp"]
 ARCH = os.environ.get("PF_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

@@ -155,6 +155,7 @@ struct pf_context {
     std::map<std::string, int> seen;            // signature -> submissions seen (capture on the 2nd)
     uint64_t use_clock = 0;
     hipStream_t stream = nullptr;
+    hipStream_t init_stream = nullptr;   // filter creation runs here, beside the step stream
     bool own_stream = false;
     Pool pool;
     FilterDesc* d_desc = nullptr;
@@ -343,6 +344,7 @@ extern "C" pf_status pf_context_create(int device, uint64_t pool_bytes, void* hi
         HIP_TRY(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
         ctx->own_stream = true;
     }
+    HIP_TRY(hipStreamCreateWithFlags(&ctx->init_stream, hipStreamNonBlocking));
     if (pool_bytes == 0) {
         size_t fr = 0, tot = 0;
         HIP_TRY(hipMemGetInfo(&fr, &tot));
@@ -395,6 +397,7 @@ extern "C" void pf_context_destroy(pf_context* ctx)
     (void)hipFree(ctx->d_state);
     (void)hipFree(ctx->pool.base);
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+    (void)hipStreamDestroy(ctx->init_stream);
     delete ctx;
 }
 
@@ -461,17 +464,17 @@ extern "C" pf_status pf_create(pf_context* ctx, const pf_config* cfg, pf_filter*
         ctx->slot_used[f->slot] = 0;
         return e;
     };
-    if (hipMemcpyAsync(ctx->d_desc + f->slot, &f->desc, sizeof(FilterDesc), hipMemcpyHostToDevice, ctx->stream) != hipSuccess ||
-        hipMemcpyAsync(ctx->d_state + f->slot, &st, sizeof(FilterState), hipMemcpyHostToDevice, ctx->stream) != hipSuccess ||
-        hipMemsetAsync(f->desc.anc, 0, sizeof(int32_t) * (size_t)f->desc.npad, ctx->stream) != hipSuccess)
+    if (hipMemcpyAsync(ctx->d_desc + f->slot, &f->desc, sizeof(FilterDesc), hipMemcpyHostToDevice, ctx->init_stream) != hipSuccess ||
+        hipMemcpyAsync(ctx->d_state + f->slot, &st, sizeof(FilterState), hipMemcpyHostToDevice, ctx->init_stream) != hipSuccess ||
+        hipMemsetAsync(f->desc.anc, 0, sizeof(int32_t) * (size_t)f->desc.npad, ctx->init_stream) != hipSuccess)
         return cleanup(fail(PF_EDEVICE, "upload of filter descriptor failed"));
     const unsigned grid = grid_for(ctx, f->desc.ntiles);
     if (f->desc.prec == PREC_FP32)
-        hipLaunchKernelGGL(k_init<float>, dim3(grid), dim3(TILE), 0, ctx->stream, f->slot, ctx->d_desc, ctx->d_state);
+        hipLaunchKernelGGL(k_init<float>, dim3(grid), dim3(TILE), 0, ctx->init_stream, f->slot, ctx->d_desc, ctx->d_state);
     else
-        hipLaunchKernelGGL(k_init<double>, dim3(grid), dim3(TILE), 0, ctx->stream, f->slot, ctx->d_desc, ctx->d_state);
-    hipLaunchKernelGGL(k_init_moments, dim3(1), dim3(TILE), 0, ctx->stream, f->slot, ctx->d_desc, ctx->d_state);
-    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(ctx->stream) != hipSuccess)
+        hipLaunchKernelGGL(k_init<double>, dim3(grid), dim3(TILE), 0, ctx->init_stream, f->slot, ctx->d_desc, ctx->d_state);
+    hipLaunchKernelGGL(k_init_moments, dim3(1), dim3(TILE), 0, ctx->init_stream, f->slot, ctx->d_desc, ctx->d_state);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(ctx->init_stream) != hipSuccess)
         return cleanup(fail(PF_EDEVICE, "initialisation kernel failed"));
     int32_t status = 0;
     if (hipMemcpy(&status, &ctx->d_state[f->slot].status, sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
@@ -740,6 +743,27 @@ extern "C" pf_status pf_wait(pf_filter* f, uint64_t ticket)
     return st;
 }
 
+extern "C" pf_status pf_query(pf_filter* f, uint64_t ticket)
+{
+    if (!f) return fail(PF_EINVAL, "NULL filter");
+    if (ticket == 0 || ticket >= f->next_seq) return fail(PF_EINVAL, "unknown ticket");
+    HIP_TRY(hipSetDevice(f->ctx->device));
+    // complete every ticket up to this one whose event has fired
+    while (!f->pending.empty() && f->pending.front().seq <= ticket) {
+        const hipError_t q = hipEventQuery(*f->pending.front().ev);
+        if (q == hipErrorNotReady) return PF_EBUSY;
+        if (q != hipSuccess) return fail(PF_EDEVICE, std::string("hipEventQuery: ") + hipGetErrorString(q));
+        Ticket t = f->pending.front();
+        f->done_status[t.seq] = f->ctx->h_ring[(size_t)f->slot * RING + t.seq % RING];
+        f->pending.pop_front();
+    }
+    auto it = f->done_status.find(ticket);
+    if (it == f->done_status.end()) return fail(PF_EINVAL, "ticket already consumed");
+    const pf_status st = (pf_status)it->second;
+    f->done_status.erase(it);
+    return st;
+}
+
 extern "C" pf_status pf_assimilate(pf_filter* f, double t_obs, const double* y, const double* sigma)
 {
     uint64_t t = 0;
@@ -803,8 +827,9 @@ extern "C" void pf_destroy(pf_filter* f)
     if (!f) return;
     pf_context* ctx = f->ctx;
     (void)hipSetDevice(ctx->device);
-    drain(f, f->next_seq - 1);
-    (void)hipStreamSynchronize(ctx->stream);
+    // every kernel that touches this filter's memory belongs to one of its
+    // tickets: once they are complete the memory can be reused
+    (void)drain(f, f->next_seq - 1);
     {
         std::lock_guard<std::mutex> lk(ctx->mu);
         ctx->pool.release(f->pool_off, f->pool_bytes);

@@ -25,7 +25,9 @@ EXPORTS = [
     "pf_context_create", "pf_context_destroy", "pf_filter_bytes", "pf_context_memory",
     "pf_create", "pf_assimilate", "pf_assimilate_async", "pf_wait", "pf_assimilate_batch",
     "pf_posterior", "pf_stats", "pf_destroy", "pf_status_str", "pf_last_error",
-    "pf_context_profile", "pf_context_kernel_time",
+    "pf_context_profile", "pf_context_kernel_time", "pf_query",
+    "pf_server_create", "pf_server_open", "pf_server_submit", "pf_server_poll", "pf_server_posterior",
+    "pf_server_close", "pf_server_drain", "pf_server_stats", "pf_server_destroy",
     "pf_test_philox", "pf_test_normals", "pf_test_propagate", "pf_test_resample",
     "pf_test_get_ensemble", "pf_test_set_ensemble", "pf_test_last_ancestors",
 ]
@@ -50,6 +52,20 @@ class pf_config(C.Structure):
         ("newton_rtol", C.c_double), ("state_floor", C.POINTER(C.c_double)),
         ("precision", C.c_int),
     ]
+
+
+class pf_server_config(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("max_inflight", C.c_uint32), ("max_batch", C.c_uint32),
+                ("reserved", C.c_uint32)]
+
+
+class pf_server_report(C.Structure):
+    _fields_ = [("streams_opened", C.c_uint64), ("streams_admitted", C.c_uint64),
+                ("streams_closed", C.c_uint64), ("ticks", C.c_uint64), ("steps_completed", C.c_uint64),
+                ("steps_skipped", C.c_uint64), ("particle_steps", C.c_uint64),
+                ("latency_p50_ms", C.c_double), ("latency_p99_ms", C.c_double), ("latency_max_ms", C.c_double),
+                ("admit_wait_p50_ms", C.c_double), ("admit_wait_p99_ms", C.c_double),
+                ("mean_batch", C.c_double), ("busy_s", C.c_double)]
 
 
 _lib = None
@@ -91,6 +107,17 @@ def lib():
         L.pf_test_get_ensemble.argtypes = [vp, vp, vp, vp]
         L.pf_test_set_ensemble.argtypes = [vp, vp, vp, vp, dp, dp, u64, C.c_double]
         L.pf_test_last_ancestors.argtypes = [vp, vp]
+        L.pf_query.argtypes = [vp, u64]
+        L.pf_server_create.argtypes = [vp, C.POINTER(pf_server_config), C.POINTER(vp)]
+        L.pf_server_open.argtypes = [vp, C.POINTER(pf_config), C.POINTER(u64)]
+        L.pf_server_submit.argtypes = [vp, u64, C.c_double, dp, dp, C.POINTER(u64)]
+        L.pf_server_poll.argtypes = [vp, u64, u64, dp]
+        L.pf_server_posterior.argtypes = [vp, u64, dp, dp, dp, C.POINTER(u64)]
+        L.pf_server_close.argtypes = [vp, u64]
+        L.pf_server_drain.argtypes = [vp]
+        L.pf_server_stats.argtypes = [vp, C.POINTER(pf_server_report)]
+        L.pf_server_destroy.argtypes = [vp]
+        L.pf_server_destroy.restype = None
         _lib = L
     return _lib
 
@@ -241,6 +268,64 @@ class Filter:
     def close(self):
         if self.h:
             lib().pf_destroy(self.h)
+            self.h = None
+
+
+class Server:
+    """Continuous-batching server over a context (pf_server_* of the C ABI)."""
+
+    def __init__(self, ctx: Context, max_inflight=3, max_batch=4096):
+        cfg = pf_server_config(C.sizeof(pf_server_config), int(max_inflight), int(max_batch), 0)
+        h = C.c_void_p()
+        check(lib().pf_server_create(ctx.h, C.byref(cfg), C.byref(h)), "pf_server_create")
+        self.h = h
+        self.m = {}
+
+    def open(self, cfg: Config) -> int:
+        sid = C.c_uint64()
+        check(lib().pf_server_open(self.h, cfg.ptr(), C.byref(sid)), "pf_server_open")
+        self.m[sid.value] = cfg.c.m
+        return sid.value
+
+    def submit(self, sid, t, y, sigma) -> int:
+        m = self.m[sid]
+        yy = np.zeros(4)
+        ss = np.ones(4)
+        yy[:m] = y[:m]
+        ss[:m] = sigma[:m]
+        tk = C.c_uint64()
+        check(lib().pf_server_submit(self.h, sid, float(t), _dp(yy), _dp(ss), C.byref(tk)), "pf_server_submit")
+        return tk.value
+
+    def poll(self, sid, ticket):
+        """(status, latency_ms); status PF_EBUSY while pending."""
+        lat = C.c_double()
+        st = lib().pf_server_poll(self.h, sid, ticket, C.byref(lat))
+        return st, lat.value
+
+    def posterior(self, sid, p):
+        mean = np.zeros(p)
+        cov = np.zeros(p * p)
+        ess = C.c_double()
+        step = C.c_uint64()
+        check(lib().pf_server_posterior(self.h, sid, _dp(mean), _dp(cov), C.byref(ess), C.byref(step)),
+              "pf_server_posterior")
+        return {"mean": mean, "cov": cov.reshape(p, p), "ess": ess.value, "step": step.value}
+
+    def close(self, sid):
+        check(lib().pf_server_close(self.h, sid), "pf_server_close")
+
+    def drain(self):
+        check(lib().pf_server_drain(self.h), "pf_server_drain")
+
+    def stats(self):
+        r = pf_server_report()
+        check(lib().pf_server_stats(self.h, C.byref(r)), "pf_server_stats")
+        return {name: getattr(r, name) for name, _ in pf_server_report._fields_}
+
+    def destroy(self):
+        if self.h:
+            lib().pf_server_destroy(self.h)
             self.h = None
 
 
