@@ -81,8 +81,8 @@ typedef struct {
     double shrink_a;             /* Liu-West factor, 0 < a < 1; jitter s = sqrt(1 - a^2) */
     pf_lmm lmm;
     uint32_t order;              /* BDF order k, 1..3 */
-    uint32_t substeps;           /* fixed steps per observation interval, >= 1 */
-    uint32_t newton_max_iter;    /* >= 1 */
+    uint32_t substeps;           /* fixed steps per observation interval, 1..65536 */
+    uint32_t newton_max_iter;    /* 1..64 */
     double newton_rtol;          /* stopping test max |dx_i| / max(|x_i|, floor_i) */
     const double* state_floor;   /* [d] scale floors of that test */
     pf_precision precision;

@@ -45,6 +45,10 @@ pf_status pf_test_propagate(const pf_config* cfg, uint64_t n, const double* x_in
 pf_status pf_test_resample(uint64_t n, const double* g, uint64_t r, int32_t* anc,
                            void* hip_stream);
 
+/* The three filter-based calls below run on the context's own stream: each
+ * first waits for all work on the device (so buffers the caller produced on
+ * any stream are ready) and returns after its own work is done. */
+
 /* Reads the current ensemble as doubles: x [d][N], theta [p][N], logw [N]
  * (normalised log-weights); device pointers, any may be NULL.  Synchronous. */
 pf_status pf_test_get_ensemble(pf_filter* f, double* x, double* theta, double* logw);

@@ -259,8 +259,11 @@ __device__ inline void integrate(const Model& md, R x[Model::D], R gam[Model::D]
             xn[i] = p;
         }
         typename Model::LU lu;
-        bool conv = false;
-        for (int it = 0; it < kmax; ++it) {
+        // one exit (converged or kmax reached), so the loop is a plain
+        // while-any-lane-active loop; the counts come from its exit state
+        bool ok = false;
+        int it = 0;
+        do {
             R f[D];
             md.eval(xn, c, f, lu);
             if (LTE && avail == 0 && it == 0) {
@@ -271,16 +274,16 @@ __device__ inline void integrate(const Model& md, R x[Model::D], R gam[Model::D]
 #pragma unroll
             for (int i = 0; i < D; ++i) b[i] = (psi[i] + c * f[i]) - xn[i];
             md.solve(lu, b);
-            ++iters;
-            bool ok = true;
+            ok = true;
 #pragma unroll
             for (int i = 0; i < D; ++i) {
                 xn[i] += b[i];
                 ok &= rabs(b[i]) <= rtol * rmax(rabs(xn[i]), fl[i]);
             }
-            if (ok) { conv = true; break; }
-        }
-        if (!conv) ++fails;
+            ++it;
+        } while (!ok && it < kmax);
+        iters += (uint32_t)it;
+        fails += ok ? 0u : 1u;
         if constexpr (LTE) {
             const R kap = avail == 0 ? R(0.5) : (R)co.kappa;
             R e[D];
@@ -305,19 +308,29 @@ __device__ inline void integrate(const Model& md, R x[Model::D], R gam[Model::D]
 }
 
 // Gaussian log-likelihood of the observed components, constants dropped;
-// -inf for a non-finite observed state.
-template <class R>
-__device__ inline double loglik(const R* x, const int32_t* obs, const double* y, const double* sg,
-                                int m)
+// -inf for a non-finite observed state.  Loops are unrolled over the largest
+// sizes so every index into the lane's registers is static.
+template <class R, int D>
+__device__ inline double loglik(const R (&x)[D], const int32_t* obs, const double (&y)[MMAX],
+                                const double (&sg)[MMAX], int m)
 {
     double s = 0.0;
-    for (int i = 0; i < m; ++i) {
-        const double v = (double)x[obs[i]];
-        if (!isfinite(v)) return -INFINITY;
-        const double r = (y[i] - v) / sg[i];
-        s += r * r;
+    bool finite = true;
+#pragma unroll
+    for (int i = 0; i < MMAX; ++i) {
+        if (i < m) {
+            const int k = obs[i];
+            R xv = x[0];
+#pragma unroll
+            for (int c = 1; c < D; ++c)
+                if (c == k) xv = x[c];
+            const double v = (double)xv;
+            finite = finite && isfinite(v);
+            const double r = (y[i] - v) / sg[i];
+            s += r * r;
+        }
     }
-    return -0.5 * s;
+    return finite ? -0.5 * s : -INFINITY;
 }
 
 }  // namespace pf

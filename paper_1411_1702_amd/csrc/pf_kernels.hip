@@ -143,6 +143,28 @@ __device__ inline unsigned long long block_sum_u64(unsigned long long v, unsigne
     return r;
 }
 
+// two block sums at once (one barrier pair); sh holds 2*NWAVE words
+__device__ inline void block_sum2_u64(unsigned long long a, unsigned long long b, unsigned long long* sh,
+                                      unsigned long long& sa, unsigned long long& sb)
+{
+    a = wave_sum_u64(a);
+    b = wave_sum_u64(b);
+    const int w = threadIdx.x / WAVE, l = threadIdx.x % WAVE;
+    __syncthreads();
+    if (l == 0) {
+        sh[w] = a;
+        sh[NWAVE + w] = b;
+    }
+    __syncthreads();
+    sa = sh[0];
+    sb = sh[NWAVE];
+#pragma unroll
+    for (int i = 1; i < NWAVE; ++i) {
+        sa += sh[i];
+        sb += sh[NWAVE + i];
+    }
+}
+
 // exclusive prefix sum over the block (uint64, exact); returns the total
 __device__ inline unsigned long long block_exscan_u64(unsigned long long v, unsigned long long& excl,
                                                       unsigned long long* sh)
@@ -167,22 +189,36 @@ __device__ inline unsigned long long block_exscan_u64(unsigned long long v, unsi
     return total;
 }
 
+// Newton counters of one lane in one word, so a wavefront adds them with one
+// reduction: iterations in bits 0-31, failed solves in bits 32-55,
+// non-finite weights in bits 56-63 (a lane makes at most substeps*kmax <=
+// 2^22 iterations and substeps <= 2^16 failures, so 64 lanes fit).
+__device__ inline uint64_t pack_counts(uint32_t iters, uint32_t fails, uint32_t nonf)
+{
+    return (uint64_t)iters | ((uint64_t)fails << 32) | ((uint64_t)nonf << 56);
+}
+__device__ inline double count_iters(uint64_t w) { return (double)(w & 0xFFFFFFFFull); }
+__device__ inline double count_fails(uint64_t w) { return (double)((w >> 32) & 0xFFFFFFull); }
+__device__ inline double count_nonf(uint64_t w) { return (double)(w >> 56); }
+
 // Combine per-tile log-domain partials part[t*stride + 0] = tile max,
 // part[t*stride + 1 + a] = sums scaled by exp(-tile max), a < nsum, in a
 // fixed order: out[a] = sum_t exp(max_t - M) part[t][1+a].  The sum with
-// index sq (a sum of squared weights) scales with exp(2 (max_t - M)).
+// index sq (a sum of squared weights) scales with exp(2 (max_t - M)); the
+// last nplain sums are plain counts, added unscaled.
 // With an LDS staging buffer (buf, buf_len doubles), tiles are read in
 // coalesced chunks; the order of the sums depends only on ntiles, stride and
 // buf_len.  Returns M.
 __device__ __forceinline__ double combine_tiles(const double* part, int stride, int ntiles, int nsum, double* out,
                                 double* sh /* >= TILE doubles */, int sq = -1, double* buf = nullptr,
-                                int buf_len = 0)
+                                int buf_len = 0, int nplain = 0)
 {
     double mx = -INFINITY;
     for (int t = threadIdx.x; t < ntiles; t += TILE) mx = fmax(mx, part[(size_t)t * stride]);
     const double M = block_max(mx, sh);
     const int groups = TILE / nsum;
     const int a = threadIdx.x % nsum, g = threadIdx.x / nsum;
+    const bool plain = a >= nsum - nplain;
     double acc = 0.0;
     if (buf) {
         const int ch = buf_len / stride;
@@ -216,16 +252,19 @@ __device__ __forceinline__ double combine_tiles(const double* part, int stride, 
             if (g < groups) {
                 for (int t = g; t < nt; t += groups) {
                     const double sc = buf[t * stride];
-                    acc += (a == sq ? sc * sc : sc) * buf[t * stride + 1 + a];
+                    acc += (plain ? 1.0 : a == sq ? sc * sc : sc) * buf[t * stride + 1 + a];
                 }
             }
         }
-    } else if (g < groups && M > -INFINITY) {
+    } else if (g < groups) {
         for (int t = g; t < ntiles; t += groups) {
             const double mt = part[(size_t)t * stride];
-            if (mt > -INFINITY) {
+            const double v = part[(size_t)t * stride + 1 + a];
+            if (plain) {
+                acc += v;
+            } else if (mt > -INFINITY && M > -INFINITY) {
                 const double sc = exp(mt - M);
-                acc += (a == sq ? sc * sc : sc) * part[(size_t)t * stride + 1 + a];
+                acc += (a == sq ? sc * sc : sc) * v;
             }
         }
     }
@@ -241,15 +280,78 @@ __device__ __forceinline__ double combine_tiles(const double* part, int stride, 
     return M;
 }
 
+// The same combination for rows of a length known at compile time (small
+// models; the first-stage partials), in one pass with the rows in registers:
+// the first NS sums of rows of STRIDE doubles.  Each lane visits its tiles
+// (round-robin, two rows in flight) in increasing order, keeping its sums
+// relative to its own running max; then the block max, one rescale per lane,
+// and a block sum per column.  The order depends only on ntiles.
+template <int STRIDE, int NS>
+__device__ __forceinline__ double combine_rows(const double* part, int ntiles, int sq, int nplain, double* out,
+                                               double* sh)
+{
+    static_assert(NS < STRIDE, "row holds the max and NS sums");
+    constexpr int NA = NS + 1;
+    __shared__ double colsum[NWAVE][NS];
+    double acc[NS];
+#pragma unroll
+    for (int a = 0; a < NS; ++a) acc[a] = 0.0;
+    double mloc = -INFINITY;
+    auto scale = [&](int a, double r) { return a >= NS - nplain ? 1.0 : a == sq ? r * r : r; };
+    auto take = [&](const double (&row)[NA]) {
+        const double mt = row[0];
+        if (mt > mloc) {
+            const double r = mloc > -INFINITY ? exp(mloc - mt) : 0.0;
+#pragma unroll
+            for (int a = 0; a < NS; ++a) acc[a] *= scale(a, r);
+            mloc = mt;
+        }
+        const double sc = mt > -INFINITY ? exp(mt - mloc) : 0.0;
+#pragma unroll
+        for (int a = 0; a < NS; ++a) acc[a] += scale(a, sc) * row[1 + a];
+    };
+    for (int t = threadIdx.x; t < ntiles; t += 2 * TILE) {
+        const int t2 = t + TILE;
+        double r0[NA], r1[NA];
+#pragma unroll
+        for (int k = 0; k < NA; ++k) r0[k] = part[(size_t)t * STRIDE + k];
+        if (t2 < ntiles) {
+#pragma unroll
+            for (int k = 0; k < NA; ++k) r1[k] = part[(size_t)t2 * STRIDE + k];
+        }
+        take(r0);
+        if (t2 < ntiles) take(r1);
+    }
+    const double M = block_max(mloc, sh);
+    const double r = (mloc > -INFINITY && M > -INFINITY) ? exp(mloc - M) : 0.0;
+    const int w = threadIdx.x / WAVE, ln = threadIdx.x % WAVE;
+#pragma unroll
+    for (int a = 0; a < NS; ++a) {
+        const double v = wave_sum(acc[a] * scale(a, r));
+        if (ln == 0) colsum[w][a] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < NS) {
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < NWAVE; ++i) s += colsum[i][threadIdx.x];
+        out[threadIdx.x] = s;
+    }
+    __syncthreads();
+    return M;
+}
+
 // ---------------------------------------------------------------------------
 // moments of the parameters for one tile: partial[0] = max l, then
 // s0 = sum e, s00 = sum e^2, S1 = sum e d, S2 = sum e d d^T (upper triangle,
-// row by row), Sx = sum e x, with e = exp(l - max) and d = theta - c.
+// row by row), Sx = sum e x, with e = exp(l - max) and d = theta - c; then
+// the NPLAIN counters: the lanes' packed counts, plus the predictor's
+// (iterations, fails) of the tile when pred is given.
 // PM, DM bound p and d at compile time so every register index is static.
 // ---------------------------------------------------------------------------
 template <class R, int PM, int DM>
 __device__ void tile_moments(double l, bool valid, const double* th, const R* x, const double* cshift,
-                             int p, int d, double* out_part, double* sh)
+                             int p, int d, uint64_t counts, const double* pred, double* out_part, double* sh)
 {
     const double lv = valid ? l : -INFINITY;
     const double Mt = block_max(lv, sh);
@@ -278,12 +380,22 @@ __device__ void tile_moments(double l, bool valid, const double* th, const R* x,
 #pragma unroll
     for (int i = 0; i < DM; ++i)
         if (i < d) emit(e > 0.0 ? e * (double)x[i] : 0.0);
-    const int nsum = a;
+    const uint64_t wc = wave_sum_u64(counts);
+    if (ln == 0) {
+        wsum[w][a] = count_iters(wc);
+        wsum[w][a + 1] = count_fails(wc);
+        wsum[w][a + 2] = count_nonf(wc);
+        wsum[w][a + 3] = 0.0;
+    }
+    const int c0 = a;
+    const int nsum = a + NPLAIN;
     __syncthreads();
     if (threadIdx.x < nsum) {
         double s = 0.0;
 #pragma unroll
         for (int i = 0; i < NWAVE; ++i) s += wsum[i][threadIdx.x];
+        if (pred && threadIdx.x == c0 + 1) s += pred[1];
+        if (pred && threadIdx.x == c0 + 3) s += pred[0];
         out_part[1 + threadIdx.x] = s;
     }
     if (threadIdx.x == 0) out_part[0] = Mt;
@@ -377,8 +489,16 @@ __device__ __forceinline__ void finalize_moments(const FilterDesc& fd, FilterSta
                                                  double* buf)
 {
     __shared__ double tot[NACC_MAX];
-    combine_tiles(fd.part2, fd.nacc, fd.ntiles, fd.nacc - 1, tot, sh, 1, buf, STAGE_LEN);
+    const int nsum = fd.nacc - 1;
+    constexpr int NA33 = 3 + 3 + 6 + 3 + NPLAIN;   // row length for p = d = 3
+    if (fd.nacc == NA33) combine_rows<NA33, NA33 - 1>(fd.part2, fd.ntiles, 1, NPLAIN, tot, sh);
+    else combine_tiles(fd.part2, fd.nacc, fd.ntiles, nsum, tot, sh, 1, buf, STAGE_LEN, NPLAIN);
     if (threadIdx.x == 0) {
+        const double* c = tot + nsum - NPLAIN;
+        st.newton_upd += (unsigned long long)c[0];
+        st.newton_fails += (unsigned long long)c[1];
+        st.nonfinite += (unsigned long long)c[2];
+        st.newton_pred += (unsigned long long)c[3];
         if (fd.p == 3 && fd.d == 3) moments_tail<3, 3>(tot, st, flip);
         else moments_tail<PMAX, DMAX>(tot, st, flip);
     }
@@ -390,18 +510,28 @@ __device__ __forceinline__ void finalize_moments(const FilterDesc& fd, FilterSta
 // ---------------------------------------------------------------------------
 struct Item {
     int b, slot, tile;
+    StepRec rec;
 };
 // items, batch entries and slots are uniform over the workgroup; saying so
 // lets the compiler use scalar loads for every descriptor field
 __device__ inline int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-__device__ inline Item decode(uint32_t it, const StepRec* recs)
+__device__ inline StepRec record(const Batch& B, int b) { return B.recs ? B.recs[b] : B.one; }
+
+__device__ inline Item fetch(const Batch& B, int itx)
 {
     Item r;
-    it = (uint32_t)uniform((int)it);
-    r.b = (int)(it >> 16);
-    r.slot = uniform(recs[r.b].slot);
-    r.tile = (int)(it & 0xFFFFu);
+    if (B.recs) {
+        const uint32_t it = (uint32_t)uniform((int)B.items[itx]);
+        r.b = (int)(it >> 16);
+        r.tile = (int)(it & 0xFFFFu);
+        r.rec = B.recs[r.b];
+    } else {
+        r.b = 0;
+        r.tile = itx;
+        r.rec = B.one;
+    }
+    r.slot = uniform(r.rec.slot);
     return r;
 }
 
@@ -439,7 +569,7 @@ __global__ __launch_bounds__(TILE) void k_init(int slot, const FilterDesc* descs
             }
             fd.logw[0][n] = -log((double)fd.n);
         }
-        tile_moments<R, PMAX, DMAX>(-log((double)fd.n), valid, th, xs, fd.prior_mean, fd.p, fd.d,
+        tile_moments<R, PMAX, DMAX>(-log((double)fd.n), valid, th, xs, fd.prior_mean, fd.p, fd.d, 0, nullptr,
                                     fd.part2 + (size_t)tile * fd.nacc, sh);
     }
 }
@@ -457,17 +587,16 @@ __global__ __launch_bounds__(TILE) void k_init_moments(int slot, const FilterDes
 // steps 2 and 3(a): shrink, predictor, first-stage log-weights
 // ---------------------------------------------------------------------------
 template <class Model, class R, int KORD>
-__global__ __launch_bounds__(TILE) void k_predict(const uint32_t* items, int n_items, const StepRec* recs,
-                                                  const FilterDesc* descs, FilterState* states)
+__global__ __launch_bounds__(TILE) void k_predict(Batch B, const FilterDesc* descs, FilterState* states)
 {
     constexpr int D = Model::D, P = Model::P;
     __shared__ double sh[TILE];
-    __shared__ unsigned long long shu[NWAVE];
-    for (int itx = blockIdx.x; itx < n_items; itx += gridDim.x) {
-        const Item itm = decode(items[itx], recs);
-        const StepRec& rec = recs[itm.b];
+    __shared__ unsigned long long wcnt[NWAVE];
+    for (int itx = blockIdx.x; itx < B.n_items; itx += gridDim.x) {
+        const Item itm = fetch(B, itx);
+        const StepRec& rec = itm.rec;
         const FilterDesc& fd = descs[itm.slot];
-        FilterState& st = states[itm.slot];
+        const FilterState& st = states[itm.slot];
         if (!step_valid(rec, st)) continue;
         const double h = (rec.t_next - st.t) / fd.substeps;
         const int n = itm.tile * TILE + threadIdx.x;
@@ -496,16 +625,27 @@ __global__ __launch_bounds__(TILE) void k_predict(const uint32_t* items, int n_i
             fd.lbar[n] = lb;
             fd.lg[n] = lg;
         }
+        // per-wavefront counts: written before the barriers of block_max,
+        // read before those of block_sum (which the next tile's writes follow)
+        const uint64_t wc = wave_sum_u64(pack_counts(iters, fails, 0));
+        if (threadIdx.x % WAVE == 0) wcnt[threadIdx.x / WAVE] = wc;
         const double Mt = block_max(lg, sh);
+        double ci = 0.0, cf = 0.0;
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int w = 0; w < NWAVE; ++w) {
+                ci += count_iters(wcnt[w]);
+                cf += count_fails(wcnt[w]);
+            }
+        }
         const double e = lg > -INFINITY ? exp(lg - Mt) : 0.0;
         const double s = block_sum(e, sh);
-        const unsigned long long it_sum = block_sum_u64(iters, shu);
-        const unsigned long long fl_sum = block_sum_u64(fails, shu);
         if (threadIdx.x == 0) {
-            fd.part1[2 * itm.tile] = Mt;
-            fd.part1[2 * itm.tile + 1] = s;
-            atomicAdd(&st.newton_pred, it_sum);
-            if (fl_sum) atomicAdd(&st.newton_fails, fl_sum);
+            double* p1 = fd.part1 + (size_t)itm.tile * PART1_STRIDE;
+            p1[0] = Mt;
+            p1[1] = s;
+            p1[2] = ci;
+            p1[3] = cf;
         }
     }
 }
@@ -513,28 +653,27 @@ __global__ __launch_bounds__(TILE) void k_predict(const uint32_t* items, int n_i
 // ---------------------------------------------------------------------------
 // step 3(b): systematic resampling in integers
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(TILE) void k_count(const uint32_t* items, int n_items, const StepRec* recs,
-                                                const FilterDesc* descs, FilterState* states)
+__global__ __launch_bounds__(TILE) void k_count(Batch B, const FilterDesc* descs, FilterState* states)
 {
     __shared__ double sh[TILE];
     __shared__ double tot[1];
     __shared__ unsigned long long shu[NWAVE];
-    for (int itx = blockIdx.x; itx < n_items; itx += gridDim.x) {
-        const Item itm = decode(items[itx], recs);
+    for (int itx = blockIdx.x; itx < B.n_items; itx += gridDim.x) {
+        const Item itm = fetch(B, itx);
         const FilterDesc& fd = descs[itm.slot];
         const FilterState& st = states[itm.slot];
-        if (!fd.g_direct && !step_valid(recs[itm.b], st)) continue;
+        if (!fd.g_direct && !step_valid(itm.rec, st)) continue;
+        const int n = itm.tile * TILE + threadIdx.x;
+        const double l = n < fd.n ? fd.lg[n] : -INFINITY;   // in flight during the combine
         double M = 0.0, S = 1.0;
         if (!fd.g_direct) {
             // the filter's first-stage log-sum-exp, from the tile partials
-            M = combine_tiles(fd.part1, 2, fd.ntiles, 1, tot, sh);
+            M = combine_rows<PART1_STRIDE, 1>(fd.part1, fd.ntiles, -1, 0, tot, sh);
             S = tot[0];
         }
         const bool ok = fd.g_direct || (M > -INFINITY && isfinite(M) && S > 0.0);
-        const int n = itm.tile * TILE + threadIdx.x;
         unsigned long long q = 0;
         if (n < fd.n) {
-            const double l = fd.lg[n];
             const double g = fd.g_direct ? l : (ok && l > -INFINITY ? exp(l - M) / S : 0.0);
             if (g > 0.0) q = (unsigned long long)floor(ldexp(g, fd.shift));
             fd.q[n] = q;
@@ -559,27 +698,20 @@ __device__ inline uint64_t first_slot(uint64_t c, uint64_t N, uint64_t T, uint64
 // by the whole workgroup
 constexpr uint64_t LONG_RUN = 16;
 
-__global__ __launch_bounds__(TILE) void k_scatter(const uint32_t* items, int n_items, const StepRec* recs,
-                                                  const FilterDesc* descs, FilterState* states)
+__global__ __launch_bounds__(TILE) void k_scatter(Batch B, const FilterDesc* descs, FilterState* states)
 {
-    __shared__ unsigned long long shu[NWAVE];
+    __shared__ unsigned long long shu[2 * NWAVE];
     __shared__ int n_long;
     __shared__ uint32_t run_lo[TILE], run_hi[TILE];
     __shared__ int run_k[TILE];
-    for (int itx = blockIdx.x; itx < n_items; itx += gridDim.x) {
-        const Item itm = decode(items[itx], recs);
+    for (int itx = blockIdx.x; itx < B.n_items; itx += gridDim.x) {
+        const Item itm = fetch(B, itx);
         const FilterDesc& fd = descs[itm.slot];
         FilterState& st = states[itm.slot];
-        if (!fd.g_direct && !step_valid(recs[itm.b], st)) continue;
-        // exclusive offset of this tile and total T of the integer weights
-        unsigned long long pre = 0, all = 0;
-        for (int t = threadIdx.x; t < fd.ntiles; t += TILE) {
-            const unsigned long long v = fd.tsum[t];
-            all += v;
-            if (t < itm.tile) pre += v;
-        }
-        pre = block_sum_u64(pre, shu);
-        const unsigned long long T = block_sum_u64(all, shu);
+        if (!fd.g_direct && !step_valid(itm.rec, st)) continue;
+        // this lane's weight and the systematic draw, ahead of the tile scan
+        const int n = itm.tile * TILE + threadIdx.x;
+        const unsigned long long q = n < fd.n ? fd.q[n] : 0ull;
         uint64_t r;
         if (fd.g_direct) {
             r = st.V;   // test mode: the uniform word was stored by the host
@@ -588,14 +720,21 @@ __global__ __launch_bounds__(TILE) void k_scatter(const uint32_t* items, int n_i
             Philox::block(st.j + 1, 0, PUR_RESAMPLE, 0, fd.seed, 0, w);
             r = w[0];
         }
+        // exclusive offset of this tile and total T of the integer weights
+        unsigned long long pre = 0, all = 0;
+        for (int t = threadIdx.x; t < fd.ntiles; t += TILE) {
+            const unsigned long long v = fd.tsum[t];
+            all += v;
+            if (t < itm.tile) pre += v;
+        }
+        unsigned long long T;
+        block_sum2_u64(pre, all, shu, pre, T);
         const uint64_t V = T ? __umul64hi(r, T) : 0;
         if (itm.tile == 0 && threadIdx.x == 0) {
             st.T = T;
             if (!fd.g_direct) st.V = V;
         }
         if (T == 0) continue;
-        const int n = itm.tile * TILE + threadIdx.x;
-        const unsigned long long q = n < fd.n ? fd.q[n] : 0ull;
         unsigned long long ex;
         block_exscan_u64(q, ex, shu);
         if (threadIdx.x == 0) n_long = 0;
@@ -625,17 +764,15 @@ __global__ __launch_bounds__(TILE) void k_scatter(const uint32_t* items, int n_i
 // steps 3(c)-5 per output slot
 // ---------------------------------------------------------------------------
 template <class Model, class R, int KORD>
-__global__ __launch_bounds__(TILE) void k_update(const uint32_t* items, int n_items, const StepRec* recs,
-                                                 const FilterDesc* descs, FilterState* states)
+__global__ __launch_bounds__(TILE) void k_update(Batch B, const FilterDesc* descs, FilterState* states)
 {
     constexpr int D = Model::D, P = Model::P;
     __shared__ double sh[TILE];
-    __shared__ unsigned long long shu[NWAVE];
-    for (int itx = blockIdx.x; itx < n_items; itx += gridDim.x) {
-        const Item itm = decode(items[itx], recs);
-        const StepRec& rec = recs[itm.b];
+    for (int itx = blockIdx.x; itx < B.n_items; itx += gridDim.x) {
+        const Item itm = fetch(B, itx);
+        const StepRec& rec = itm.rec;
         const FilterDesc& fd = descs[itm.slot];
-        FilterState& st = states[itm.slot];
+        const FilterState& st = states[itm.slot];
         if (!step_valid(rec, st) || st.T == 0) continue;
         const double h = (rec.t_next - st.t) / fd.substeps;
         const uint64_t step = st.j + 1;
@@ -643,12 +780,12 @@ __global__ __launch_bounds__(TILE) void k_update(const uint32_t* items, int n_it
         const bool valid = n < fd.n;
         const int cur = st.cur, nxt = cur ^ 1;
         double l = -INFINITY;
-        double th[PMAX];
-        R x[DMAX];
+        double th[P];
+        R x[D];
 #pragma unroll
-        for (int i = 0; i < PMAX; ++i) th[i] = 0.0;
+        for (int i = 0; i < P; ++i) th[i] = 0.0;
 #pragma unroll
-        for (int i = 0; i < DMAX; ++i) x[i] = R(0);
+        for (int i = 0; i < D; ++i) x[i] = R(0);
         uint32_t iters = 0, fails = 0, nonf = 0;
         if (valid) {
             int k = fd.anc[n];
@@ -701,16 +838,9 @@ __global__ __launch_bounds__(TILE) void k_update(const uint32_t* items, int n_it
             if (!(l > -INFINITY) || bad) { l = -INFINITY; nonf = 1; }
             fd.logw[nxt][n] = l;
         }
-        const unsigned long long it_sum = block_sum_u64(iters, shu);
-        const unsigned long long fl_sum = block_sum_u64(fails, shu);
-        const unsigned long long nf_sum = block_sum_u64(nonf, shu);
-        if (threadIdx.x == 0) {
-            atomicAdd(&st.newton_upd, it_sum);
-            if (fl_sum) atomicAdd(&st.newton_fails, fl_sum);
-            if (nf_sum) atomicAdd(&st.nonfinite, nf_sum);
-        }
         // 6 (partials): tile moments with shift theta_bar_j
-        tile_moments<R, P, D>(l, valid, th, x, st.theta_bar, P, D,
+        tile_moments<R, P, D>(l, valid, th, x, st.theta_bar, P, D, pack_counts(iters, fails, nonf),
+                              fd.part1 + (size_t)itm.tile * PART1_STRIDE + 2,
                               fd.part2 + (size_t)itm.tile * fd.nacc, sh);
     }
 }
@@ -719,13 +849,30 @@ __global__ __launch_bounds__(TILE) void k_update(const uint32_t* items, int n_it
 // step 6: one workgroup per batch entry -- mean, covariance, ESS, Cholesky,
 // commit, and the step's status by ticket (device ring and host-mapped ring)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(TILE) void k_moments(const StepRec* recs, int count, const FilterDesc* descs,
-                                                  FilterState* states, int32_t* host_ring)
+// A step whose update did not run (all first-stage weights zero): its
+// predictor counters, from the first-stage partials.
+__device__ inline void add_predict_counts(const FilterDesc& fd, FilterState& st, double* sh)
+{
+    double ci = 0.0, cf = 0.0;
+    for (int t = threadIdx.x; t < fd.ntiles; t += TILE) {
+        ci += fd.part1[(size_t)t * PART1_STRIDE + 2];
+        cf += fd.part1[(size_t)t * PART1_STRIDE + 3];
+    }
+    ci = block_sum(ci, sh);
+    cf = block_sum(cf, sh);
+    if (threadIdx.x == 0) {
+        st.newton_pred += (unsigned long long)ci;
+        st.newton_fails += (unsigned long long)cf;
+    }
+}
+
+__global__ __launch_bounds__(TILE) void k_moments(Batch B, const FilterDesc* descs, FilterState* states,
+                                                  int32_t* host_ring)
 {
     __shared__ double sh[TILE];
     __shared__ double buf[STAGE_LEN];
-    for (int b = blockIdx.x; b < count; b += gridDim.x) {
-        const StepRec& rec = recs[b];
+    for (int b = blockIdx.x; b < B.count; b += gridDim.x) {
+        const StepRec rec = record(B, b);
         const int slot = uniform(rec.slot);
         const FilterDesc& fd = descs[slot];
         FilterState& st = states[slot];
@@ -733,6 +880,7 @@ __global__ __launch_bounds__(TILE) void k_moments(const StepRec* recs, int count
         if (!step_valid(rec, st)) {
             status = ST_EORDER;
         } else if (st.T == 0) {
+            add_predict_counts(fd, st, sh);
             status = ST_EDEGENERATE;
         } else {
             if (threadIdx.x == 0) {

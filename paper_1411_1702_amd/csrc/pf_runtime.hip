@@ -174,7 +174,7 @@ static pf_status prof_collect(pf_context* ctx);
 // ---------------------------------------------------------------------------
 // kernel dispatch by (model, precision, order)
 // ---------------------------------------------------------------------------
-typedef void (*StepKernel)(const uint32_t*, int, const StepRec*, const FilterDesc*, FilterState*);
+typedef void (*StepKernel)(Batch, const FilterDesc*, FilterState*);
 
 template <template <class> class Mdl, class R>
 static StepKernel pick_predict(int order)
@@ -234,7 +234,8 @@ static pf_status check_config(const pf_config* c)
     if (!(c->shrink_a > 0.0 && c->shrink_a < 1.0)) return fail(PF_EINVAL, "shrink_a must be in (0,1)");
     if (c->lmm != PF_LMM_BDF) return fail(PF_EINVAL, "only BDF is implemented");
     if (c->order < 1 || c->order > 3) return fail(PF_EINVAL, "order must be 1..3");
-    if (c->substeps < 1 || c->newton_max_iter < 1) return fail(PF_EINVAL, "substeps and newton_max_iter must be >= 1");
+    if (c->substeps < 1 || c->substeps > SUBSTEPS_MAX) return fail(PF_EINVAL, "substeps must be 1..65536");
+    if (c->newton_max_iter < 1 || c->newton_max_iter > KMAX_MAX) return fail(PF_EINVAL, "newton_max_iter must be 1..64");
     if (!(c->newton_rtol > 0.0)) return fail(PF_EINVAL, "newton_rtol must be > 0");
     if (c->precision != PF_PREC_FP64 && c->precision != PF_PREC_FP32_PROP) return fail(PF_EINVAL, "bad precision");
     for (uint32_t i = 0; i < c->p; ++i)
@@ -260,7 +261,7 @@ static void fill_static(FilterDesc& d, const pf_config* c)
     int cl = 0;
     while ((1ll << cl) < (long long)d.n) ++cl;
     d.shift = 62 - cl;
-    d.nacc = 3 + d.p + d.p * (d.p + 1) / 2 + d.d;
+    d.nacc = 3 + d.p + d.p * (d.p + 1) / 2 + d.d + NPLAIN;
     d.seed = c->seed;
     d.a = c->shrink_a;
     d.s = std::sqrt(1.0 - c->shrink_a * c->shrink_a);
@@ -301,7 +302,7 @@ static Layout layout_of(const FilterDesc& d)
     L.lg = take(np * 8);
     L.q = take(np * 8);
     L.anc = take(np * 4);
-    L.part1 = take((uint64_t)d.ntiles * 2 * 8);
+    L.part1 = take((uint64_t)d.ntiles * PART1_STRIDE * 8);
     L.tsum = take((uint64_t)d.ntiles * 8);
     L.part2 = take((uint64_t)d.ntiles * d.nacc * 8);
     L.total = o;
@@ -616,35 +617,54 @@ static pf_status submit(pf_context* ctx, uint32_t count, pf_filter* const* fs, c
         off += (int)kv.second.size();
     }
     const int n_all = off;
-    StepRec* d_recs = (StepRec*)sg.dev;
-    uint32_t* d_items = (uint32_t*)(sg.dev + rec_bytes);
     const bool timed = ctx->profiling;
+    // one filter: its record travels in the kernel arguments and nothing is
+    // copied ahead of the kernels; otherwise one copy of [recs | items]
+    const bool inline_rec = count == 1;
+    Batch all{};
+    all.count = (int32_t)count;
+    all.n_items = n_all;
+    if (inline_rec) {
+        all.one = recs[0];
+    } else {
+        all.recs = (const StepRec*)sg.dev;
+        all.items = (const uint32_t*)(sg.dev + rec_bytes);
+    }
+    auto part = [&](const Range& r) {
+        Batch b = all;
+        if (b.recs) b.items += r.off;
+        b.n_items = r.cnt;
+        return b;
+    };
 
-    // the step: one copy of [recs | items], then the kernel groups
+    // the step: the copy (batches only), then the kernel groups
     auto enqueue = [&]() -> hipError_t {
-        hipError_t e = hipMemcpyAsync(sg.dev, sg.host, rec_bytes + sizeof(uint32_t) * n_all,
-                                      hipMemcpyHostToDevice, ctx->stream);
-        if (e != hipSuccess) return e;
+        hipError_t e = hipSuccess;
+        if (!inline_rec) {
+            e = hipMemcpyAsync(sg.dev, sg.host, rec_bytes + sizeof(uint32_t) * n_all, hipMemcpyHostToDevice,
+                               ctx->stream);
+            if (e != hipSuccess) return e;
+        }
         if (timed && (e = hipEventRecord(sg.tev[0], ctx->stream)) != hipSuccess) return e;
         for (const Range& r : ranges) {
             const int model = r.cls / 8 + 1, prec = (r.cls % 8) / 4, order = r.cls % 4;
             hipLaunchKernelGGL(predict_kernel(model, prec, order), dim3(grid_for(ctx, r.cnt)), dim3(TILE), 0,
-                               ctx->stream, d_items + r.off, r.cnt, d_recs, ctx->d_desc, ctx->d_state);
+                               ctx->stream, part(r), ctx->d_desc, ctx->d_state);
         }
         if (timed && (e = hipEventRecord(sg.tev[1], ctx->stream)) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_count, dim3(grid_for(ctx, n_all)), dim3(TILE), 0, ctx->stream, d_items, n_all, d_recs,
-                           ctx->d_desc, ctx->d_state);
-        hipLaunchKernelGGL(k_scatter, dim3(grid_for(ctx, n_all)), dim3(TILE), 0, ctx->stream, d_items, n_all,
-                           d_recs, ctx->d_desc, ctx->d_state);
+        hipLaunchKernelGGL(k_count, dim3(grid_for(ctx, n_all)), dim3(TILE), 0, ctx->stream, all, ctx->d_desc,
+                           ctx->d_state);
+        hipLaunchKernelGGL(k_scatter, dim3(grid_for(ctx, n_all)), dim3(TILE), 0, ctx->stream, all, ctx->d_desc,
+                           ctx->d_state);
         if (timed && (e = hipEventRecord(sg.tev[2], ctx->stream)) != hipSuccess) return e;
         for (const Range& r : ranges) {
             const int model = r.cls / 8 + 1, prec = (r.cls % 8) / 4, order = r.cls % 4;
             hipLaunchKernelGGL(update_kernel(model, prec, order), dim3(grid_for(ctx, r.cnt)), dim3(TILE), 0,
-                               ctx->stream, d_items + r.off, r.cnt, d_recs, ctx->d_desc, ctx->d_state);
+                               ctx->stream, part(r), ctx->d_desc, ctx->d_state);
         }
         if (timed && (e = hipEventRecord(sg.tev[3], ctx->stream)) != hipSuccess) return e;
         hipLaunchKernelGGL(k_moments, dim3(std::min<uint32_t>(count, (uint32_t)ctx->grid_cap)), dim3(TILE), 0,
-                           ctx->stream, d_recs, (int)count, ctx->d_desc, ctx->d_state, ctx->d_ring);
+                           ctx->stream, all, ctx->d_desc, ctx->d_state, ctx->d_ring);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if (timed && (e = hipEventRecord(sg.tev[4], ctx->stream)) != hipSuccess) return e;
         return hipSuccess;
@@ -652,8 +672,9 @@ static pf_status submit(pf_context* ctx, uint32_t count, pf_filter* const* fs, c
 
     bool launched = false;
     // profiled submissions launch directly: their events then bracket the
-    // kernels themselves
-    if (ctx->use_graphs && !timed) {
+    // kernels themselves.  A single filter's step launches directly too: its
+    // record is in the kernel arguments, which a graph would freeze.
+    if (ctx->use_graphs && !timed && !inline_rec) {
         auto it = ctx->graphs.find(sig);
         if (it == ctx->graphs.end() && ++ctx->seen[sig] >= 2) {
             // a repeated batch shape: capture it once and replay it afterwards
@@ -966,8 +987,13 @@ extern "C" pf_status pf_test_resample(uint64_t n, const double* g, uint64_t r, i
     if (e == hipSuccess) e = hipMemcpyAsync(di, items.data(), 4 * items.size(), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) {
         const unsigned grid = (unsigned)std::min(d.ntiles, 2048);
-        hipLaunchKernelGGL(k_count, dim3(grid), dim3(TILE), 0, st, di, d.ntiles, dr, dd, ds);
-        hipLaunchKernelGGL(k_scatter, dim3(grid), dim3(TILE), 0, st, di, d.ntiles, dr, dd, ds);
+        Batch bt{};
+        bt.recs = dr;
+        bt.items = di;
+        bt.n_items = d.ntiles;
+        bt.count = 1;
+        hipLaunchKernelGGL(k_count, dim3(grid), dim3(TILE), 0, st, bt, dd, ds);
+        hipLaunchKernelGGL(k_scatter, dim3(grid), dim3(TILE), 0, st, bt, dd, ds);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipMemcpyAsync(&hs, ds, sizeof(hs), hipMemcpyDeviceToHost, st);
@@ -1007,11 +1033,16 @@ __global__ void k_test_set(const FilterDesc* descs, const FilterState* states, i
 }
 }  // namespace pf
 
+// The filter-based test entry points run on the context's own stream, which
+// does not wait for the caller's streams: they first wait for the whole
+// device, so the caller's buffers are ready (e.g. still being cleared on
+// another stream) before the library writes or reads them.
 extern "C" pf_status pf_test_get_ensemble(pf_filter* f, double* x, double* theta, double* logw)
 {
     if (!f) return fail(PF_EINVAL, "NULL filter");
     pf_context* ctx = f->ctx;
     HIP_TRY(hipSetDevice(ctx->device));
+    HIP_TRY(hipDeviceSynchronize());
     pf_status s = drain(f, f->next_seq - 1);
     if (s != PF_OK) return s;
     const unsigned g = (unsigned)((f->desc.n + 255) / 256);
@@ -1044,6 +1075,7 @@ extern "C" pf_status pf_test_set_ensemble(pf_filter* f, const double* x, const d
     if (!f || !x || !theta || !logw || !theta_bar || !L) return fail(PF_EINVAL, "NULL argument");
     pf_context* ctx = f->ctx;
     HIP_TRY(hipSetDevice(ctx->device));
+    HIP_TRY(hipDeviceSynchronize());
     pf_status s = drain(f, f->next_seq - 1);
     if (s != PF_OK) return s;
     const unsigned g = (unsigned)((f->desc.n + 255) / 256);
@@ -1072,6 +1104,7 @@ extern "C" pf_status pf_test_last_ancestors(pf_filter* f, int32_t* anc)
 {
     if (!f || !anc) return fail(PF_EINVAL, "NULL argument");
     HIP_TRY(hipSetDevice(f->ctx->device));
+    HIP_TRY(hipDeviceSynchronize());
     pf_status s = drain(f, f->next_seq - 1);
     if (s != PF_OK) return s;
     HIP_TRY(hipMemcpyAsync(anc, f->desc.anc, sizeof(int32_t) * f->desc.n, hipMemcpyDeviceToDevice, f->ctx->stream));

@@ -11,9 +11,19 @@ constexpr int DMAX = 16;       // largest state dimension
 constexpr int PMAX = 12;       // largest parameter dimension
 constexpr int MMAX = 4;        // largest number of observed components
 constexpr int RING = 64;       // per-filter status ring (steps in flight)
-// moment accumulators per tile: s0, s00, sum w (theta - c), sum w (theta-c)(theta-c)^T
-// (upper triangle), sum w x, and the tile's max log-weight
-constexpr int NACC_MAX = 3 + PMAX + PMAX * (PMAX + 1) / 2 + DMAX;
+// per-tile first-stage partials: tile max, sum exp, Newton iterations and
+// failed solves of the predictor
+constexpr int PART1_STRIDE = 4;
+// counter columns at the end of each moment-partial row (summed unscaled):
+// update iterations, failed solves (both kernels), non-finite weights,
+// predictor iterations
+constexpr int NPLAIN = 4;
+constexpr int SUBSTEPS_MAX = 65536;
+constexpr int KMAX_MAX = 64;
+// moment accumulators per tile: the tile's max log-weight, s0, s00,
+// sum w (theta - c), sum w (theta-c)(theta-c)^T (upper triangle), sum w x,
+// and the NPLAIN counters
+constexpr int NACC_MAX = 3 + PMAX + PMAX * (PMAX + 1) / 2 + DMAX + NPLAIN;
 
 enum Status : int32_t {
     ST_OK = 0, ST_EINVAL = 1, ST_ENOMEM = 2, ST_EADMIT = 3, ST_EDEGENERATE = 4,
@@ -51,9 +61,9 @@ struct FilterDesc {
     double* lg;                         // [npad] first-stage log-weights
     uint64_t* q;                        // [npad] scaled integer weights
     int32_t* anc;                       // [npad] ancestors
-    double* part1;                      // [ntiles][2] (max, sum exp)
+    double* part1;                      // [ntiles][PART1_STRIDE] (max, sum exp, iterations, fails)
     uint64_t* tsum;                     // [ntiles] integer weight per tile (then offsets)
-    double* part2;                      // [ntiles][nacc] moment partials
+    double* part2;                      // [ntiles][nacc] moment partials and counters
 };
 
 // Dynamic state of one filter (device resident, updated by the kernels).
@@ -81,6 +91,18 @@ struct StepRec {
     uint64_t seq;
     double t_next;
     double y[MMAX], sigma[MMAX];
+};
+
+// Where the step kernels find their batch (passed by value as a kernel
+// argument).  A batch of one filter carries its record here and needs no
+// copy ahead of the kernels: item i is tile i.  Larger batches point at the
+// device copy of the records and of the (entry << 16 | tile) item list.
+struct Batch {
+    const StepRec* recs;       // nullptr: the single record `one`
+    const uint32_t* items;     // unused when recs is nullptr
+    int32_t n_items;           // tiles this launch covers
+    int32_t count;             // batch entries
+    StepRec one;
 };
 
 }  // namespace pf

@@ -65,10 +65,15 @@ def test_bad_configs_rejected_on_host():
     prob = inputs.robertson(100, 5)
     for mutate in (lambda c: setattr(c.c, "order", 4), lambda c: setattr(c.c, "shrink_a", 1.0),
                    lambda c: setattr(c.c, "n_particles", 0), lambda c: setattr(c.c, "d", 4),
-                   lambda c: setattr(c.c, "struct_size", 8), lambda c: setattr(c.c, "m", 0)):
+                   lambda c: setattr(c.c, "struct_size", 8), lambda c: setattr(c.c, "m", 0),
+                   lambda c: setattr(c.c, "substeps", 65537), lambda c: setattr(c.c, "newton_max_iter", 65)):
         cfg = pf.Config(prob)
         mutate(cfg)
         assert L.pf_filter_bytes(cfg.ptr()) == 0
+    # the largest accepted sizes (the packed Newton counters are sized for them)
+    cfg = pf.Config(prob)
+    cfg.c.substeps, cfg.c.newton_max_iter = 65536, 64
+    assert L.pf_filter_bytes(cfg.ptr()) > 0
 
 
 def test_product_never_loads_the_oracle():
