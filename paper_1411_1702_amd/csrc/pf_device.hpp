@@ -21,13 +21,28 @@ struct Philox {
     static constexpr uint64_t kWeylA = 0x9E3779B97F4A7C15ULL;
     static constexpr uint64_t kWeylB = 0xBB67AE8584CAA73BULL;
 
+    // full 64x64 -> 128-bit product from four 32x32 -> 64 partial products
+    // (each one multiply-add with a 64-bit addend), sharing the partial
+    // products between the low and the high word
+    __device__ static inline void mulhilo(uint64_t m, uint64_t a, uint64_t& lo, uint64_t& hi)
+    {
+        const uint32_t ml = (uint32_t)m, mh = (uint32_t)(m >> 32);
+        const uint32_t al = (uint32_t)a, ah = (uint32_t)(a >> 32);
+        const uint64_t p0 = (uint64_t)ml * al;
+        const uint64_t p1 = (uint64_t)mh * al + (p0 >> 32);
+        const uint64_t p2 = (uint64_t)ml * ah + (uint32_t)p1;
+        hi = (uint64_t)mh * ah + (p1 >> 32) + (p2 >> 32);
+        lo = (p2 << 32) | (uint32_t)p0;
+    }
+
     __device__ static inline void block(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
                                         uint64_t k0, uint64_t k1, uint64_t out[4])
     {
 #pragma unroll
         for (int round = 0; round < 10; ++round) {
-            const uint64_t pa_lo = kMulA * c0, pa_hi = __umul64hi(kMulA, c0);
-            const uint64_t pb_lo = kMulB * c2, pb_hi = __umul64hi(kMulB, c2);
+            uint64_t pa_lo, pa_hi, pb_lo, pb_hi;
+            mulhilo(kMulA, c0, pa_lo, pa_hi);
+            mulhilo(kMulB, c2, pb_lo, pb_hi);
             const uint64_t n0 = pb_hi ^ c1 ^ k0;
             const uint64_t n2 = pa_hi ^ c3 ^ k1;
             c0 = n0;

@@ -208,6 +208,14 @@ static StepKernel update_kernel(int model, int prec, int order)
     return prec == PREC_FP32 ? pick_update<Chain16, float>(order) : pick_update<Chain16, double>(order);
 }
 
+typedef void (*InitKernel)(int, const FilterDesc*, FilterState*);
+static InitKernel init_kernel(int model, int prec)
+{
+    if (model == MODEL_ROBERTSON)
+        return prec == PREC_FP32 ? k_init<Robertson<float>, float> : k_init<Robertson<double>, double>;
+    return prec == PREC_FP32 ? k_init<Chain16<float>, float> : k_init<Chain16<double>, double>;
+}
+
 static int class_of(const FilterDesc& d) { return (d.model - 1) * 8 + d.prec * 4 + d.order; }
 
 // ---------------------------------------------------------------------------
@@ -470,10 +478,8 @@ extern "C" pf_status pf_create(pf_context* ctx, const pf_config* cfg, pf_filter*
         hipMemsetAsync(f->desc.anc, 0, sizeof(int32_t) * (size_t)f->desc.npad, ctx->init_stream) != hipSuccess)
         return cleanup(fail(PF_EDEVICE, "upload of filter descriptor failed"));
     const unsigned grid = grid_for(ctx, f->desc.ntiles);
-    if (f->desc.prec == PREC_FP32)
-        hipLaunchKernelGGL(k_init<float>, dim3(grid), dim3(TILE), 0, ctx->init_stream, f->slot, ctx->d_desc, ctx->d_state);
-    else
-        hipLaunchKernelGGL(k_init<double>, dim3(grid), dim3(TILE), 0, ctx->init_stream, f->slot, ctx->d_desc, ctx->d_state);
+    hipLaunchKernelGGL(init_kernel(f->desc.model, f->desc.prec), dim3(grid), dim3(TILE), 0, ctx->init_stream, f->slot,
+                       ctx->d_desc, ctx->d_state);
     hipLaunchKernelGGL(k_init_moments, dim3(1), dim3(TILE), 0, ctx->init_stream, f->slot, ctx->d_desc, ctx->d_state);
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(ctx->init_stream) != hipSuccess)
         return cleanup(fail(PF_EDEVICE, "initialisation kernel failed"));
