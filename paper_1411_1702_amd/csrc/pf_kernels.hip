@@ -454,15 +454,41 @@ __device__ void tile_moments(double l, bool valid, const double* th, const R* x,
 // The factor overwrites a packed lower triangle of C (row i at i(i+1)/2).
 // Commits unless degenerate; `flip` switches to the new ensemble buffers and
 // advances the step counter.
+// State fields a moment pass reads, loaded before the tile combine so that
+// the loads overlap it (the moments kernel is one workgroup per filter and
+// latency bound).
+struct MomPre {
+    double tb[PMAX];
+    double t;
+    uint64_t j, T;
+    unsigned long long jit, n_pred, n_upd, n_fail, n_nonf;
+    int32_t cur;
+};
+template <int P>
+__device__ inline MomPre mom_prefetch(const FilterState& st)
+{
+    MomPre r;
+#pragma unroll
+    for (int i = 0; i < P; ++i) r.tb[i] = st.theta_bar[i];
+    r.t = st.t;
+    r.j = st.j;
+    r.T = st.T;
+    r.jit = st.jitters;
+    r.n_pred = st.newton_pred;
+    r.n_upd = st.newton_upd;
+    r.n_fail = st.newton_fails;
+    r.n_nonf = st.nonfinite;
+    r.cur = st.cur;
+    return r;
+}
+
 template <int P, int D>
-__device__ __forceinline__ void moments_tail(const double* tot, FilterState& st, bool flip)
+__device__ __forceinline__ int32_t moments_tail(const double* tot, const MomPre& pre, FilterState& st, bool flip,
+                                                double t_next)
 {
     constexpr int NT = P * (P + 1) / 2;
     const double s0 = tot[0], s00 = tot[1];
-    if (!(s0 > 0.0) || !isfinite(s0)) {
-        st.status = ST_EDEGENERATE;
-        return;
-    }
+    if (!(s0 > 0.0) || !isfinite(s0)) return ST_EDEGENERATE;
     const double inv = 1.0 / s0;
     double dm[P];
 #pragma unroll
@@ -502,10 +528,7 @@ __device__ __forceinline__ void moments_tail(const double* tot, FilterState& st,
         }
         if (ok) jit = attempt;
     }
-    if (jit < 0) {
-        st.status = ST_EDEGENERATE;
-        return;
-    }
+    if (jit < 0) return ST_EDEGENERATE;
 #pragma unroll
     for (int i = 0; i < P; ++i) {
 #pragma unroll
@@ -515,39 +538,41 @@ __device__ __forceinline__ void moments_tail(const double* tot, FilterState& st,
         }
     }
 #pragma unroll
-    for (int i = 0; i < P; ++i) st.theta_bar[i] += dm[i];
+    for (int i = 0; i < P; ++i) st.theta_bar[i] = pre.tb[i] + dm[i];
 #pragma unroll
     for (int i = 0; i < D; ++i) st.state_mean[i] = tot[2 + P + NT + i] * inv;
     st.ess = s0 * s0 / s00;
-    st.jitters += (unsigned long long)jit;
+    st.jitters = pre.jit + (unsigned long long)jit;
     if (flip) {
-        st.cur ^= 1;
-        st.j = st.step;
-        st.t = st.t_next;
+        st.cur = pre.cur ^ 1;
+        st.j = pre.j + 1;
+        st.t = t_next;
     }
-    st.status = ST_OK;
+    return ST_OK;
 }
 
 constexpr int STAGE_LEN = 8192;   // doubles of LDS staging for the tile combine
 
-__device__ __forceinline__ void finalize_moments(const FilterDesc& fd, FilterState& st, bool flip, double* sh,
-                                                 double* buf)
+// Moment pass of one filter (one workgroup): the tile combine, then in lane
+// 0 the counters and the tail.  The combine only reads, so callers run it
+// before deciding whether the step commits.
+template <int P, int D>
+__device__ __forceinline__ void moments_combine(const FilterDesc& fd, double* tot, double* sh, double* buf)
 {
-    __shared__ double tot[NACC_MAX];
-    const int nsum = fd.nacc - 1;
-    constexpr int NA33 = 3 + 3 + 6 + 3 + NPLAIN;   // row length for p = d = 3
-    if (fd.nacc == NA33) combine_rows<NA33, NA33 - 1>(fd.part2, fd.ntiles, 1, NPLAIN, tot, sh);
-    else combine_tiles(fd.part2, fd.nacc, fd.ntiles, nsum, tot, sh, 1, buf, STAGE_LEN, NPLAIN);
-    if (threadIdx.x == 0) {
-        const double* c = tot + nsum - NPLAIN;
-        st.newton_upd += (unsigned long long)c[0];
-        st.newton_fails += (unsigned long long)c[1];
-        st.nonfinite += (unsigned long long)c[2];
-        st.newton_pred += (unsigned long long)c[3];
-        if (fd.p == 3 && fd.d == 3) moments_tail<3, 3>(tot, st, flip);
-        else moments_tail<PMAX, DMAX>(tot, st, flip);
-    }
-    __syncthreads();
+    constexpr int NA = 1 + 2 + P + P * (P + 1) / 2 + D + NPLAIN;
+    if constexpr (NA * 8 <= 256) combine_rows<NA, NA - 1>(fd.part2, fd.ntiles, 1, NPLAIN, tot, sh);
+    else combine_tiles(fd.part2, fd.nacc, fd.ntiles, fd.nacc - 1, tot, sh, 1, buf, STAGE_LEN, NPLAIN);
+}
+template <int P, int D>
+__device__ __forceinline__ int32_t moments_finish(const FilterDesc& fd, const double* tot, const MomPre& pre,
+                                                  FilterState& st, bool flip, double t_next)
+{
+    const double* c = tot + fd.nacc - 1 - NPLAIN;
+    st.newton_upd = pre.n_upd + (unsigned long long)c[0];
+    st.newton_fails = pre.n_fail + (unsigned long long)c[1];
+    st.nonfinite = pre.n_nonf + (unsigned long long)c[2];
+    st.newton_pred = pre.n_pred + (unsigned long long)c[3];
+    return moments_tail<P, D>(tot, pre, st, flip, t_next);
 }
 
 // ---------------------------------------------------------------------------
@@ -561,23 +586,38 @@ struct Item {
 // lets the compiler use scalar loads for every descriptor field
 __device__ inline int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-__device__ inline StepRec record(const Batch& B, int b) { return B.recs ? B.recs[b] : B.one; }
+// INL: the inline (single-filter) form of the batch, a compile-time choice
+// so that every record and descriptor read is a scalar load
+template <bool INL>
+__device__ inline StepRec record(const Batch& B, int b)
+{
+    if constexpr (INL) return B.one;
+    else return B.recs[b];
+}
 
+template <bool INL>
 __device__ inline Item fetch(const Batch& B, int itx)
 {
     Item r;
-    if (B.recs) {
+    if constexpr (INL) {
+        r.b = 0;
+        r.tile = itx;
+        r.rec = B.one;
+    } else {
         const uint32_t it = (uint32_t)uniform((int)B.items[itx]);
         r.b = (int)(it >> 16);
         r.tile = (int)(it & 0xFFFFu);
         r.rec = B.recs[r.b];
-    } else {
-        r.b = 0;
-        r.tile = itx;
-        r.rec = B.one;
     }
     r.slot = uniform(r.rec.slot);
     return r;
+}
+
+template <bool INL>
+__device__ inline const FilterDesc& desc_of(const Batch& B, const FilterDesc* descs, int slot)
+{
+    if constexpr (INL) return B.fd;
+    else return descs[slot];
 }
 
 // The step of batch entry b may run: its observation time is after the
@@ -626,26 +666,33 @@ __global__ __launch_bounds__(TILE) void k_init(int slot, const FilterDesc* descs
 
 // one workgroup: moments of the prior draw (the shift is the prior mean, which
 // the host stored as theta_bar)
+template <class Model>
 __global__ __launch_bounds__(TILE) void k_init_moments(int slot, const FilterDesc* descs, FilterState* states)
 {
+    constexpr int P = Model::P, D = Model::D;
     __shared__ double sh[TILE];
     __shared__ double buf[STAGE_LEN];
-    finalize_moments(descs[slot], states[slot], false, sh, buf);
+    __shared__ double tot[NACC_MAX];
+    const FilterDesc& fd = descs[slot];
+    FilterState& st = states[slot];
+    const MomPre pre = mom_prefetch<P>(st);
+    moments_combine<P, D>(fd, tot, sh, buf);
+    if (threadIdx.x == 0) st.status = moments_finish<P, D>(fd, tot, pre, st, false, pre.t);
 }
 
 // ---------------------------------------------------------------------------
 // steps 2 and 3(a): shrink, predictor, first-stage log-weights
 // ---------------------------------------------------------------------------
-template <class Model, class R, int KORD>
+template <class Model, class R, int KORD, bool INL>
 __global__ __launch_bounds__(TILE) void k_predict(Batch B, const FilterDesc* descs, FilterState* states)
 {
     constexpr int D = Model::D, P = Model::P;
     __shared__ double sh[TILE];
     __shared__ unsigned long long wcnt[NWAVE];
     for (int itx = blockIdx.x; itx < B.n_items; itx += gridDim.x) {
-        const Item itm = fetch(B, itx);
+        const Item itm = fetch<INL>(B, itx);
         const StepRec& rec = itm.rec;
-        const FilterDesc& fd = descs[itm.slot];
+        const FilterDesc& fd = desc_of<INL>(B, descs, itm.slot);
         const FilterState& st = states[itm.slot];
         if (!step_valid(rec, st)) continue;
         const double h = (rec.t_next - st.t) / fd.substeps;
@@ -703,18 +750,22 @@ __global__ __launch_bounds__(TILE) void k_predict(Batch B, const FilterDesc* des
 // ---------------------------------------------------------------------------
 // step 3(b): systematic resampling in integers
 // ---------------------------------------------------------------------------
+template <bool INL>
 __global__ __launch_bounds__(TILE) void k_count(Batch B, const FilterDesc* descs, FilterState* states)
 {
     __shared__ double sh[TILE];
     __shared__ double tot[1];
     __shared__ unsigned long long shu[NWAVE];
     for (int itx = blockIdx.x; itx < B.n_items; itx += gridDim.x) {
-        const Item itm = fetch(B, itx);
-        const FilterDesc& fd = descs[itm.slot];
+        const Item itm = fetch<INL>(B, itx);
+        const FilterDesc& fd = desc_of<INL>(B, descs, itm.slot);
         const FilterState& st = states[itm.slot];
-        if (!fd.g_direct && !step_valid(itm.rec, st)) continue;
+        // every load is issued before anything waits: the lane's log-weight,
+        // the filter time (the step's validity only gates the stores), and
+        // the tile partials of the combine
         const int n = itm.tile * TILE + threadIdx.x;
-        const double l = n < fd.n ? fd.lg[n] : -INFINITY;   // in flight during the combine
+        const double l = n < fd.n ? fd.lg[n] : -INFINITY;
+        const double t_cur = st.t;
         double M = 0.0, S = 1.0;
         if (!fd.g_direct) {
             // the filter's first-stage log-sum-exp, from the tile partials
@@ -726,9 +777,10 @@ __global__ __launch_bounds__(TILE) void k_count(Batch B, const FilterDesc* descs
         if (n < fd.n) {
             const double g = fd.g_direct ? l : (ok && l > -INFINITY ? exp(l - M) / S : 0.0);
             if (g > 0.0) q = (unsigned long long)floor(ldexp(g, fd.shift));
-            fd.q[n] = q;
         }
         const unsigned long long ts = block_sum_u64(q, shu);
+        if (!fd.g_direct && !(itm.rec.t_next > t_cur)) continue;   // the step does not run
+        if (n < fd.n) fd.q[n] = q;
         if (threadIdx.x == 0) fd.tsum[itm.tile] = ts;
     }
 }
@@ -748,6 +800,7 @@ __device__ inline uint64_t first_slot(uint64_t c, uint64_t N, uint64_t T, uint64
 // by the whole workgroup
 constexpr uint64_t LONG_RUN = 16;
 
+template <bool INL>
 __global__ __launch_bounds__(TILE) void k_scatter(Batch B, const FilterDesc* descs, FilterState* states)
 {
     __shared__ unsigned long long shu[2 * NWAVE];
@@ -755,21 +808,15 @@ __global__ __launch_bounds__(TILE) void k_scatter(Batch B, const FilterDesc* des
     __shared__ uint32_t run_lo[TILE], run_hi[TILE];
     __shared__ int run_k[TILE];
     for (int itx = blockIdx.x; itx < B.n_items; itx += gridDim.x) {
-        const Item itm = fetch(B, itx);
-        const FilterDesc& fd = descs[itm.slot];
+        const Item itm = fetch<INL>(B, itx);
+        const FilterDesc& fd = desc_of<INL>(B, descs, itm.slot);
         FilterState& st = states[itm.slot];
-        if (!fd.g_direct && !step_valid(itm.rec, st)) continue;
-        // this lane's weight and the systematic draw, ahead of the tile scan
+        // loads first: this lane's weight, the filter state, the tile sums
+        // (the step's validity only gates the stores)
         const int n = itm.tile * TILE + threadIdx.x;
         const unsigned long long q = n < fd.n ? fd.q[n] : 0ull;
-        uint64_t r;
-        if (fd.g_direct) {
-            r = st.V;   // test mode: the uniform word was stored by the host
-        } else {
-            uint64_t w[4];
-            Philox::block(st.j + 1, 0, PUR_RESAMPLE, 0, fd.seed, 0, w);
-            r = w[0];
-        }
+        const double t_cur = st.t;
+        const uint64_t j_cur = st.j, v_test = st.V;
         // exclusive offset of this tile and total T of the integer weights
         unsigned long long pre = 0, all = 0;
         for (int t = threadIdx.x; t < fd.ntiles; t += TILE) {
@@ -777,8 +824,17 @@ __global__ __launch_bounds__(TILE) void k_scatter(Batch B, const FilterDesc* des
             all += v;
             if (t < itm.tile) pre += v;
         }
+        uint64_t r;
+        if (fd.g_direct) {
+            r = v_test;   // test mode: the uniform word was stored by the host
+        } else {
+            uint64_t w[4];
+            Philox::block(j_cur + 1, 0, PUR_RESAMPLE, 0, fd.seed, 0, w);
+            r = w[0];
+        }
         unsigned long long T;
         block_sum2_u64(pre, all, shu, pre, T);
+        if (!fd.g_direct && !(itm.rec.t_next > t_cur)) continue;   // the step does not run
         const uint64_t V = T ? __umul64hi(r, T) : 0;
         if (itm.tile == 0 && threadIdx.x == 0) {
             st.T = T;
@@ -813,21 +869,22 @@ __global__ __launch_bounds__(TILE) void k_scatter(Batch B, const FilterDesc* des
 // ---------------------------------------------------------------------------
 // steps 3(c)-5 per output slot
 // ---------------------------------------------------------------------------
-template <class Model, class R, int KORD>
+template <class Model, class R, int KORD, bool INL>
 __global__ __launch_bounds__(TILE) void k_update(Batch B, const FilterDesc* descs, FilterState* states)
 {
     constexpr int D = Model::D, P = Model::P;
     __shared__ double sh[TILE];
     for (int itx = blockIdx.x; itx < B.n_items; itx += gridDim.x) {
-        const Item itm = fetch(B, itx);
+        const Item itm = fetch<INL>(B, itx);
         const StepRec& rec = itm.rec;
-        const FilterDesc& fd = descs[itm.slot];
+        const FilterDesc& fd = desc_of<INL>(B, descs, itm.slot);
         const FilterState& st = states[itm.slot];
+        const int n = itm.tile * TILE + threadIdx.x;
+        const bool valid = n < fd.n;
+        const int k_anc = valid ? fd.anc[n] : 0;   // issued before the state checks wait
         if (!step_valid(rec, st) || st.T == 0) continue;
         const double h = (rec.t_next - st.t) / fd.substeps;
         const uint64_t step = st.j + 1;
-        const int n = itm.tile * TILE + threadIdx.x;
-        const bool valid = n < fd.n;
         const int cur = st.cur, nxt = cur ^ 1;
         double l = -INFINITY;
         double th[P];
@@ -838,7 +895,7 @@ __global__ __launch_bounds__(TILE) void k_update(Batch B, const FilterDesc* desc
         for (int i = 0; i < D; ++i) x[i] = R(0);
         uint32_t iters = 0, fails = 0, nonf = 0;
         if (valid) {
-            int k = fd.anc[n];
+            int k = k_anc;
             // the scatter covers every slot exactly once; an out-of-range
             // ancestor would be a bug: keep the read in bounds, zero the weight
             const bool bad = k < 0 || k >= fd.n;
@@ -916,32 +973,43 @@ __device__ inline void add_predict_counts(const FilterDesc& fd, FilterState& st,
     }
 }
 
+template <int P, int D>
+__device__ __forceinline__ int32_t moment_step(const FilterDesc& fd, FilterState& st, const StepRec& rec, double* sh,
+                                               double* buf, double* tot)
+{
+    const MomPre pre = mom_prefetch<P>(st);
+    moments_combine<P, D>(fd, tot, sh, buf);   // reads only: runs ahead of the checks
+    __shared__ int32_t status;
+    if (!(rec.t_next > pre.t)) return ST_EORDER;
+    if (pre.T == 0) {
+        add_predict_counts(fd, st, sh);
+        return ST_EDEGENERATE;
+    }
+    if (threadIdx.x == 0) {
+        st.step = pre.j + 1;
+        st.t_next = rec.t_next;
+        status = moments_finish<P, D>(fd, tot, pre, st, true, rec.t_next);
+    }
+    __syncthreads();
+    return status;
+}
+
+template <bool INL>
 __global__ __launch_bounds__(TILE) void k_moments(Batch B, const FilterDesc* descs, FilterState* states,
                                                   int32_t* host_ring)
 {
     __shared__ double sh[TILE];
     __shared__ double buf[STAGE_LEN];
+    __shared__ double tot[NACC_MAX];
     for (int b = blockIdx.x; b < B.count; b += gridDim.x) {
-        const StepRec rec = record(B, b);
+        const StepRec rec = record<INL>(B, b);
         const int slot = uniform(rec.slot);
-        const FilterDesc& fd = descs[slot];
+        const FilterDesc& fd = desc_of<INL>(B, descs, slot);
         FilterState& st = states[slot];
-        int32_t status;
-        if (!step_valid(rec, st)) {
-            status = ST_EORDER;
-        } else if (st.T == 0) {
-            add_predict_counts(fd, st, sh);
-            status = ST_EDEGENERATE;
-        } else {
-            if (threadIdx.x == 0) {
-                st.step = st.j + 1;
-                st.t_next = rec.t_next;
-            }
-            __syncthreads();
-            finalize_moments(fd, st, true, sh, buf);
-            status = st.status;
-        }
-        __syncthreads();
+        using RB = Robertson<double>;
+        using CH = Chain16<double>;
+        const int32_t status = fd.model == MODEL_ROBERTSON ? moment_step<RB::P, RB::D>(fd, st, rec, sh, buf, tot)
+                                                           : moment_step<CH::P, CH::D>(fd, st, rec, sh, buf, tot);
         if (threadIdx.x == 0) {
             st.status = status;
             st.ring[rec.seq % RING] = status;

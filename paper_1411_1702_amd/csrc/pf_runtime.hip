@@ -175,37 +175,41 @@ static pf_status prof_collect(pf_context* ctx);
 // kernel dispatch by (model, precision, order)
 // ---------------------------------------------------------------------------
 typedef void (*StepKernel)(Batch, const FilterDesc*, FilterState*);
+typedef void (*MomentsKernel)(Batch, const FilterDesc*, FilterState*, int32_t*);
 
-template <template <class> class Mdl, class R>
+template <template <class> class Mdl, class R, bool INL>
 static StepKernel pick_predict(int order)
 {
     switch (order) {
-    case 1: return k_predict<Mdl<R>, R, 1>;
-    case 2: return k_predict<Mdl<R>, R, 2>;
-    default: return k_predict<Mdl<R>, R, 3>;
+    case 1: return k_predict<Mdl<R>, R, 1, INL>;
+    case 2: return k_predict<Mdl<R>, R, 2, INL>;
+    default: return k_predict<Mdl<R>, R, 3, INL>;
     }
 }
-template <template <class> class Mdl, class R>
+template <template <class> class Mdl, class R, bool INL>
 static StepKernel pick_update(int order)
 {
     switch (order) {
-    case 1: return k_update<Mdl<R>, R, 1>;
-    case 2: return k_update<Mdl<R>, R, 2>;
-    default: return k_update<Mdl<R>, R, 3>;
+    case 1: return k_update<Mdl<R>, R, 1, INL>;
+    case 2: return k_update<Mdl<R>, R, 2, INL>;
+    default: return k_update<Mdl<R>, R, 3, INL>;
     }
 }
-
+template <bool INL>
 static StepKernel predict_kernel(int model, int prec, int order)
 {
     if (model == MODEL_ROBERTSON)
-        return prec == PREC_FP32 ? pick_predict<Robertson, float>(order) : pick_predict<Robertson, double>(order);
-    return prec == PREC_FP32 ? pick_predict<Chain16, float>(order) : pick_predict<Chain16, double>(order);
+        return prec == PREC_FP32 ? pick_predict<Robertson, float, INL>(order)
+                                 : pick_predict<Robertson, double, INL>(order);
+    return prec == PREC_FP32 ? pick_predict<Chain16, float, INL>(order) : pick_predict<Chain16, double, INL>(order);
 }
+template <bool INL>
 static StepKernel update_kernel(int model, int prec, int order)
 {
     if (model == MODEL_ROBERTSON)
-        return prec == PREC_FP32 ? pick_update<Robertson, float>(order) : pick_update<Robertson, double>(order);
-    return prec == PREC_FP32 ? pick_update<Chain16, float>(order) : pick_update<Chain16, double>(order);
+        return prec == PREC_FP32 ? pick_update<Robertson, float, INL>(order)
+                                 : pick_update<Robertson, double, INL>(order);
+    return prec == PREC_FP32 ? pick_update<Chain16, float, INL>(order) : pick_update<Chain16, double, INL>(order);
 }
 
 typedef void (*InitKernel)(int, const FilterDesc*, FilterState*);
@@ -480,7 +484,8 @@ extern "C" pf_status pf_create(pf_context* ctx, const pf_config* cfg, pf_filter*
     const unsigned grid = grid_for(ctx, f->desc.ntiles);
     hipLaunchKernelGGL(init_kernel(f->desc.model, f->desc.prec), dim3(grid), dim3(TILE), 0, ctx->init_stream, f->slot,
                        ctx->d_desc, ctx->d_state);
-    hipLaunchKernelGGL(k_init_moments, dim3(1), dim3(TILE), 0, ctx->init_stream, f->slot, ctx->d_desc, ctx->d_state);
+    hipLaunchKernelGGL(f->desc.model == MODEL_ROBERTSON ? k_init_moments<Robertson<double>> : k_init_moments<Chain16<double>>,
+                       dim3(1), dim3(TILE), 0, ctx->init_stream, f->slot, ctx->d_desc, ctx->d_state);
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(ctx->init_stream) != hipSuccess)
         return cleanup(fail(PF_EDEVICE, "initialisation kernel failed"));
     int32_t status = 0;
@@ -632,6 +637,7 @@ static pf_status submit(pf_context* ctx, uint32_t count, pf_filter* const* fs, c
     all.n_items = n_all;
     if (inline_rec) {
         all.one = recs[0];
+        all.fd = fs[0]->desc;
     } else {
         all.recs = (const StepRec*)sg.dev;
         all.items = (const uint32_t*)(sg.dev + rec_bytes);
@@ -654,22 +660,29 @@ static pf_status submit(pf_context* ctx, uint32_t count, pf_filter* const* fs, c
         if (timed && (e = hipEventRecord(sg.tev[0], ctx->stream)) != hipSuccess) return e;
         for (const Range& r : ranges) {
             const int model = r.cls / 8 + 1, prec = (r.cls % 8) / 4, order = r.cls % 4;
-            hipLaunchKernelGGL(predict_kernel(model, prec, order), dim3(grid_for(ctx, r.cnt)), dim3(TILE), 0,
+            hipLaunchKernelGGL(inline_rec ? predict_kernel<true>(model, prec, order)
+                                          : predict_kernel<false>(model, prec, order),
+                               dim3(grid_for(ctx, r.cnt)), dim3(TILE), 0,
                                ctx->stream, part(r), ctx->d_desc, ctx->d_state);
         }
         if (timed && (e = hipEventRecord(sg.tev[1], ctx->stream)) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_count, dim3(grid_for(ctx, n_all)), dim3(TILE), 0, ctx->stream, all, ctx->d_desc,
+        hipLaunchKernelGGL(inline_rec ? k_count<true> : k_count<false>, dim3(grid_for(ctx, n_all)), dim3(TILE), 0,
+                           ctx->stream, all, ctx->d_desc,
                            ctx->d_state);
-        hipLaunchKernelGGL(k_scatter, dim3(grid_for(ctx, n_all)), dim3(TILE), 0, ctx->stream, all, ctx->d_desc,
+        hipLaunchKernelGGL(inline_rec ? k_scatter<true> : k_scatter<false>, dim3(grid_for(ctx, n_all)), dim3(TILE),
+                           0, ctx->stream, all, ctx->d_desc,
                            ctx->d_state);
         if (timed && (e = hipEventRecord(sg.tev[2], ctx->stream)) != hipSuccess) return e;
         for (const Range& r : ranges) {
             const int model = r.cls / 8 + 1, prec = (r.cls % 8) / 4, order = r.cls % 4;
-            hipLaunchKernelGGL(update_kernel(model, prec, order), dim3(grid_for(ctx, r.cnt)), dim3(TILE), 0,
+            hipLaunchKernelGGL(inline_rec ? update_kernel<true>(model, prec, order)
+                                          : update_kernel<false>(model, prec, order),
+                               dim3(grid_for(ctx, r.cnt)), dim3(TILE), 0,
                                ctx->stream, part(r), ctx->d_desc, ctx->d_state);
         }
         if (timed && (e = hipEventRecord(sg.tev[3], ctx->stream)) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_moments, dim3(std::min<uint32_t>(count, (uint32_t)ctx->grid_cap)), dim3(TILE), 0,
+        hipLaunchKernelGGL(inline_rec ? k_moments<true> : k_moments<false>,
+                           dim3(std::min<uint32_t>(count, (uint32_t)ctx->grid_cap)), dim3(TILE), 0,
                            ctx->stream, all, ctx->d_desc, ctx->d_state, ctx->d_ring);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if (timed && (e = hipEventRecord(sg.tev[4], ctx->stream)) != hipSuccess) return e;
@@ -998,8 +1011,8 @@ extern "C" pf_status pf_test_resample(uint64_t n, const double* g, uint64_t r, i
         bt.items = di;
         bt.n_items = d.ntiles;
         bt.count = 1;
-        hipLaunchKernelGGL(k_count, dim3(grid), dim3(TILE), 0, st, bt, dd, ds);
-        hipLaunchKernelGGL(k_scatter, dim3(grid), dim3(TILE), 0, st, bt, dd, ds);
+        hipLaunchKernelGGL(k_count<false>, dim3(grid), dim3(TILE), 0, st, bt, dd, ds);
+        hipLaunchKernelGGL(k_scatter<false>, dim3(grid), dim3(TILE), 0, st, bt, dd, ds);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipMemcpyAsync(&hs, ds, sizeof(hs), hipMemcpyDeviceToHost, st);

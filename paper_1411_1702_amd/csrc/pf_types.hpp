@@ -94,15 +94,19 @@ struct StepRec {
 };
 
 // Where the step kernels find their batch (passed by value as a kernel
-// argument).  A batch of one filter carries its record here and needs no
-// copy ahead of the kernels: item i is tile i.  Larger batches point at the
-// device copy of the records and of the (entry << 16 | tile) item list.
+// argument).  A batch of one filter carries its record and a copy of its
+// descriptor here (the kernels' inline form): nothing is copied ahead of the
+// kernels, item i is tile i, and the descriptor fields are read from the
+// kernel arguments without first looking up the slot.  Larger batches point
+// at the device copy of the records and of the (entry << 16 | tile) item
+// list, and read descriptors from the context's table.
 struct Batch {
-    const StepRec* recs;       // nullptr: the single record `one`
-    const uint32_t* items;     // unused when recs is nullptr
+    const StepRec* recs;       // nullptr in the inline form
+    const uint32_t* items;     // unused in the inline form
     int32_t n_items;           // tiles this launch covers
     int32_t count;             // batch entries
-    StepRec one;
+    StepRec one;               // inline form: the record
+    FilterDesc fd;             // inline form: the filter's descriptor
 };
 
 }  // namespace pf
