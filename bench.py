@@ -89,7 +89,8 @@ def time_path(pf, ctx, prob, prec, steps, warmup):
     run_steps(pf, f, prob, steps)
     times = {k: ctx.kernel_time(w) for k, w in
              (("step", pf.PF_TIME_STEP), ("predict", pf.PF_TIME_PREDICT),
-              ("resample", pf.PF_TIME_RESAMPLE), ("update", pf.PF_TIME_UPDATE))}
+              ("resample", pf.PF_TIME_RESAMPLE), ("update", pf.PF_TIME_UPDATE),
+              ("moments", pf.PF_TIME_MOMENTS))}
     ctx.profile(False)
     s1 = f.stats()
     f.close()

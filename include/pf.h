@@ -170,10 +170,13 @@ pf_status pf_stats(pf_filter* f, uint64_t* counters, uint32_t n);
  * pf_context_kernel_time waits for the recorded submissions and returns the
  * number of timed submissions and their summed milliseconds for one group:
  * PF_TIME_STEP (whole step), PF_TIME_PREDICT (step 2 and 3a kernels),
- * PF_TIME_RESAMPLE (step 3b kernels), PF_TIME_UPDATE (steps 3c-6 kernels).
+ * PF_TIME_RESAMPLE (step 3b kernels), PF_TIME_UPDATE (steps 3c-5 kernels,
+ * which also form the per-tile moment sums), PF_TIME_MOMENTS (step 6: the
+ * per-filter moments, Cholesky factor and commit).  Each interval lies between
+ * two events on the context's stream, so it includes one dispatch gap.
  * pf_context_profile(ctx, on) clears the totals.
  */
-enum { PF_TIME_STEP = 0, PF_TIME_PREDICT = 1, PF_TIME_RESAMPLE = 2, PF_TIME_UPDATE = 3 };
+enum { PF_TIME_STEP = 0, PF_TIME_PREDICT = 1, PF_TIME_RESAMPLE = 2, PF_TIME_UPDATE = 3, PF_TIME_MOMENTS = 4 };
 pf_status pf_context_profile(pf_context* ctx, int enable);
 pf_status pf_context_kernel_time(pf_context* ctx, int which, uint64_t* count, double* ms);
 

@@ -150,7 +150,7 @@ struct pf_context {
     std::vector<hipEvent_t> ev_pool;
     std::mutex ev_mu;                           // guards ev_pool
     uint64_t prof_count = 0;
-    double prof_ms[4] = {0, 0, 0, 0};
+    double prof_ms[5] = {0, 0, 0, 0, 0};
     std::map<std::string, GraphEntry> graphs;   // signature -> executable graph
     std::map<std::string, int> seen;            // signature -> submissions seen (capture on the 2nd)
     uint64_t use_clock = 0;
@@ -380,7 +380,10 @@ extern "C" pf_status pf_context_create(int device, uint64_t pool_bytes, void* hi
         HIP_TRY(hipMalloc(&ctx->stage[s].dev, sbytes));
         HIP_TRY(hipEventCreateWithFlags(&ctx->stage[s].ev, hipEventDisableTiming));
         HIP_TRY(hipEventRecord(ctx->stage[s].ev, ctx->stream));
-        for (int i = 0; i < 5; ++i) HIP_TRY(hipEventCreate(&ctx->stage[s].tev[i]));
+        // timing-only events: no system-scope cache flush when recorded, so
+        // an interval holds the kernels and their dispatch, not a flush
+        for (int i = 0; i < 5; ++i)
+            HIP_TRY(hipEventCreateWithFlags(&ctx->stage[s].tev[i], hipEventDisableSystemFence));
     }
     hipDeviceProp_t prop;
     HIP_TRY(hipGetDeviceProperties(&prop, device));
@@ -517,12 +520,13 @@ static pf_status stage_collect(pf_context* ctx, Stage& sg)
 {
     if (!sg.timed) return PF_OK;
     HIP_TRY(hipEventSynchronize(sg.tev[4]));
-    float ms[4];
+    float ms[5];
     HIP_TRY(hipEventElapsedTime(&ms[0], sg.tev[0], sg.tev[4]));
     HIP_TRY(hipEventElapsedTime(&ms[1], sg.tev[0], sg.tev[1]));
     HIP_TRY(hipEventElapsedTime(&ms[2], sg.tev[1], sg.tev[2]));
     HIP_TRY(hipEventElapsedTime(&ms[3], sg.tev[2], sg.tev[3]));
-    for (int i = 0; i < 4; ++i) ctx->prof_ms[i] += ms[i];
+    HIP_TRY(hipEventElapsedTime(&ms[4], sg.tev[3], sg.tev[4]));
+    for (int i = 0; i < 5; ++i) ctx->prof_ms[i] += ms[i];
     ctx->prof_count++;
     sg.timed = false;
     return PF_OK;
@@ -552,7 +556,7 @@ extern "C" pf_status pf_context_profile(pf_context* ctx, int enable)
 
 extern "C" pf_status pf_context_kernel_time(pf_context* ctx, int which, uint64_t* count, double* ms)
 {
-    if (!ctx || which < 0 || which > 3) return fail(PF_EINVAL, "bad argument");
+    if (!ctx || which < 0 || which > 4) return fail(PF_EINVAL, "bad argument");
     std::lock_guard<std::mutex> lk(ctx->mu);
     HIP_TRY(hipSetDevice(ctx->device));
     pf_status s = prof_collect(ctx);

@@ -19,7 +19,7 @@ PF_ENONFINITE, PF_EDEVICE, PF_EBUSY, PF_EORDER = 5, 6, 7, 8
 PF_MODEL_ROBERTSON, PF_MODEL_CHAIN16 = 1, 2
 PF_LMM_BDF = 0
 PF_PREC_FP64, PF_PREC_FP32_PROP = 0, 1
-PF_TIME_STEP, PF_TIME_PREDICT, PF_TIME_RESAMPLE, PF_TIME_UPDATE = 0, 1, 2, 3
+PF_TIME_STEP, PF_TIME_PREDICT, PF_TIME_RESAMPLE, PF_TIME_UPDATE, PF_TIME_MOMENTS = 0, 1, 2, 3, 4
 
 EXPORTS = [
     "pf_context_create", "pf_context_destroy", "pf_filter_bytes", "pf_context_memory",
