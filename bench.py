@@ -40,6 +40,39 @@ FLOPS = {
     inputs.MODEL_ROBERTSON: {"iter": 60, "sub_predict": 22, "sub_update": 47},
     inputs.MODEL_CHAIN: {"iter": 384, "sub_predict": 177, "sub_update": 305},
 }
+# HBM bytes of one k_update launch (Robertson, N = 2^17, FP32 propagation)
+# from two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE; KiB per dispatch),
+# each scaled by what the counter reads for a plain 1 GiB device copy in the
+# same run (FETCH_SIZE reads 524308 KiB for the copy's 1048576 KiB of reads:
+# x2.0; WRITE_SIZE reads 1048576: x1.0).  Keyed by a hash of the kernel
+# sources: once they change, the figure no longer applies and bench reports
+# null until the counters are taken again.
+TRAFFIC = {
+    "1619723d46498aa3": {"fetch_kib": 3439.4, "write_kib": 5720.0, "fetch_scale": 2.0, "write_scale": 1.0},
+}
+KERNEL_SOURCES = ("pf_kernels.hip", "pf_device.hpp", "pf_types.hpp")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1411_1702_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def update_traffic_bytes(prob):
+    """Counter-measured HBM bytes per k_update launch, or None when the
+    counters were not taken on this workload and these kernel sources."""
+    if prob.model != inputs.MODEL_ROBERTSON or prob.n_particles != 1 << 17:
+        return None
+    t = TRAFFIC.get(kernel_source_hash())
+    if t is None:
+        return None
+    return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
+
+
 # MI355X vector ALU peak: 256 CU x 4 SIMD x 16 lanes x 2 flop (fma) x 2.4 GHz
 PEAK_VALU_NONPACKED = 256 * 4 * 16 * 2 * 2.4e9 / 1e12      # 78.6 TFLOP/s (fp32 and fp64)
 PEAK_FP32_PUBLISHED = 157.3                                   # TFLOP/s, packed fp32
@@ -172,7 +205,9 @@ def single_filter(pf, args, prob):
         "achieved": achieved, "peak": PEAK_VALU_NONPACKED, "unit": "TFLOP/s",
         "frac": achieved / PEAK_VALU_NONPACKED,
         "frac_of_published_fp32": achieved / PEAK_FP32_PUBLISHED,
-        "traffic": None,
+        "traffic": update_traffic_bytes(prob),
+        "traffic_unit": "bytes per launch (HBM, counter-measured)",
+        "algorithmic_bytes": 92 * prob.n_particles,
         "avg_launch_ms": upd_ms,
         "flop_per_launch": r32["flop_update_per_launch"],
     }
@@ -316,6 +351,9 @@ def main():
                     choices=["robertson", "small", "chain", "batched", "serving"])
     ap.add_argument("--filters", type=int, default=256)
     ap.add_argument("--streams", type=int, default=2000)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first run one plain device-to-device copy of this many MiB (a known-size "
+                         "reference for the HBM byte counters of a profiler pass)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); independent filters shard "
@@ -327,6 +365,14 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.init()
+    if args.copy_probe_mib > 0:
+        n = args.copy_probe_mib << 20
+        src = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if args.config == "batched":
         out = batched(pf, args)
     elif args.config == "serving":
