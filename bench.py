@@ -99,9 +99,9 @@ def run_steps(pf, f, prob, steps):
 
 def time_path(pf, ctx, prob, prec, steps, warmup):
     """Warm up on one filter, time `steps` observation steps of a fresh one
-    (captured step graphs, no instrumentation), then repeat the same steps on
-    another fresh filter with HIP events between the kernel groups (direct
-    launches) for the per-kernel durations."""
+    (no instrumentation; the contract's timed region), time the same steps on
+    four more fresh filters (spread), then repeat them once more with timing
+    events between the kernel groups for the per-kernel durations."""
     import torch
     if warmup:
         fw = pf.Filter(ctx, pf.Config(prob, prec))
@@ -115,6 +115,16 @@ def time_path(pf, ctx, prob, prec, steps, warmup):
     t1 = time.perf_counter()
     post = f.posterior()
     f.close()
+    # four more passes of the same steps on fresh filters, for the spread
+    repeats = [1e3 * (t1 - t0) / steps]
+    for _ in range(4):
+        fr = pf.Filter(ctx, pf.Config(prob, prec))
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        run_steps(pf, fr, prob, steps)
+        torch.cuda.synchronize()
+        repeats.append(1e3 * (time.perf_counter() - a) / steps)
+        fr.close()
     # instrumented pass
     f = pf.Filter(ctx, pf.Config(prob, prec))
     s0 = f.stats()
@@ -138,6 +148,8 @@ def time_path(pf, ctx, prob, prec, steps, warmup):
         "wall_s": wall,
         "particle_steps_per_s": n * steps / wall,
         "ms_per_step": 1e3 * wall / steps,
+        "ms_per_step_5_passes": repeats,
+        "ms_per_step_median_of_5": float(np.median(repeats)),
         "kernel_ms": {k: v[1] / max(v[0], 1) for k, v in times.items()},
         "launches": times["update"][0],
         "newton_per_substep": (iters_upd + iters_pred) / (2.0 * steps * n * prob.substeps),
@@ -164,9 +176,22 @@ def latency(pf, ctx, prob, prec, count):
     return {"p50_ms": _percentile(lat, 50), "p99_ms": _percentile(lat, 99), "calls": count}
 
 
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(prob, target_s):
     """The FP64 oracle on the host cores: the first S observation steps of the
-    same workload, S chosen so the sample takes about target_s seconds."""
+    same workload, S chosen so the sample takes about target_s seconds.  The
+    first two steps are also timed on one thread, for the speedup
+    S_P = T_1 / T_P and efficiency E_P = S_P / P of the OpenMP run."""
     from oracle import oracle as O
     O.lib()
     threads = O.num_threads()
@@ -175,16 +200,76 @@ def cpu_baseline(prob, target_s):
     F.step(prob.times[0], prob.y[0], prob.sigma[0])
     one = time.perf_counter() - t0
     S = 1
+    t_two = None
     while S < prob.T and (time.perf_counter() - t0) + one < target_s:
         out = F.step(prob.times[S], prob.y[S], prob.sigma[S])
+        if S == 1:
+            t_two = time.perf_counter() - t0
         if out["status"]:
             break
         S += 1
     el = time.perf_counter() - t0
-    return {"value": prob.n_particles * S / el, "unit": "particle-steps/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"first {S} of {prob.T} observation steps at N={prob.n_particles} "
-                      f"(FP64 C oracle, OpenMP over particles, {el:.1f} s)"}
+    res = {"value": prob.n_particles * S / el, "unit": "particle-steps/s", "cores": threads,
+           "kind": "oracle", "cpu_model": _cpu_model(),
+           "sample": f"first {S} of {prob.T} observation steps at N={prob.n_particles} "
+                     f"(FP64 C oracle, OpenMP over particles, {el:.1f} s)"}
+    if t_two is not None and threads > 1:
+        O.set_threads(1)
+        F1 = O.Filter(prob)
+        a = time.perf_counter()
+        F1.step(prob.times[0], prob.y[0], prob.sigma[0])
+        F1.step(prob.times[1], prob.y[1], prob.sigma[1])
+        t1 = time.perf_counter() - a
+        O.set_threads(threads)
+        sp = t1 / t_two
+        res["single_thread_first_2_steps_s"] = t1
+        res["threads_first_2_steps_s"] = t_two
+        res["speedup_S_P"] = sp
+        res["efficiency_E_P"] = sp / threads
+    return res
+
+
+def precision_error(pf, ctx, prob, steps, reps=8):
+    """FP32-propagation against FP64 at the stated error: `reps` seeds, each
+    run in both precisions on the same data; after every step, the paired
+    difference of each log-parameter's posterior mean, t = mean(d) /
+    (sd(d)/sqrt(reps)) over the seeds.  Runs are compared only in
+    distribution (a last-bit difference flips a resampling decision sooner
+    or later and the paired runs decorrelate); |t| stays O(1) when the two
+    precisions estimate the same posterior.  Also the difference in units of
+    the posterior standard deviation."""
+    mu = {}
+    for prec in (pf.PF_PREC_FP32_PROP, pf.PF_PREC_FP64):
+        for r in range(reps):
+            f = pf.Filter(ctx, pf.Config(prob, prec, seed=1000 + r))
+            rows = []
+            for j in range(steps):
+                if f.assimilate(prob.times[j], prob.y[j], prob.sigma[j]) != pf.PF_OK:
+                    rows.append(None)
+                    continue
+                post = f.posterior()
+                rows.append((post["mean"], np.sqrt(np.maximum(np.diag(post["cov"]), 0.0))))
+            f.close()
+            mu[(prec, r)] = rows
+    tt, eff = [], []
+    for j in range(steps):
+        pairs = [(mu[(pf.PF_PREC_FP32_PROP, r)][j], mu[(pf.PF_PREC_FP64, r)][j]) for r in range(reps)]
+        pairs = [(a, b) for a, b in pairs if a is not None and b is not None]
+        if len(pairs) < 3:
+            continue
+        d = np.array([a[0] - b[0] for a, b in pairs])
+        sd_post = np.mean([b[1] for _, b in pairs], axis=0)
+        se = d.std(axis=0, ddof=1) / np.sqrt(len(pairs))
+        tt.append(np.abs(d.mean(axis=0)) / np.maximum(se, 1e-300))
+        eff.append(np.abs(d.mean(axis=0)) / np.maximum(sd_post, 1e-300))
+    tt, eff = np.asarray(tt), np.asarray(eff)
+    if not tt.size:
+        return None
+    return {"seeds": reps, "steps": int(tt.shape[0]),
+            "paired_t_median": float(np.median(tt)), "paired_t_p95": float(np.percentile(tt, 95)),
+            "frac_abs_t_above_3": float(np.mean(tt > 3.0)),
+            "mean_diff_in_posterior_sd_median": float(np.median(eff)),
+            "mean_diff_in_posterior_sd_max": float(eff.max())}
 
 
 def single_filter(pf, args, prob):
@@ -195,6 +280,7 @@ def single_filter(pf, args, prob):
         r32 = time_path(pf, ctx, prob, pf.PF_PREC_FP32_PROP, steps, warm)
         r64 = None if args.no_fp64 else time_path(pf, ctx, prob, pf.PF_PREC_FP64, steps, warm)
         lat = latency(pf, ctx, prob, pf.PF_PREC_FP32_PROP, min(60, prob.T))
+        err = None if args.no_fp64 else precision_error(pf, ctx, prob, steps)
     upd_ms = r32["kernel_ms"]["update"]
     achieved = r32["flop_update_per_launch"] / (upd_ms * 1e-3) / 1e12
     model = "robertson" if prob.model == inputs.MODEL_ROBERTSON else "chain16"
@@ -227,6 +313,8 @@ def single_filter(pf, args, prob):
         "fp32": r32,
         "fp64": r64,
         "fp32_over_fp64": (r32["particle_steps_per_s"] / r64["particle_steps_per_s"]) if r64 else None,
+        "fp32_error_vs_fp64": err,
+        "lmm_substeps_per_s": r32["particle_steps_per_s"] * 2 * prob.substeps,
         "latency": lat,
         "roofline": roofline,
     }
