@@ -373,6 +373,56 @@ __device__ __forceinline__ double row_sum16(double (&v)[16])
     return v[0];
 }
 
+// Combination of at most TILE rows of NA doubles (long rows: the chain's
+// moments), one row per lane held in registers: the block max of the tile
+// maxima, each lane scales its own row, and the NA-1 columns are summed with
+// the sixteen-at-a-time row reduction, then across rows and wavefronts in LDS.
+template <int NA>
+__device__ __forceinline__ double combine_wide(const double* part, int ntiles, int sq, int nplain, double* out,
+                                               double* sh)
+{
+    constexpr int NS = NA - 1;
+    constexpr int NCH = (NS + 15) / 16;
+    __shared__ double cs[NWAVE][NCH][WAVE];
+    const int t = threadIdx.x;
+    double v[NCH * 16];
+    double mt = -INFINITY;
+    if (t < ntiles) {
+        mt = part[(size_t)t * NA];
+#pragma unroll
+        for (int a = 0; a < NS; ++a) v[a] = part[(size_t)t * NA + 1 + a];
+    } else {
+#pragma unroll
+        for (int a = 0; a < NS; ++a) v[a] = 0.0;
+    }
+#pragma unroll
+    for (int a = NS; a < NCH * 16; ++a) v[a] = 0.0;
+    const double M = block_max(mt, sh);
+    const double sc = (mt > -INFINITY && M > -INFINITY) ? exp(mt - M) : 0.0;
+#pragma unroll
+    for (int a = 0; a < NS; ++a) v[a] *= a >= NS - nplain ? 1.0 : a == sq ? sc * sc : sc;
+    const int w = threadIdx.x / WAVE, ln = threadIdx.x % WAVE;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+        double chunk[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) chunk[k] = v[16 * c + k];
+        cs[w][c][ln] = row_sum16(chunk);
+    }
+    __syncthreads();
+    if (t < NS) {
+        const int c = t / 16, j = t % 16;
+        double s = 0.0;
+#pragma unroll
+        for (int ww = 0; ww < NWAVE; ++ww)
+#pragma unroll
+            for (int r = 0; r < WAVE / 16; ++r) s += cs[ww][c][16 * r + j];
+        out[t] = s;
+    }
+    __syncthreads();
+    return M;
+}
+
 // ---------------------------------------------------------------------------
 // moments of the parameters for one tile: partial[0] = max l, then
 // s0 = sum e, s00 = sum e^2, S1 = sum e d, S2 = sum e d d^T (upper triangle,
@@ -560,8 +610,12 @@ template <int P, int D>
 __device__ __forceinline__ void moments_combine(const FilterDesc& fd, double* tot, double* sh, double* buf)
 {
     constexpr int NA = 1 + 2 + P + P * (P + 1) / 2 + D + NPLAIN;
-    if constexpr (NA * 8 <= 256) combine_rows<NA, NA - 1>(fd.part2, fd.ntiles, 1, NPLAIN, tot, sh);
-    else combine_tiles(fd.part2, fd.nacc, fd.ntiles, fd.nacc - 1, tot, sh, 1, buf, STAGE_LEN, NPLAIN);
+    if constexpr (NA * 8 <= 256) {
+        combine_rows<NA, NA - 1>(fd.part2, fd.ntiles, 1, NPLAIN, tot, sh);
+    } else {
+        if (fd.ntiles <= TILE) combine_wide<NA>(fd.part2, fd.ntiles, 1, NPLAIN, tot, sh);
+        else combine_tiles(fd.part2, fd.nacc, fd.ntiles, fd.nacc - 1, tot, sh, 1, buf, STAGE_LEN, NPLAIN);
+    }
 }
 template <int P, int D>
 __device__ __forceinline__ int32_t moments_finish(const FilterDesc& fd, const double* tot, const MomPre& pre,
@@ -994,7 +1048,10 @@ __device__ __forceinline__ int32_t moment_step(const FilterDesc& fd, FilterState
     return status;
 }
 
-template <bool INL>
+// MDL: the model of every filter in the launch (MODEL_ROBERTSON or
+// MODEL_CHAIN16), or 0 when the batch mixes models (chosen per filter); a
+// single-model instance carries only that model's combine and tail.
+template <bool INL, int MDL>
 __global__ __launch_bounds__(TILE) void k_moments(Batch B, const FilterDesc* descs, FilterState* states,
                                                   int32_t* host_ring)
 {
@@ -1008,8 +1065,11 @@ __global__ __launch_bounds__(TILE) void k_moments(Batch B, const FilterDesc* des
         FilterState& st = states[slot];
         using RB = Robertson<double>;
         using CH = Chain16<double>;
-        const int32_t status = fd.model == MODEL_ROBERTSON ? moment_step<RB::P, RB::D>(fd, st, rec, sh, buf, tot)
-                                                           : moment_step<CH::P, CH::D>(fd, st, rec, sh, buf, tot);
+        int32_t status;
+        if constexpr (MDL == MODEL_ROBERTSON) status = moment_step<RB::P, RB::D>(fd, st, rec, sh, buf, tot);
+        else if constexpr (MDL == MODEL_CHAIN16) status = moment_step<CH::P, CH::D>(fd, st, rec, sh, buf, tot);
+        else status = fd.model == MODEL_ROBERTSON ? moment_step<RB::P, RB::D>(fd, st, rec, sh, buf, tot)
+                                                  : moment_step<CH::P, CH::D>(fd, st, rec, sh, buf, tot);
         if (threadIdx.x == 0) {
             st.status = status;
             st.ring[rec.seq % RING] = status;

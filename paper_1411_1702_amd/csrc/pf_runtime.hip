@@ -653,6 +653,11 @@ static pf_status submit(pf_context* ctx, uint32_t count, pf_filter* const* fs, c
         return b;
     };
 
+    MomentsKernel moments_kernel = k_moments<false, 0>;
+    if (inline_rec)
+        moments_kernel = fs[0]->desc.model == MODEL_ROBERTSON ? k_moments<true, MODEL_ROBERTSON>
+                                                              : k_moments<true, MODEL_CHAIN16>;
+
     // the step: the copy (batches only), then the kernel groups
     auto enqueue = [&]() -> hipError_t {
         hipError_t e = hipSuccess;
@@ -685,7 +690,7 @@ static pf_status submit(pf_context* ctx, uint32_t count, pf_filter* const* fs, c
                                ctx->stream, part(r), ctx->d_desc, ctx->d_state);
         }
         if (timed && (e = hipEventRecord(sg.tev[3], ctx->stream)) != hipSuccess) return e;
-        hipLaunchKernelGGL(inline_rec ? k_moments<true> : k_moments<false>,
+        hipLaunchKernelGGL(moments_kernel,
                            dim3(std::min<uint32_t>(count, (uint32_t)ctx->grid_cap)), dim3(TILE), 0,
                            ctx->stream, all, ctx->d_desc, ctx->d_state, ctx->d_ring);
         if ((e = hipGetLastError()) != hipSuccess) return e;
