@@ -201,96 +201,15 @@ __device__ inline double count_iters(uint64_t w) { return (double)(w & 0xFFFFFFF
 __device__ inline double count_fails(uint64_t w) { return (double)((w >> 32) & 0xFFFFFFull); }
 __device__ inline double count_nonf(uint64_t w) { return (double)(w >> 56); }
 
-// Combine per-tile log-domain partials part[t*stride + 0] = tile max,
-// part[t*stride + 1 + a] = sums scaled by exp(-tile max), a < nsum, in a
-// fixed order: out[a] = sum_t exp(max_t - M) part[t][1+a].  The sum with
-// index sq (a sum of squared weights) scales with exp(2 (max_t - M)); the
-// last nplain sums are plain counts, added unscaled.
-// With an LDS staging buffer (buf, buf_len doubles), tiles are read in
-// coalesced chunks; the order of the sums depends only on ntiles, stride and
-// buf_len.  Returns M.
-__device__ __forceinline__ double combine_tiles(const double* part, int stride, int ntiles, int nsum, double* out,
-                                double* sh /* >= TILE doubles */, int sq = -1, double* buf = nullptr,
-                                int buf_len = 0, int nplain = 0)
-{
-    double mx = -INFINITY;
-    for (int t = threadIdx.x; t < ntiles; t += TILE) mx = fmax(mx, part[(size_t)t * stride]);
-    const double M = block_max(mx, sh);
-    const int groups = TILE / nsum;
-    const int a = threadIdx.x % nsum, g = threadIdx.x / nsum;
-    const bool plain = a >= nsum - nplain;
-    double acc = 0.0;
-    if (buf) {
-        const int ch = buf_len / stride;
-        for (int t0 = 0; t0 < ntiles; t0 += ch) {
-            const int nt = min(ch, ntiles - t0);
-            __syncthreads();
-            const double* src = part + (size_t)t0 * stride;
-            const int cnt = nt * stride;
-            // issue all of this thread's loads before the first LDS store
-            constexpr int PER = 32;
-            for (int base = 0; base < cnt; base += PER * TILE) {
-                double r[PER];
-#pragma unroll
-                for (int k = 0; k < PER; ++k) {
-                    const int i = base + k * TILE + (int)threadIdx.x;
-                    r[k] = i < cnt ? src[i] : 0.0;
-                }
-#pragma unroll
-                for (int k = 0; k < PER; ++k) {
-                    const int i = base + k * TILE + (int)threadIdx.x;
-                    if (i < cnt) buf[i] = r[k];
-                }
-            }
-            __syncthreads();
-            // the tile max slot becomes the tile's scale factor
-            for (int t = threadIdx.x; t < nt; t += TILE) {
-                const double mt = buf[t * stride];
-                buf[t * stride] = (mt > -INFINITY && M > -INFINITY) ? exp(mt - M) : 0.0;
-            }
-            __syncthreads();
-            if (g < groups) {
-                for (int t = g; t < nt; t += groups) {
-                    const double sc = buf[t * stride];
-                    acc += (plain ? 1.0 : a == sq ? sc * sc : sc) * buf[t * stride + 1 + a];
-                }
-            }
-        }
-    } else if (g < groups) {
-        for (int t = g; t < ntiles; t += groups) {
-            const double mt = part[(size_t)t * stride];
-            const double v = part[(size_t)t * stride + 1 + a];
-            if (plain) {
-                acc += v;
-            } else if (mt > -INFINITY && M > -INFINITY) {
-                const double sc = exp(mt - M);
-                acc += (a == sq ? sc * sc : sc) * v;
-            }
-        }
-    }
-    __syncthreads();
-    if (g < groups) sh[g * nsum + a] = acc;
-    __syncthreads();
-    if (threadIdx.x < nsum) {
-        double s = 0.0;
-        for (int gg = 0; gg < groups; ++gg) s += sh[gg * nsum + threadIdx.x];
-        out[threadIdx.x] = s;
-    }
-    __syncthreads();
-    return M;
-}
-
-// The same combination for rows of a length known at compile time (small
-// models; the first-stage partials), in one pass with the rows in registers:
-// the first NS sums of rows of STRIDE doubles.  Each lane visits its tiles
-// (round-robin, two rows in flight) in increasing order, keeping its sums
-// relative to its own running max; then the block max, one rescale per lane,
-// and a block sum per column.  The order depends only on ntiles.
-template <int STRIDE, int NS>
-__device__ __forceinline__ double combine_rows(const double* part, int ntiles, int sq, int nplain, double* out,
+// The same combination in one pass for a few columns (small models; the
+// first-stage partials): each lane visits its tiles (round-robin, two in
+// flight) in increasing order with the NS sums in registers, relative to its
+// own running max; then the block max, one rescale per lane, and a block sum
+// per column.
+template <int NS>
+__device__ __forceinline__ double combine_rows(const double* part, int cs, int ntiles, int sq, int nplain, double* out,
                                                double* sh)
 {
-    static_assert(NS < STRIDE, "row holds the max and NS sums");
     constexpr int NA = NS + 1;
     __shared__ double colsum[NWAVE][NS];
     double acc[NS];
@@ -314,10 +233,10 @@ __device__ __forceinline__ double combine_rows(const double* part, int ntiles, i
         const int t2 = t + TILE;
         double r0[NA], r1[NA];
 #pragma unroll
-        for (int k = 0; k < NA; ++k) r0[k] = part[(size_t)t * STRIDE + k];
+        for (int k = 0; k < NA; ++k) r0[k] = part[(size_t)k * cs + t];
         if (t2 < ntiles) {
 #pragma unroll
-            for (int k = 0; k < NA; ++k) r1[k] = part[(size_t)t2 * STRIDE + k];
+            for (int k = 0; k < NA; ++k) r1[k] = part[(size_t)k * cs + t2];
         }
         take(r0);
         if (t2 < ntiles) take(r1);
@@ -373,24 +292,24 @@ __device__ __forceinline__ double row_sum16(double (&v)[16])
     return v[0];
 }
 
-// Combination of at most TILE rows of NA doubles (long rows: the chain's
-// moments), one row per lane held in registers: the block max of the tile
-// maxima, each lane scales its own row, and the NA-1 columns are summed with
-// the sixteen-at-a-time row reduction, then across rows and wavefronts in LDS.
-template <int NA>
-__device__ __forceinline__ double combine_wide(const double* part, int ntiles, int sq, int nplain, double* out,
-                                               double* sh)
+// The combination for at most TILE tiles and many columns (the chain's
+// moments): one tile per lane, all its columns loaded at once (coalesced
+// across lanes, one memory round trip), the block max of the tile maxima,
+// each lane scales its own values, and the columns are summed sixteen at a
+// time with row_sum16, then across rows and wavefronts in LDS.
+template <int NS>
+__device__ __forceinline__ double combine_wide(const double* part, int cs, int ntiles, int sq, int nplain,
+                                               double* out, double* sh)
 {
-    constexpr int NS = NA - 1;
     constexpr int NCH = (NS + 15) / 16;
-    __shared__ double cs[NWAVE][NCH][WAVE];
+    __shared__ double csum[NWAVE][NCH][WAVE];
     const int t = threadIdx.x;
     double v[NCH * 16];
     double mt = -INFINITY;
     if (t < ntiles) {
-        mt = part[(size_t)t * NA];
+        mt = part[t];
 #pragma unroll
-        for (int a = 0; a < NS; ++a) v[a] = part[(size_t)t * NA + 1 + a];
+        for (int a = 0; a < NS; ++a) v[a] = part[(size_t)(1 + a) * cs + t];
     } else {
 #pragma unroll
         for (int a = 0; a < NS; ++a) v[a] = 0.0;
@@ -399,15 +318,16 @@ __device__ __forceinline__ double combine_wide(const double* part, int ntiles, i
     for (int a = NS; a < NCH * 16; ++a) v[a] = 0.0;
     const double M = block_max(mt, sh);
     const double sc = (mt > -INFINITY && M > -INFINITY) ? exp(mt - M) : 0.0;
-#pragma unroll
-    for (int a = 0; a < NS; ++a) v[a] *= a >= NS - nplain ? 1.0 : a == sq ? sc * sc : sc;
     const int w = threadIdx.x / WAVE, ln = threadIdx.x % WAVE;
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
         double chunk[16];
 #pragma unroll
-        for (int k = 0; k < 16; ++k) chunk[k] = v[16 * c + k];
-        cs[w][c][ln] = row_sum16(chunk);
+        for (int k = 0; k < 16; ++k) {
+            const int a = 16 * c + k;
+            chunk[k] = v[a] * (a >= NS - nplain ? 1.0 : a == sq ? sc * sc : sc);
+        }
+        csum[w][c][ln] = row_sum16(chunk);
     }
     __syncthreads();
     if (t < NS) {
@@ -416,7 +336,62 @@ __device__ __forceinline__ double combine_wide(const double* part, int ntiles, i
 #pragma unroll
         for (int ww = 0; ww < NWAVE; ++ww)
 #pragma unroll
-            for (int r = 0; r < WAVE / 16; ++r) s += cs[ww][c][16 * r + j];
+            for (int r = 0; r < WAVE / 16; ++r) s += csum[ww][c][16 * r + j];
+        out[t] = s;
+    }
+    __syncthreads();
+    return M;
+}
+
+// Combine per-tile log-domain partials, stored by column: part[c * cs + t]
+// for tile t, where column 0 holds the tile max and column 1 + a the tile's
+// sum a (a < nsum), scaled by exp(-tile max).  The filter's sums are
+// out[a] = sum_t exp(max_t - M) part[1 + a][t] with M = max_t max_t; the
+// sum with index sq (a sum of squared weights) scales with exp(2 (max_t - M))
+// and the last nplain sums are plain counts, added unscaled.  Every reader
+// visits the tiles in a fixed assignment to lanes and a fixed order, so the
+// result depends only on ntiles.
+//
+// General form (any ntiles; many columns): the tile maxima first, then for
+// sixteen columns at a time each lane accumulates its tiles' scaled values
+// (consecutive lanes read consecutive tiles, so every load is coalesced) and
+// the sixteen lane sums are added over the block.
+template <int NS>
+__device__ __noinline__ double combine_cols(const double* part, int cs, int ntiles, int sq, int nplain, double* out,
+                                            double* sh)
+{
+    constexpr int NCH = (NS + 15) / 16;
+    __shared__ double csum[NWAVE][NCH][WAVE];
+    double mx = -INFINITY;
+    for (int t = threadIdx.x; t < ntiles; t += TILE) mx = fmax(mx, part[t]);
+    const double M = block_max(mx, sh);
+    const int w = threadIdx.x / WAVE, ln = threadIdx.x % WAVE;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+        double acc[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) acc[k] = 0.0;
+        for (int t = threadIdx.x; t < ntiles; t += TILE) {
+            const double mt = part[t];
+            const double sc = (mt > -INFINITY && M > -INFINITY) ? exp(mt - M) : 0.0;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const int a = 16 * c + k;
+                if (a < NS)
+                    acc[k] += (a >= NS - nplain ? 1.0 : a == sq ? sc * sc : sc) * part[(size_t)(1 + a) * cs + t];
+            }
+        }
+        csum[w][c][ln] = row_sum16(acc);
+    }
+    __syncthreads();
+    const int t = threadIdx.x;
+    if (t < NS) {
+        const int c = t / 16, j = t % 16;
+        double s = 0.0;
+#pragma unroll
+        for (int ww = 0; ww < NWAVE; ++ww)
+#pragma unroll
+            for (int r = 0; r < WAVE / 16; ++r) s += csum[ww][c][16 * r + j];
         out[t] = s;
     }
     __syncthreads();
@@ -428,12 +403,13 @@ __device__ __forceinline__ double combine_wide(const double* part, int ntiles, i
 // s0 = sum e, s00 = sum e^2, S1 = sum e d, S2 = sum e d d^T (upper triangle,
 // row by row), Sx = sum e x, with e = exp(l - max) and d = theta - c; then
 // the NPLAIN counters: the lanes' packed counts, plus the predictor's
-// (iterations, fails) of the tile when pred is given.  P and D are the
+// (iterations, fails) of the tile when pred is given (pred[0], pred[cs]).
+// Column c of the tile's partials goes to out_part[c * cs].  P and D are the
 // model's, so every register index is static.
 // ---------------------------------------------------------------------------
 template <class R, int P, int D>
 __device__ void tile_moments(double l, bool valid, const double* th, const R* x, const double* cshift,
-                             uint64_t counts, const double* pred, double* out_part, double* sh)
+                             uint64_t counts, const double* pred, double* out_part, int cs, double* sh)
 {
     constexpr int NV = 2 + P + P * (P + 1) / 2 + D;   // weighted sums
     constexpr int NCH = (NV + 15) / 16;
@@ -488,10 +464,10 @@ __device__ void tile_moments(double l, bool valid, const double* th, const R* x,
 #pragma unroll
                 for (int ww = 0; ww < NWAVE; ++ww) s += cw[ww][k];
             }
-            if (pred && k == 1) s += pred[1];
+            if (pred && k == 1) s += pred[cs];
             if (pred && k == 3) s += pred[0];
         }
-        out_part[1 + t] = s;
+        out_part[(size_t)(1 + t) * cs] = s;
     }
     if (threadIdx.x == 0) out_part[0] = Mt;
     __syncthreads();
@@ -601,32 +577,133 @@ __device__ __forceinline__ int32_t moments_tail(const double* tot, const MomPre&
     return ST_OK;
 }
 
-constexpr int STAGE_LEN = 8192;   // doubles of LDS staging for the tile combine
 
 // Moment pass of one filter (one workgroup): the tile combine, then in lane
 // 0 the counters and the tail.  The combine only reads, so callers run it
 // before deciding whether the step commits.
 template <int P, int D>
-__device__ __forceinline__ void moments_combine(const FilterDesc& fd, double* tot, double* sh, double* buf)
+__device__ __forceinline__ void moments_combine(const FilterDesc& fd, double* tot, double* sh)
 {
     constexpr int NA = 1 + 2 + P + P * (P + 1) / 2 + D + NPLAIN;
     if constexpr (NA * 8 <= 256) {
-        combine_rows<NA, NA - 1>(fd.part2, fd.ntiles, 1, NPLAIN, tot, sh);
+        combine_rows<NA - 1>(fd.part2, fd.ntiles, fd.ntiles, 1, NPLAIN, tot, sh);
     } else {
-        if (fd.ntiles <= TILE) combine_wide<NA>(fd.part2, fd.ntiles, 1, NPLAIN, tot, sh);
-        else combine_tiles(fd.part2, fd.nacc, fd.ntiles, fd.nacc - 1, tot, sh, 1, buf, STAGE_LEN, NPLAIN);
+        if (fd.ntiles <= TILE) combine_wide<NA - 1>(fd.part2, fd.ntiles, fd.ntiles, 1, NPLAIN, tot, sh);
+        else combine_cols<NA - 1>(fd.part2, fd.ntiles, fd.ntiles, 1, NPLAIN, tot, sh);
     }
 }
+// The same tail for larger P with the whole workgroup: covariance entries in
+// parallel, then a right-looking Cholesky in LDS, one column per round (the
+// column scaled by 1/l_jj, then the trailing triangle updated in parallel).
+// Every entry sees the same operations in the same order as in moments_tail
+// (c_ij + delta - l_i0 l_j0 - l_i1 l_j1 - ..., then times 1/l_jj), and so
+// does the jitter rule; a failed column ends an attempt early.
 template <int P, int D>
-__device__ __forceinline__ int32_t moments_finish(const FilterDesc& fd, const double* tot, const MomPre& pre,
-                                                  FilterState& st, bool flip, double t_next)
+__device__ __forceinline__ int32_t moments_tail_wg(const double* tot, const MomPre& pre, FilterState& st, bool flip,
+                                                   double t_next)
+{
+    constexpr int NT = P * (P + 1) / 2;
+    __shared__ double cv[P][P];
+    __shared__ double A[P][P];
+    __shared__ double dms[P];
+    const int t = threadIdx.x;
+    const double s0 = tot[0], s00 = tot[1];
+    if (!(s0 > 0.0) || !isfinite(s0)) return ST_EDEGENERATE;
+    const double inv = 1.0 / s0;
+    if (t < P) dms[t] = tot[2 + t] * inv;
+    __syncthreads();
+    for (int e = t; e < P * P; e += TILE) {
+        const int i = e / P, j = e % P;
+        const int r = i < j ? i : j, c = i < j ? j : i;
+        cv[i][j] = tot[2 + P + r * P - r * (r - 1) / 2 + (c - r)] * inv - dms[i] * dms[j];
+    }
+    __syncthreads();
+    double tr = 0.0;
+#pragma unroll
+    for (int i = 0; i < P; ++i) tr += cv[i][i];
+    double delta = 0.0;
+    int jit = -1;
+    for (int attempt = 0; attempt <= 5 && jit < 0; ++attempt) {
+        if (attempt == 1) delta = 1e-10 * tr / P;
+        else if (attempt > 1) delta *= 10.0;
+        for (int e = t; e < P * P; e += TILE) {
+            const int i = e / P, j = e % P;
+            A[i][j] = i == j ? cv[i][j] + delta : cv[i][j];
+        }
+        __syncthreads();
+        bool ok = true;
+        for (int j = 0; j < P && ok; ++j) {
+            const double sdiag = A[j][j];
+            ok = sdiag > 0.0 && isfinite(sdiag);
+            if (ok) {
+                const double ljj = sqrt(sdiag);
+                const double rl = 1.0 / ljj;
+                __syncthreads();
+                if (t == j) A[j][j] = ljj;
+                if (t > j && t < P) A[t][j] = A[t][j] * rl;
+                __syncthreads();
+                // trailing triangle: rows i > j, columns j < k <= i
+                const int m = P - j - 1;
+                for (int e = t; e < m * (m + 1) / 2; e += TILE) {
+                    int i = 0;
+                    while ((i + 1) * (i + 2) / 2 <= e) ++i;
+                    const int k = e - i * (i + 1) / 2;
+                    const int ii = j + 1 + i, kk = j + 1 + k;
+                    A[ii][kk] -= A[ii][j] * A[kk][j];
+                }
+                __syncthreads();
+            }
+        }
+        if (ok) jit = attempt;
+    }
+    if (jit < 0) return ST_EDEGENERATE;
+    for (int e = t; e < P * P; e += TILE) {
+        const int i = e / P, j = e % P;
+        st.C[e] = cv[i][j];
+        st.L[e] = j <= i ? A[i][j] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < P; ++i)   // static indices keep pre in registers
+        if (t == i) st.theta_bar[i] = pre.tb[i] + dms[i];
+    if (t < D) st.state_mean[t] = tot[2 + P + NT + t] * inv;
+    if (t == 0) {
+        st.ess = s0 * s0 / s00;
+        st.jitters = pre.jit + (unsigned long long)jit;
+        if (flip) {
+            st.cur = pre.cur ^ 1;
+            st.j = pre.j + 1;
+            st.t = t_next;
+        }
+    }
+    return ST_OK;
+}
+
+// counters of the step from the counter columns of the combined partials
+__device__ __forceinline__ void moments_counters(const FilterDesc& fd, const double* tot, const MomPre& pre,
+                                                 FilterState& st)
 {
     const double* c = tot + fd.nacc - 1 - NPLAIN;
     st.newton_upd = pre.n_upd + (unsigned long long)c[0];
     st.newton_fails = pre.n_fail + (unsigned long long)c[1];
     st.nonfinite = pre.n_nonf + (unsigned long long)c[2];
     st.newton_pred = pre.n_pred + (unsigned long long)c[3];
-    return moments_tail<P, D>(tot, pre, st, flip, t_next);
+}
+
+// counters and tail, called by the whole workgroup; returns the status to
+// every thread.  Small P: one lane; larger P: the workgroup.
+template <int P, int D>
+__device__ __forceinline__ int32_t moments_finish(const FilterDesc& fd, const double* tot, const MomPre& pre,
+                                                  FilterState& st, bool flip, double t_next)
+{
+    __shared__ int32_t status;
+    if (threadIdx.x == 0) moments_counters(fd, tot, pre, st);
+    if constexpr (P >= 8) {
+        return moments_tail_wg<P, D>(tot, pre, st, flip, t_next);
+    } else {
+        if (threadIdx.x == 0) status = moments_tail<P, D>(tot, pre, st, flip, t_next);
+        __syncthreads();
+        return status;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -713,8 +790,8 @@ __global__ __launch_bounds__(TILE) void k_init(int slot, const FilterDesc* descs
             }
             fd.logw[0][n] = -log((double)fd.n);
         }
-        tile_moments<R, P, D>(-log((double)fd.n), valid, th, xs, fd.prior_mean, 0, nullptr,
-                              fd.part2 + (size_t)tile * fd.nacc, sh);
+        tile_moments<R, P, D>(-log((double)fd.n), valid, th, xs, fd.prior_mean, 0, nullptr, fd.part2 + tile,
+                              fd.ntiles, sh);
     }
 }
 
@@ -725,13 +802,13 @@ __global__ __launch_bounds__(TILE) void k_init_moments(int slot, const FilterDes
 {
     constexpr int P = Model::P, D = Model::D;
     __shared__ double sh[TILE];
-    __shared__ double buf[STAGE_LEN];
     __shared__ double tot[NACC_MAX];
     const FilterDesc& fd = descs[slot];
     FilterState& st = states[slot];
     const MomPre pre = mom_prefetch<P>(st);
-    moments_combine<P, D>(fd, tot, sh, buf);
-    if (threadIdx.x == 0) st.status = moments_finish<P, D>(fd, tot, pre, st, false, pre.t);
+    moments_combine<P, D>(fd, tot, sh);
+    const int32_t status = moments_finish<P, D>(fd, tot, pre, st, false, pre.t);
+    if (threadIdx.x == 0) st.status = status;
 }
 
 // ---------------------------------------------------------------------------
@@ -792,11 +869,12 @@ __global__ __launch_bounds__(TILE) void k_predict(Batch B, const FilterDesc* des
         const double e = lg > -INFINITY ? exp(lg - Mt) : 0.0;
         const double s = block_sum(e, sh);
         if (threadIdx.x == 0) {
-            double* p1 = fd.part1 + (size_t)itm.tile * PART1_STRIDE;
+            double* p1 = fd.part1 + itm.tile;
+            const size_t cs = (size_t)fd.ntiles;
             p1[0] = Mt;
-            p1[1] = s;
-            p1[2] = ci;
-            p1[3] = cf;
+            p1[cs] = s;
+            p1[2 * cs] = ci;
+            p1[3 * cs] = cf;
         }
     }
 }
@@ -823,7 +901,7 @@ __global__ __launch_bounds__(TILE) void k_count(Batch B, const FilterDesc* descs
         double M = 0.0, S = 1.0;
         if (!fd.g_direct) {
             // the filter's first-stage log-sum-exp, from the tile partials
-            M = combine_rows<PART1_STRIDE, 1>(fd.part1, fd.ntiles, -1, 0, tot, sh);
+            M = combine_rows<1>(fd.part1, fd.ntiles, fd.ntiles, -1, 0, tot, sh);
             S = tot[0];
         }
         const bool ok = fd.g_direct || (M > -INFINITY && isfinite(M) && S > 0.0);
@@ -1001,8 +1079,7 @@ __global__ __launch_bounds__(TILE) void k_update(Batch B, const FilterDesc* desc
         }
         // 6 (partials): tile moments with shift theta_bar_j
         tile_moments<R, P, D>(l, valid, th, x, st.theta_bar, pack_counts(iters, fails, nonf),
-                              fd.part1 + (size_t)itm.tile * PART1_STRIDE + 2,
-                              fd.part2 + (size_t)itm.tile * fd.nacc, sh);
+                              fd.part1 + (size_t)2 * fd.ntiles + itm.tile, fd.part2 + itm.tile, fd.ntiles, sh);
     }
 }
 
@@ -1016,8 +1093,8 @@ __device__ inline void add_predict_counts(const FilterDesc& fd, FilterState& st,
 {
     double ci = 0.0, cf = 0.0;
     for (int t = threadIdx.x; t < fd.ntiles; t += TILE) {
-        ci += fd.part1[(size_t)t * PART1_STRIDE + 2];
-        cf += fd.part1[(size_t)t * PART1_STRIDE + 3];
+        ci += fd.part1[(size_t)2 * fd.ntiles + t];
+        cf += fd.part1[(size_t)3 * fd.ntiles + t];
     }
     ci = block_sum(ci, sh);
     cf = block_sum(cf, sh);
@@ -1029,11 +1106,10 @@ __device__ inline void add_predict_counts(const FilterDesc& fd, FilterState& st,
 
 template <int P, int D>
 __device__ __forceinline__ int32_t moment_step(const FilterDesc& fd, FilterState& st, const StepRec& rec, double* sh,
-                                               double* buf, double* tot)
+                                               double* tot)
 {
     const MomPre pre = mom_prefetch<P>(st);
-    moments_combine<P, D>(fd, tot, sh, buf);   // reads only: runs ahead of the checks
-    __shared__ int32_t status;
+    moments_combine<P, D>(fd, tot, sh);   // reads only: runs ahead of the checks
     if (!(rec.t_next > pre.t)) return ST_EORDER;
     if (pre.T == 0) {
         add_predict_counts(fd, st, sh);
@@ -1042,10 +1118,8 @@ __device__ __forceinline__ int32_t moment_step(const FilterDesc& fd, FilterState
     if (threadIdx.x == 0) {
         st.step = pre.j + 1;
         st.t_next = rec.t_next;
-        status = moments_finish<P, D>(fd, tot, pre, st, true, rec.t_next);
     }
-    __syncthreads();
-    return status;
+    return moments_finish<P, D>(fd, tot, pre, st, true, rec.t_next);
 }
 
 // MDL: the model of every filter in the launch (MODEL_ROBERTSON or
@@ -1056,9 +1130,11 @@ __global__ __launch_bounds__(TILE) void k_moments(Batch B, const FilterDesc* des
                                                   int32_t* host_ring)
 {
     __shared__ double sh[TILE];
-    __shared__ double buf[STAGE_LEN];
     __shared__ double tot[NACC_MAX];
-    for (int b = blockIdx.x; b < B.count; b += gridDim.x) {
+    // the inline form has one entry (and a grid of one): no loop, so nothing
+    // per-filter is hoisted and kept live across iterations
+    const int b_end = INL ? 1 : B.count;
+    for (int b = blockIdx.x; b < b_end; b += INL ? b_end : gridDim.x) {
         const StepRec rec = record<INL>(B, b);
         const int slot = uniform(rec.slot);
         const FilterDesc& fd = desc_of<INL>(B, descs, slot);
@@ -1066,10 +1142,10 @@ __global__ __launch_bounds__(TILE) void k_moments(Batch B, const FilterDesc* des
         using RB = Robertson<double>;
         using CH = Chain16<double>;
         int32_t status;
-        if constexpr (MDL == MODEL_ROBERTSON) status = moment_step<RB::P, RB::D>(fd, st, rec, sh, buf, tot);
-        else if constexpr (MDL == MODEL_CHAIN16) status = moment_step<CH::P, CH::D>(fd, st, rec, sh, buf, tot);
-        else status = fd.model == MODEL_ROBERTSON ? moment_step<RB::P, RB::D>(fd, st, rec, sh, buf, tot)
-                                                  : moment_step<CH::P, CH::D>(fd, st, rec, sh, buf, tot);
+        if constexpr (MDL == MODEL_ROBERTSON) status = moment_step<RB::P, RB::D>(fd, st, rec, sh, tot);
+        else if constexpr (MDL == MODEL_CHAIN16) status = moment_step<CH::P, CH::D>(fd, st, rec, sh, tot);
+        else status = fd.model == MODEL_ROBERTSON ? moment_step<RB::P, RB::D>(fd, st, rec, sh, tot)
+                                                  : moment_step<CH::P, CH::D>(fd, st, rec, sh, tot);
         if (threadIdx.x == 0) {
             st.status = status;
             st.ring[rec.seq % RING] = status;

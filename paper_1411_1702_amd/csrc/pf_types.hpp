@@ -61,9 +61,9 @@ struct FilterDesc {
     double* lg;                         // [npad] first-stage log-weights
     uint64_t* q;                        // [npad] scaled integer weights
     int32_t* anc;                       // [npad] ancestors
-    double* part1;                      // [ntiles][PART1_STRIDE] (max, sum exp, iterations, fails)
+    double* part1;                      // [PART1_STRIDE][ntiles] (max, sum exp, iterations, fails), by column
     uint64_t* tsum;                     // [ntiles] integer weight per tile (then offsets)
-    double* part2;                      // [ntiles][nacc] moment partials and counters
+    double* part2;                      // [nacc][ntiles] moment partials and counters, by column
 };
 
 // Dynamic state of one filter (device resident, updated by the kernels).
