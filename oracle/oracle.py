@@ -40,7 +40,8 @@ class _Cfg(C.Structure):
                 ("order", C.c_int), ("substeps", C.c_int),
                 ("kmax", C.c_int), ("rtol", C.c_double),
                 ("floor_", C.c_double * DMAX), ("x0", C.c_double * DMAX),
-                ("prior_mean", C.c_double * PMAX), ("prior_sd", C.c_double * PMAX)]
+                ("prior_mean", C.c_double * PMAX), ("prior_sd", C.c_double * PMAX),
+                ("resampling", C.c_int)]
 
 
 class _State(C.Structure):
@@ -89,6 +90,8 @@ def lib():
         L.or_resample_shift.argtypes = [C.c_long]
         L.or_resample_int.argtypes = [C.c_long, up, C.c_uint64, C.POINTER(C.c_int32)]
         L.or_resample.argtypes = [C.c_long, dp, C.c_uint64, C.POINTER(C.c_int32)]
+        L.or_resample_multinomial_int.argtypes = [C.c_long, up, up, C.POINTER(C.c_int32)]
+        L.or_resample_multinomial.argtypes = [C.c_long, dp, C.c_uint64, C.c_uint64, C.POINTER(C.c_int32)]
         L.or_moments.argtypes = [C.c_long, C.c_int, dp, dp, dp, dp]
         L.or_cholesky.argtypes = [C.c_int, dp, dp, C.POINTER(C.c_int)]
         L.or_filter_init.argtypes = [C.POINTER(_Cfg), C.c_double, C.POINTER(_State)]
@@ -226,6 +229,26 @@ def resample(g, r):
     return st, anc
 
 
+def resample_multinomial_int(q, r):
+    """Multinomial draw on integer weights q with one uniform word per slot."""
+    q = np.ascontiguousarray(q, dtype=np.uint64)
+    r = np.ascontiguousarray(r, dtype=np.uint64)
+    anc = np.zeros(len(q), dtype=np.int32)
+    st = lib().or_resample_multinomial_int(len(q), q.ctypes.data_as(C.POINTER(C.c_uint64)),
+                                           r.ctypes.data_as(C.POINTER(C.c_uint64)),
+                                           anc.ctypes.data_as(C.POINTER(C.c_int32)))
+    return st, anc
+
+
+def resample_multinomial(g, seed, step):
+    """Multinomial draw on the weights g with the RESAMPLE words of (seed, step)."""
+    g = _f64(g)
+    anc = np.zeros(len(g), dtype=np.int32)
+    st = lib().or_resample_multinomial(len(g), _dp(g), C.c_uint64(int(seed)), C.c_uint64(int(step)),
+                                       anc.ctypes.data_as(C.POINTER(C.c_int32)))
+    return st, anc
+
+
 def moments(theta, w):
     theta = _f64(theta)
     N, p = theta.shape
@@ -259,7 +282,7 @@ class Filter:
     """Algorithm 1 on the CPU.  `prob` is an inputs.Problem (or any object with
     the same fields)."""
 
-    def __init__(self, prob, n_particles=None, seed=None, rtol=None):
+    def __init__(self, prob, n_particles=None, seed=None, rtol=None, resampling=None):
         self.prob = prob
         N = int(prob.n_particles if n_particles is None else n_particles)
         d, p, m = prob.d, prob.p, prob.m
@@ -278,6 +301,7 @@ class Filter:
         cfg.order, cfg.substeps = int(prob.order), int(prob.substeps)
         cfg.kmax = int(prob.newton_max_iter)
         cfg.rtol = float(prob.newton_rtol_fp64 if rtol is None else rtol)
+        cfg.resampling = int(getattr(prob, "resampling", 0) if resampling is None else resampling)
         for i in range(d):
             cfg.floor_[i] = float(prob.state_floor[i])
             cfg.x0[i] = float(prob.x0[i])

@@ -457,6 +457,58 @@ int or_resample(long N, const double* g, uint64_t r, int32_t* anc)
 }
 
 /* ------------------------------------------------------------------------- */
+/* Multinomial resampling: the literal draw of step 3(b), each output slot   */
+/* an independent draw of an index with probability g_k.  On the same       */
+/* integer weights q_k as above (T = C_N): slot i has its own uniform word    */
+/* r_i and takes the first k with C_k > tau_i, tau_i = floor(r_i T / 2^64),   */
+/* so index k is drawn with probability q_k / T.                              */
+/* ------------------------------------------------------------------------- */
+int or_resample_multinomial_int(long N, const uint64_t* q, const uint64_t* r, int32_t* anc)
+{
+    uint64_t* Cc = (uint64_t*)malloc(sizeof(uint64_t) * (N > 0 ? N : 1));
+    uint64_t T = 0;
+    for (long k = 0; k < N; ++k) {
+        T += q[k];
+        Cc[k] = T;
+    }
+    if (T == 0) {
+        free(Cc);
+        return OR_EDEGENERATE;
+    }
+    for (long i = 0; i < N; ++i) {
+        uint64_t tau = (uint64_t)(((unsigned __int128)r[i] * T) >> 64);
+        long lo = 0, hi = N - 1;            /* first k with Cc[k] > tau */
+        while (lo < hi) {
+            long mid = lo + (hi - lo) / 2;
+            if (Cc[mid] > tau) hi = mid;
+            else lo = mid + 1;
+        }
+        anc[i] = (int32_t)lo;
+    }
+    free(Cc);
+    return OR_OK;
+}
+
+/* the uniform word of output slot i at step j: Philox(seed; j, i, RESAMPLE, 0)[0] */
+int or_resample_multinomial(long N, const double* g, uint64_t seed, uint64_t step, int32_t* anc)
+{
+    int S = or_resample_shift(N);
+    uint64_t* q = (uint64_t*)malloc(sizeof(uint64_t) * (N > 0 ? N : 1));
+    uint64_t* r = (uint64_t*)malloc(sizeof(uint64_t) * (N > 0 ? N : 1));
+    for (long k = 0; k < N; ++k) {
+        double v = (g[k] > 0.0) ? floor(ldexp(g[k], S)) : 0.0;
+        q[k] = (uint64_t)v;
+        uint64_t key[2] = {seed, 0}, ctr[4] = {step, (uint64_t)k, PUR_RESAMPLE, 0}, wv[4];
+        or_philox4x64(ctr, key, wv);
+        r[k] = wv[0];
+    }
+    int st = or_resample_multinomial_int(N, q, r, anc);
+    free(q);
+    free(r);
+    return st;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Weighted parameter mean and covariance (Algorithm 1 steps 1 and 6):       */
 /*   mean = sum_n w_n theta_n,  C = sum_n w_n (theta_n - mean)(...)^T.       */
 /* Two passes; weights are taken as given (they sum to one).                  */
@@ -524,6 +576,7 @@ typedef struct {
     double floor_[OR_DMAX];
     double x0[OR_DMAX];
     double prior_mean[OR_PMAX], prior_sd[OR_PMAX];
+    int resampling;             /* 0 systematic (integer CDF), 1 multinomial */
 } or_config;
 
 typedef struct {
@@ -613,8 +666,11 @@ int or_filter_step(const or_config* cfg, or_state* s, double t_next,
     }
     if (or_normalise(N, lg, g) == -INFINITY) { status = OR_EDEGENERATE; goto done; }
 
-    /* Step 3(b): indices, one uniform word per filter and step */
-    {
+    /* Step 3(b): indices; systematic: one uniform word per filter and step,
+     * multinomial: one per output slot */
+    if (cfg->resampling == 1) {
+        if (or_resample_multinomial(N, g, cfg->seed, step, anc) != OR_OK) { status = OR_EDEGENERATE; goto done; }
+    } else {
         uint64_t key[2] = {cfg->seed, 0}, ctr[4] = {step, 0, PUR_RESAMPLE, 0}, wv[4];
         or_philox4x64(ctr, key, wv);
         if (or_resample(N, g, wv[0], anc) != OR_OK) { status = OR_EDEGENERATE; goto done; }
@@ -709,7 +765,9 @@ int or_filter_stage1(const or_config* cfg, const or_state* s, double t_next,
     }
     int st = OR_OK;
     if (or_normalise(N, lg, g_out) == -INFINITY) st = OR_EDEGENERATE;
-    else {
+    else if (cfg->resampling == 1) {
+        st = or_resample_multinomial(N, g_out, cfg->seed, s->j + 1, anc_out);
+    } else {
         uint64_t key[2] = {cfg->seed, 0}, ctr[4] = {s->j + 1, 0, PUR_RESAMPLE, 0}, wv[4];
         or_philox4x64(ctr, key, wv);
         st = or_resample(N, g_out, wv[0], anc_out);
