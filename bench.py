@@ -307,7 +307,9 @@ def single_filter(pf, args, prob):
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"{model} N={prob.n_particles} T={prob.T} BDF{prob.order} "
-                               f"M={prob.substeps} fp32-propagation, fp64 weights/moments",
+                               f"M={prob.substeps} fp32-propagation, fp64 weights/moments"
+                               + (", multinomial resampling" if prob.resampling else ""),
+                   "resampling": "multinomial" if prob.resampling else "systematic",
                    "particles": prob.n_particles, "observations": prob.T, "bdf_order": prob.order,
                    "substeps": prob.substeps},
         "fp32": r32,
@@ -439,6 +441,8 @@ def main():
                     choices=["robertson", "small", "chain", "batched", "serving"])
     ap.add_argument("--filters", type=int, default=256)
     ap.add_argument("--streams", type=int, default=2000)
+    ap.add_argument("--resampling", default="systematic", choices=["systematic", "multinomial"],
+                    help="index draw of step 3(b) for the single-filter configurations")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB (a known-size "
                          "reference for the HBM byte counters of a profiler pass)")
@@ -471,6 +475,7 @@ def main():
         if args.steps < 1:
             print("--steps must be >= 1", file=sys.stderr)
             sys.exit(2)
+        prob.resampling = 1 if args.resampling == "multinomial" else 0
         out = single_filter(pf, args, prob)
     print(json.dumps(out))
 

@@ -59,6 +59,15 @@ typedef enum {
     PF_PREC_FP32_PROP = 1  /* propagation in float; weights, moments, Cholesky in double */
 } pf_precision;
 
+/* Step 3(b) index draw.  Both act on the integer weights q_k = floor(g_k 2^S),
+ * S = 62 - ceil(log2 N), with T = sum q_k.
+ *   SYSTEMATIC: one uniform word r per filter and step, V = floor(r T / 2^64);
+ *               output slot i takes the first k with C_k > floor((i T + V)/N).
+ *   MULTINOMIAL: the literal draw of Algorithm 1 step 3(b): slot i has its own
+ *               word r_i = Philox(seed; step, i, RESAMPLE, 0)[0] and takes the
+ *               first k with C_k > floor(r_i T / 2^64); N <= 2^20. */
+typedef enum { PF_RESAMPLE_SYSTEMATIC = 0, PF_RESAMPLE_MULTINOMIAL = 1 } pf_resampling;
+
 /*
  * Filter configuration (Algorithm 1, problem statement of Sec. 2).
  * Array fields are host pointers read during pf_create only.
@@ -86,6 +95,7 @@ typedef struct {
     double newton_rtol;          /* stopping test max |dx_i| / max(|x_i|, floor_i) */
     const double* state_floor;   /* [d] scale floors of that test */
     pf_precision precision;
+    pf_resampling resampling;    /* index draw of step 3(b) */
 } pf_config;
 
 /*

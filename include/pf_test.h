@@ -45,6 +45,15 @@ pf_status pf_test_propagate(const pf_config* cfg, uint64_t n, const double* x_in
 pf_status pf_test_resample(uint64_t n, const double* g, uint64_t r, int32_t* anc,
                            void* hip_stream);
 
+/* Multinomial resampling (the literal draw of Algorithm 1 step 3(b)) of
+ * normalised weights g [n] (device double), n <= 2^20: output slot i draws
+ * with its own word Philox(seed; step, i, RESAMPLE, 0)[0], as a filter's
+ * step `step` does (step >= 1).  anc [n] (device int32) receives the
+ * ancestors.  PF_EDEGENERATE when every scaled weight is zero; PF_EINVAL for
+ * n or step out of range. Synchronous. */
+pf_status pf_test_resample_multinomial(uint64_t n, const double* g, uint64_t seed, uint64_t step,
+                                       int32_t* anc, void* hip_stream);
+
 /* The three filter-based calls below run on the context's own stream: each
  * first waits for all work on the device (so buffers the caller produced on
  * any stream are ready) and returns after its own work is done. */

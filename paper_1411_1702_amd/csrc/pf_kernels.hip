@@ -910,10 +910,20 @@ __global__ __launch_bounds__(TILE) void k_count(Batch B, const FilterDesc* descs
             const double g = fd.g_direct ? l : (ok && l > -INFINITY ? exp(l - M) / S : 0.0);
             if (g > 0.0) q = (unsigned long long)floor(ldexp(g, fd.shift));
         }
-        const unsigned long long ts = block_sum_u64(q, shu);
-        if (!fd.g_direct && !(itm.rec.t_next > t_cur)) continue;   // the step does not run
-        if (n < fd.n) fd.q[n] = q;
-        if (threadIdx.x == 0) fd.tsum[itm.tile] = ts;
+        if (fd.resampling == 0) {
+            const unsigned long long ts = block_sum_u64(q, shu);
+            if (!fd.g_direct && !(itm.rec.t_next > t_cur)) continue;   // the step does not run
+            if (n < fd.n) fd.q[n] = q;
+            if (threadIdx.x == 0) fd.tsum[itm.tile] = ts;
+        } else {
+            // multinomial draw: the inclusive prefix of q within the tile
+            // (every lane of the tile, so the prefix is monotone up to 255)
+            unsigned long long ex;
+            const unsigned long long ts = block_exscan_u64(q, ex, shu);
+            if (!fd.g_direct && !(itm.rec.t_next > t_cur)) continue;
+            fd.q[n] = ex + q;
+            if (threadIdx.x == 0) fd.tsum[itm.tile] = ts;
+        }
     }
 }
 
@@ -932,9 +942,65 @@ __device__ inline uint64_t first_slot(uint64_t c, uint64_t N, uint64_t T, uint64
 // by the whole workgroup
 constexpr uint64_t LONG_RUN = 16;
 
+// Multinomial draw for the output slots of one tile (Algorithm 1 step 3(b)
+// literally): the filter's tile offsets P (exclusive prefix of the tile sums,
+// P[ntiles] = T) are built in LDS by every workgroup in the same order; slot
+// i draws tau_i = floor(r_i T / 2^64) from its own RESAMPLE word, finds the
+// tile s with P[s] <= tau_i < P[s+1] by bisection in LDS, then the particle by
+// bisection over that tile's inclusive prefix (written by k_count).
+__device__ inline void multinomial_tile(const FilterDesc& fd, FilterState& st, int tile, uint64_t step, bool run,
+                                        unsigned long long* P, unsigned long long* shu)
+{
+    const int nt = fd.ntiles;
+    constexpr int PER = MULTI_MAX_TILES / TILE;   // tile sums per lane
+    unsigned long long v[PER], loc = 0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int t = threadIdx.x * PER + k;
+        v[k] = t < nt ? fd.tsum[t] : 0ull;
+        loc += v[k];
+    }
+    unsigned long long ex;
+    const unsigned long long T = block_exscan_u64(loc, ex, shu);
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int t = threadIdx.x * PER + k;
+        if (t < nt) P[t] = ex;
+        ex += v[k];
+    }
+    if (threadIdx.x == 0) P[nt] = T;
+    __syncthreads();
+    if (!run) return;
+    if (tile == 0 && threadIdx.x == 0) {
+        st.T = T;
+        st.V = 0;
+    }
+    const int i = tile * TILE + threadIdx.x;
+    if (T == 0 || i >= fd.n) return;
+    uint64_t w[4];
+    Philox::block(step, (uint64_t)i, PUR_RESAMPLE, 0, fd.seed, 0, w);
+    const uint64_t tau = __umul64hi(w[0], T);
+    int lo = 0, hi = nt;   // last s with P[s] <= tau  (P[0] = 0 <= tau < P[nt] = T)
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (P[mid] <= tau) lo = mid;
+        else hi = mid;
+    }
+    const uint64_t rem = tau - P[lo];
+    const uint64_t* cq = fd.q + (size_t)lo * TILE;
+    int a = 0, b = TILE - 1;   // first k with cq[k] > rem (cq[255] = tile sum > rem)
+    while (a < b) {
+        const int mid = (a + b) >> 1;
+        if (cq[mid] > rem) b = mid;
+        else a = mid + 1;
+    }
+    fd.anc[i] = lo * TILE + a;
+}
+
 template <bool INL>
 __global__ __launch_bounds__(TILE) void k_scatter(Batch B, const FilterDesc* descs, FilterState* states)
 {
+    __shared__ unsigned long long P[MULTI_MAX_TILES + 1];
     __shared__ unsigned long long shu[2 * NWAVE];
     __shared__ int n_long;
     __shared__ uint32_t run_lo[TILE], run_hi[TILE];
@@ -943,6 +1009,12 @@ __global__ __launch_bounds__(TILE) void k_scatter(Batch B, const FilterDesc* des
         const Item itm = fetch<INL>(B, itx);
         const FilterDesc& fd = desc_of<INL>(B, descs, itm.slot);
         FilterState& st = states[itm.slot];
+        if (fd.resampling == 1) {
+            const bool run = fd.g_direct || itm.rec.t_next > st.t;
+            multinomial_tile(fd, st, itm.tile, st.j + 1, run, P, shu);
+            __syncthreads();
+            continue;
+        }
         // loads first: this lane's weight, the filter state, the tile sums
         // (the step's validity only gates the stores)
         const int n = itm.tile * TILE + threadIdx.x;

@@ -250,6 +250,10 @@ static pf_status check_config(const pf_config* c)
     if (c->newton_max_iter < 1 || c->newton_max_iter > KMAX_MAX) return fail(PF_EINVAL, "newton_max_iter must be 1..64");
     if (!(c->newton_rtol > 0.0)) return fail(PF_EINVAL, "newton_rtol must be > 0");
     if (c->precision != PF_PREC_FP64 && c->precision != PF_PREC_FP32_PROP) return fail(PF_EINVAL, "bad precision");
+    if (c->resampling != PF_RESAMPLE_SYSTEMATIC && c->resampling != PF_RESAMPLE_MULTINOMIAL)
+        return fail(PF_EINVAL, "bad resampling");
+    if (c->resampling == PF_RESAMPLE_MULTINOMIAL && c->n_particles > (uint64_t)MULTI_MAX_TILES * TILE)
+        return fail(PF_EINVAL, "multinomial resampling needs N <= 2^20");
     for (uint32_t i = 0; i < c->p; ++i)
         if (!std::isfinite(c->prior_mean[i]) || !(c->prior_sd[i] >= 0.0)) return fail(PF_EINVAL, "bad prior");
     return PF_OK;
@@ -266,6 +270,7 @@ static void fill_static(FilterDesc& d, const pf_config* c)
     d.substeps = (int)c->substeps;
     d.kmax = (int)c->newton_max_iter;
     d.prec = c->precision == PF_PREC_FP32_PROP ? PREC_FP32 : PREC_FP64;
+    d.resampling = c->resampling == PF_RESAMPLE_MULTINOMIAL ? 1 : 0;
     for (uint32_t i = 0; i < c->m; ++i) d.obs[i] = (int)c->obs_index[i];
     d.n = (int)c->n_particles;
     d.ntiles = (d.n + TILE - 1) / TILE;
@@ -971,10 +976,16 @@ extern "C" pf_status pf_test_propagate(const pf_config* cfg, uint64_t n, const d
     return PF_OK;
 }
 
-extern "C" pf_status pf_test_resample(uint64_t n, const double* g, uint64_t r, int32_t* anc, void* hip_stream)
+// both index draws through the filter's own kernels (k_count, k_scatter) on
+// weights given directly; systematic: r is the uniform word, multinomial: the
+// words come from (seed, step) as in a filter step
+static pf_status test_resample(uint64_t n, const double* g, int multinomial, uint64_t r, uint64_t seed,
+                               uint64_t step, int32_t* anc, void* hip_stream)
 {
     if (!g || !anc) return fail(PF_EINVAL, "NULL buffer");
     if (n == 0 || n > (1ull << 24)) return fail(PF_EINVAL, "n must be 1..2^24");
+    if (multinomial && (n > (uint64_t)MULTI_MAX_TILES * TILE || step == 0))
+        return fail(PF_EINVAL, "multinomial: n must be 1..2^20 and step >= 1");
     hipStream_t st = (hipStream_t)hip_stream;
     FilterDesc d;
     std::memset(&d, 0, sizeof(d));
@@ -985,6 +996,8 @@ extern "C" pf_status pf_test_resample(uint64_t n, const double* g, uint64_t r, i
     while ((1ll << cl) < (long long)d.n) ++cl;
     d.shift = 62 - cl;
     d.g_direct = 1;
+    d.resampling = multinomial ? 1 : 0;
+    d.seed = seed;
     // scratch: desc, state, rec, items, q, tsum, done
     const size_t nb = sizeof(FilterDesc) + sizeof(FilterState) + sizeof(StepRec) + 4 * (size_t)d.ntiles +
                       8 * (size_t)d.npad + 8 * (size_t)d.ntiles + 6 * 256;
@@ -1004,6 +1017,7 @@ extern "C" pf_status pf_test_resample(uint64_t n, const double* g, uint64_t r, i
     std::memset(&hs, 0, sizeof(hs));
     hs.status = ST_OK;
     hs.V = r;
+    hs.j = multinomial ? step - 1 : 0;
     StepRec rec;
     std::memset(&rec, 0, sizeof(rec));
     std::vector<uint32_t> items(d.ntiles);
@@ -1030,6 +1044,17 @@ extern "C" pf_status pf_test_resample(uint64_t n, const double* g, uint64_t r, i
     if (e != hipSuccess) return fail(PF_EDEVICE, std::string("resample: ") + hipGetErrorString(e));
     if (hs.T == 0) return fail(PF_EDEGENERATE, "all scaled weights are zero");
     return PF_OK;
+}
+
+extern "C" pf_status pf_test_resample(uint64_t n, const double* g, uint64_t r, int32_t* anc, void* hip_stream)
+{
+    return test_resample(n, g, 0, r, 0, 0, anc, hip_stream);
+}
+
+extern "C" pf_status pf_test_resample_multinomial(uint64_t n, const double* g, uint64_t seed, uint64_t step,
+                                                  int32_t* anc, void* hip_stream)
+{
+    return test_resample(n, g, 1, 0, seed, step, anc, hip_stream);
 }
 
 namespace pf {

@@ -20,6 +20,7 @@ constexpr int PART1_STRIDE = 4;
 constexpr int NPLAIN = 4;
 constexpr int SUBSTEPS_MAX = 65536;
 constexpr int KMAX_MAX = 64;
+constexpr int MULTI_MAX_TILES = 4096;   // multinomial draw: N <= 2^20 (tile offsets in LDS)
 // moment accumulators per tile: the tile's max log-weight, s0, s00,
 // sum w (theta - c), sum w (theta-c)(theta-c)^T (upper triangle), sum w x,
 // and the NPLAIN counters
@@ -43,7 +44,7 @@ struct FilterDesc {
     int32_t order, substeps, kmax, prec;
     int32_t obs[MMAX];
     int32_t n, npad, ntiles, shift;     // shift: resampling scale 2^shift
-    int32_t nacc, g_direct, pad0, pad1;
+    int32_t nacc, g_direct, resampling, pad1;   // resampling: 0 systematic, 1 multinomial
     uint64_t seed;
     double a, s, rtol;                  // shrink factor, jitter sqrt(1-a^2), Newton rtol
     double prior_mean[PMAX], prior_sd[PMAX];
@@ -59,7 +60,7 @@ struct FilterDesc {
     double* logw[2];                    // [npad] unnormalised log-weights
     double* lbar;                       // [npad] log pi(y | predictor)
     double* lg;                         // [npad] first-stage log-weights
-    uint64_t* q;                        // [npad] scaled integer weights
+    uint64_t* q;                        // [npad] integer weights (multinomial: their inclusive prefix within the tile)
     int32_t* anc;                       // [npad] ancestors
     double* part1;                      // [PART1_STRIDE][ntiles] (max, sum exp, iterations, fails), by column
     uint64_t* tsum;                     // [ntiles] integer weight per tile (then offsets)

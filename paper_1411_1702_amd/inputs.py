@@ -72,6 +72,7 @@ class Problem:
     newton_rtol_fp64: float = 1e-12
     newton_rtol_fp32: float = 2e-6
     state_floor: np.ndarray = None   # (d,) scale floors (Newton test, parity)
+    resampling: int = 0              # step 3(b): 0 systematic, 1 multinomial
 
     @property
     def T(self) -> int:

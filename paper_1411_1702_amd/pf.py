@@ -19,6 +19,7 @@ PF_ENONFINITE, PF_EDEVICE, PF_EBUSY, PF_EORDER = 5, 6, 7, 8
 PF_MODEL_ROBERTSON, PF_MODEL_CHAIN16 = 1, 2
 PF_LMM_BDF = 0
 PF_PREC_FP64, PF_PREC_FP32_PROP = 0, 1
+PF_RESAMPLE_SYSTEMATIC, PF_RESAMPLE_MULTINOMIAL = 0, 1
 PF_TIME_STEP, PF_TIME_PREDICT, PF_TIME_RESAMPLE, PF_TIME_UPDATE, PF_TIME_MOMENTS = 0, 1, 2, 3, 4
 
 EXPORTS = [
@@ -28,7 +29,7 @@ EXPORTS = [
     "pf_context_profile", "pf_context_kernel_time", "pf_query",
     "pf_server_create", "pf_server_open", "pf_server_submit", "pf_server_poll", "pf_server_posterior",
     "pf_server_close", "pf_server_drain", "pf_server_stats", "pf_server_destroy",
-    "pf_test_philox", "pf_test_normals", "pf_test_propagate", "pf_test_resample",
+    "pf_test_philox", "pf_test_normals", "pf_test_propagate", "pf_test_resample", "pf_test_resample_multinomial",
     "pf_test_get_ensemble", "pf_test_set_ensemble", "pf_test_last_ancestors",
 ]
 
@@ -50,7 +51,7 @@ class pf_config(C.Structure):
         ("prior_sd", C.POINTER(C.c_double)), ("shrink_a", C.c_double), ("lmm", C.c_int),
         ("order", C.c_uint32), ("substeps", C.c_uint32), ("newton_max_iter", C.c_uint32),
         ("newton_rtol", C.c_double), ("state_floor", C.POINTER(C.c_double)),
-        ("precision", C.c_int),
+        ("precision", C.c_int), ("resampling", C.c_int),
     ]
 
 
@@ -104,6 +105,7 @@ def lib():
         L.pf_test_propagate.argtypes = [C.POINTER(pf_config), u64, vp, vp, C.c_double, C.c_int, vp, vp,
                                         vp, vp]
         L.pf_test_resample.argtypes = [u64, vp, u64, vp, vp]
+        L.pf_test_resample_multinomial.argtypes = [u64, vp, u64, u64, vp, vp]
         L.pf_test_get_ensemble.argtypes = [vp, vp, vp, vp]
         L.pf_test_set_ensemble.argtypes = [vp, vp, vp, vp, dp, dp, u64, C.c_double]
         L.pf_test_last_ancestors.argtypes = [vp, vp]
@@ -135,7 +137,7 @@ class Config:
     """pf_config plus the host arrays it points to (kept alive here)."""
 
     def __init__(self, prob, precision=PF_PREC_FP32_PROP, n_particles=None, seed=None,
-                 newton_rtol=None):
+                 newton_rtol=None, resampling=None):
         self.prob = prob
         f64 = lambda a: np.ascontiguousarray(a, dtype=np.float64)
         self.obs = np.ascontiguousarray(prob.obs_index, dtype=np.uint32)
@@ -166,6 +168,7 @@ class Config:
         if newton_rtol is None:
             newton_rtol = prob.newton_rtol_fp32 if precision == PF_PREC_FP32_PROP else prob.newton_rtol_fp64
         c.newton_rtol = float(newton_rtol)
+        c.resampling = int(getattr(prob, "resampling", 0) if resampling is None else resampling)
         c.state_floor = _dp(self.fl)
         c.precision = int(precision)
         self.c = c

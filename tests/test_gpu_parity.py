@@ -176,6 +176,34 @@ def test_resample_degenerate(pf):
     assert pf.lib().pf_test_resample(300, gd.data_ptr(), 5, ad.data_ptr(), None) == pf.PF_EDEGENERATE
 
 
+@pytest.mark.parametrize("N", [1, 7, 256, 257, 1000, 4097, 65549])
+def test_resample_multinomial_bitexact(pf, oracle, N):
+    rng = np.random.default_rng(1000 + N)
+    for trial in range(3):
+        g = rng.exponential(size=N) ** (1 + 2 * trial)
+        g[rng.random(N) < 0.2] = 0.0
+        if g.sum() == 0:
+            g[0] = 1.0
+        g /= g.sum()
+        seed, step = int(rng.integers(0, 2**63)), 1 + trial * 17
+        gd = dev(g)
+        ad = torch.zeros(N, dtype=torch.int32, device="cuda")
+        pf.check(pf.lib().pf_test_resample_multinomial(N, gd.data_ptr(), seed, step, ad.data_ptr(), None),
+                 "multinomial")
+        st, want = oracle.resample_multinomial(g, seed, step)
+        assert st == 0
+        assert np.array_equal(ad.cpu().numpy(), want)
+
+
+def test_resample_multinomial_limits(pf):
+    ad = torch.zeros(300, dtype=torch.int32, device="cuda")
+    gd = dev(np.zeros(300))
+    L = pf.lib()
+    assert L.pf_test_resample_multinomial(300, gd.data_ptr(), 1, 1, ad.data_ptr(), None) == pf.PF_EDEGENERATE
+    assert L.pf_test_resample_multinomial(300, gd.data_ptr(), 1, 0, ad.data_ptr(), None) == pf.PF_EINVAL
+    assert L.pf_test_resample_multinomial((1 << 20) + 1, gd.data_ptr(), 1, 1, ad.data_ptr(), None) == pf.PF_EINVAL
+
+
 # ---------------------------------------------------------------- init and one step
 def _get(pf, f):
     x = torch.zeros((f.d, f.N), dtype=torch.float64, device="cuda")
@@ -275,6 +303,25 @@ def test_step_parity_robertson(pf, ctx, oracle, prec, j0):
         assert np.allclose(post["cov"], cov, rtol=1e-7, atol=1e-12)
         assert post["ess"] == pytest.approx(out["ess"], rel=1e-8)
         assert np.allclose(post["state_mean"], out["state_mean"], rtol=1e-9, atol=1e-15)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_step_parity_robertson_multinomial(pf, ctx, oracle, prec):
+    prob = inputs.robertson(1000, 50, seed=2)
+    prob.resampling = 1
+    ora, out, anc_o, anc_g, x, th, lw, post, scale = _step_case(pf, ctx, oracle, prob, prec, 7)
+    same = anc_o == anc_g
+    if prec == 0:
+        assert same.all()
+    else:
+        assert same.mean() > 0.98
+    assert not np.all(np.diff(anc_o) >= 0)     # multinomial ancestors are not sorted
+    err = np.abs(x[same] - ora.x[same]) / scale[same]
+    assert err.max() < TOL[prec], err.max()
+    if prec == 0:
+        mean, cov = ora.moments()
+        assert np.allclose(post["mean"], mean, rtol=1e-10, atol=1e-12)
+        assert np.allclose(post["cov"], cov, rtol=1e-7, atol=1e-12)
 
 
 @pytest.mark.parametrize("prec", [0, 1])

@@ -58,6 +58,13 @@ def test_small_robertson_within_3_mcse(pf, oracle):
     _check(pf, oracle, inputs.config_small(), (pf.PF_PREC_FP64, pf.PF_PREC_FP32_PROP), R=16, T=50)
 
 
+def test_small_robertson_multinomial_within_3_mcse(pf, oracle):
+    """The small configuration with the multinomial index draw on both sides."""
+    prob = inputs.config_small()
+    prob.resampling = 1
+    _check(pf, oracle, prob, (pf.PF_PREC_FP32_PROP,), R=16, T=50)
+
+
 def test_robertson_200_steps_within_3_mcse(pf, oracle):
     """The large Robertson schedule (200 observations) at N=8192, R=8."""
     prob = inputs.robertson(8192, 200, seed=0)
