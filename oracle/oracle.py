@@ -41,7 +41,7 @@ class _Cfg(C.Structure):
                 ("kmax", C.c_int), ("rtol", C.c_double),
                 ("floor_", C.c_double * DMAX), ("x0", C.c_double * DMAX),
                 ("prior_mean", C.c_double * PMAX), ("prior_sd", C.c_double * PMAX),
-                ("resampling", C.c_int)]
+                ("resampling", C.c_int), ("lmm", C.c_int)]
 
 
 class _State(C.Structure):
@@ -78,6 +78,10 @@ def lib():
         L.or_u01.restype = C.c_double
         L.or_normals.argtypes = [C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint64, C.c_int, dp]
         L.or_bdf.argtypes = [C.c_int, dp, dp, dp]
+        L.or_am.argtypes = [C.c_int, dp, dp]
+        L.or_psi_lmm.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, dp, dp, dp, dp, C.c_double, C.c_int,
+                                 C.c_int, C.c_int, C.c_double, C.c_int, dp, dp, C.c_int, dp, dp,
+                                 C.POINTER(_PsiStats)]
         L.or_rhs.argtypes = [C.c_int, C.c_int, C.c_int, dp, dp, dp, dp, dp, dp]
         L.or_lu_solve.argtypes = [C.c_int, dp, dp]
         L.or_psi.argtypes = [C.c_int, C.c_int, C.c_int, dp, dp, dp, dp, C.c_double, C.c_int,
@@ -170,9 +174,20 @@ def lu_solve(A, b):
     return b
 
 
+def am(q):
+    """Adams-Moulton q-step coefficients (beta_0..beta_3) and |error constant|."""
+    beta = np.zeros(4)
+    e = np.zeros(1)
+    rc = lib().or_am(int(q), _dp(beta), _dp(e))
+    if rc:
+        raise ValueError(q)
+    return beta, float(e[0])
+
+
 def psi(model, x0, theta, h, M, k, lte=False, rtol=1e-12, kmax=10, floor=None,
-        mc=None, rates_fixed=None, hist=None):
-    """One particle over one interval; returns (x, gamma, stats dict)."""
+        mc=None, rates_fixed=None, hist=None, lmm=0):
+    """One particle over one interval; returns (x, gamma, stats dict).
+    lmm: 0 BDF (order k), 1 Adams-Moulton (k steps)."""
     x0 = _f64(x0)
     theta = _f64(theta)
     d, p = len(x0), len(theta)
@@ -187,9 +202,9 @@ def psi(model, x0, theta, h, M, k, lte=False, rtol=1e-12, kmax=10, floor=None,
         hptr, nq = _dp(hh), hh.shape[0]
     else:
         hptr, nq = None, 0
-    lib().or_psi(model, d, p, _dp(mc), _dp(rf), _dp(x0), _dp(theta), float(h), int(M), int(k),
-                 1 if lte else 0, float(rtol), int(kmax), _dp(floor), hptr, nq, _dp(xo), _dp(go),
-                 C.byref(st))
+    lib().or_psi_lmm(int(lmm), model, d, p, _dp(mc), _dp(rf), _dp(x0), _dp(theta), float(h), int(M), int(k),
+                     1 if lte else 0, float(rtol), int(kmax), _dp(floor), hptr, nq, _dp(xo), _dp(go),
+                     C.byref(st))
     return xo, go, {"newton_iters": st.newton_iters, "newton_fails": st.newton_fails,
                     "lu_fails": st.lu_fails}
 
@@ -302,6 +317,7 @@ class Filter:
         cfg.kmax = int(prob.newton_max_iter)
         cfg.rtol = float(prob.newton_rtol_fp64 if rtol is None else rtol)
         cfg.resampling = int(getattr(prob, "resampling", 0) if resampling is None else resampling)
+        cfg.lmm = int(getattr(prob, "lmm", 0))
         for i in range(d):
             cfg.floor_[i] = float(prob.state_floor[i])
             cfg.x0[i] = float(prob.x0[i])

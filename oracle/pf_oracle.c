@@ -117,6 +117,21 @@ int or_bdf(int q, double alpha[4], double* beta, double* errc)
     }
 }
 
+/* Adams-Moulton, q steps (order q + 1):                                     */
+/*   x_m = x_{m-1} + h (beta_0 f_m + beta_1 f_{m-1} + ... + beta_q f_{m-q}),  */
+/* AM1 the trapezoidal rule; errc = |C_{q+2}|, the local error constant.      */
+int or_am(int q, double beta[4], double* errc)
+{
+    for (int i = 0; i < 4; ++i) beta[i] = 0.0;
+    switch (q) {
+    case 1: beta[0] = 1.0 / 2.0; beta[1] = 1.0 / 2.0; *errc = 1.0 / 12.0; return 0;
+    case 2: beta[0] = 5.0 / 12.0; beta[1] = 8.0 / 12.0; beta[2] = -1.0 / 12.0; *errc = 1.0 / 24.0; return 0;
+    case 3: beta[0] = 9.0 / 24.0; beta[1] = 19.0 / 24.0; beta[2] = -5.0 / 24.0; beta[3] = 1.0 / 24.0;
+            *errc = 19.0 / 720.0; return 0;
+    default: return OR_EINVAL;
+    }
+}
+
 /* weights of the degree-q polynomial through x_{m-1},...,x_{m-1-q} evaluated
  * one step ahead: (-1)^i binom(q+1, i+1) for x_{m-1-i}. */
 static void or_extrap_weights(int q, double w[4])
@@ -372,6 +387,147 @@ int or_psi(int model, int d, int p, const double* mc, const double* rates_fixed,
 }
 
 /* ------------------------------------------------------------------------- */
+/* Psi with the Adams-Moulton family (the paper's other implicit LMMs).      */
+/*                                                                            */
+/* Reading (naming): AMk is the k-step Adams-Moulton formula, of order k + 1 */
+/* (AM1 = trapezoidal rule), so that AM1 differs from BDF1 = backward Euler   */
+/* (the paper times them differently) and "the first three of each family"   */
+/* count steps as for AB and BDF.                                             */
+/* Reading (start-up): as for BDF, each interval restarts from x_j alone;     */
+/* step m has the derivatives f_0 .. f_{m-1} and uses q = min(k, m) steps.    */
+/* f_m = f(x_m) is evaluated once at the accepted x_m.                        */
+/* Reading (Newton): the same full Newton as BDF on                           */
+/* G(x) = x - psi - h beta_0 f(x), psi = x_{m-1} + h sum_{i>=1} beta_i f_{m-i}, */
+/* started from x_0 at step 1 and from the extrapolation below afterwards.    */
+/* Reading (innovation variance, parity unpinned against the paper): Milne's */
+/* device with a polynomial predictor instead of an Adams-Bashforth one (an   */
+/* explicit derivative-based predictor is unstable for the stiff components   */
+/* when h |lambda| >> 1): x^(0) the degree-r extrapolation through            */
+/* x_{m-1} .. x_{m-1-r}, r = min(q + 1, m - 1, 3) (error constant 1), or at   */
+/* step 1 the Euler value x_0 + h f_0 (error constant 1/2);                   */
+/*   e_m = |C| / (C* + |C|) (I - h beta_0 J)^{-1} (x_m - x^(0)),              */
+/*   Gamma = diag(sum_m e_m^2).                                               */
+/* `hist` (pins only): earlier values x_{-1}, ... on the same grid; their     */
+/* derivatives join the history so the formula runs at full order.           */
+/* ------------------------------------------------------------------------- */
+int or_psi_am(int model, int d, int p, const double* mc, const double* rates_fixed,
+              const double* x0, const double* theta, double h, int M, int k,
+              int want_lte, double rtol, int kmax, const double* floor_,
+              const double* hist, int q_hist,
+              double* x_out, double* gamma_out, or_psi_stats* st)
+{
+    /* H[0] = x_{m-1}, H[1] = x_{m-2}, ...; F[r] = f(H[r]) */
+    double H[5][OR_DMAX], F[4][OR_DMAX];
+    int nh = 1;
+    memcpy(H[0], x0, sizeof(double) * d);
+    if (hist) {
+        for (int r = 0; r < q_hist && r < 4; ++r) memcpy(H[r + 1], hist + r * d, sizeof(double) * d);
+        nh = 1 + (q_hist < 4 ? q_hist : 4);
+    }
+    for (int r = 0; r < nh && r < 4; ++r) or_rhs(model, d, p, mc, rates_fixed, H[r], theta, F[r], NULL);
+    double gam[OR_DMAX];
+    for (int i = 0; i < d; ++i) gam[i] = 0.0;
+
+    for (int m = 1; m <= M; ++m) {
+        int nf = nh < 4 ? nh : 4;             /* derivatives available: f_{m-1} .. */
+        int q = nf < k ? nf : k;
+        double beta[4], errc;
+        or_am(q, beta, &errc);
+
+        /* comparison value x^(0) and its error constant; Newton start */
+        double xp[OR_DMAX], cstar;
+        int r = nh - 1 < q + 1 ? nh - 1 : q + 1;   /* extrapolation degree */
+        if (r > 3) r = 3;
+        if (r == 0) {
+            for (int i = 0; i < d; ++i) xp[i] = H[0][i] + h * F[0][i];
+            cstar = 0.5;
+        } else {
+            double w[4];
+            or_extrap_weights(r, w);
+            for (int i = 0; i < d; ++i) {
+                double s = 0.0;
+                for (int j = 0; j <= r; ++j) s += w[j] * H[j][i];
+                xp[i] = s;
+            }
+            cstar = 1.0;
+        }
+
+        /* psi = x_{m-1} + h sum_{i>=1} beta_i f_{m-i} */
+        double psi[OR_DMAX];
+        for (int i = 0; i < d; ++i) {
+            double s = 0.0;
+            for (int j = 1; j <= q; ++j) s += beta[j] * F[j - 1][i];
+            psi[i] = H[0][i] + h * s;
+        }
+
+        double x[OR_DMAX], Alast[OR_DMAX * OR_DMAX];
+        memcpy(x, r == 0 ? H[0] : xp, sizeof(double) * d);
+        double c = h * beta[0];
+        int conv = 0;
+        for (int it = 0; it < kmax; ++it) {
+            double f[OR_DMAX], J[OR_DMAX * OR_DMAX], A[OR_DMAX * OR_DMAX], rhs[OR_DMAX];
+            or_rhs(model, d, p, mc, rates_fixed, x, theta, f, J);
+            for (int i = 0; i < d; ++i) rhs[i] = -(x[i] - psi[i] - c * f[i]);
+            for (int a = 0; a < d; ++a)
+                for (int b = 0; b < d; ++b) A[a * d + b] = (a == b ? 1.0 : 0.0) - c * J[a * d + b];
+            memcpy(Alast, A, sizeof(double) * d * d);
+            if (st) st->newton_iters++;
+            if (or_lu_solve(d, A, rhs) != 0) {
+                if (st) st->lu_fails++;
+                for (int i = 0; i < d; ++i) x[i] = NAN;
+                break;
+            }
+            double worst = 0.0;
+            for (int i = 0; i < d; ++i) {
+                x[i] += rhs[i];
+                double sc = fabs(x[i]) > floor_[i] ? fabs(x[i]) : floor_[i];
+                double rr = fabs(rhs[i]) / sc;
+                if (rr != rr) rr = INFINITY;
+                if (rr > worst) worst = rr;
+            }
+            if (worst <= rtol) { conv = 1; break; }
+        }
+        if (!conv && st) st->newton_fails++;
+
+        if (want_lte) {
+            double kap = errc / (cstar + errc);
+            double e[OR_DMAX];
+            for (int i = 0; i < d; ++i) e[i] = x[i] - xp[i];
+            if (or_lu_solve(d, Alast, e) != 0)
+                for (int i = 0; i < d; ++i) e[i] = NAN;
+            for (int i = 0; i < d; ++i) {
+                double ei = kap * e[i];
+                gam[i] += ei * ei;
+            }
+        }
+
+        /* shift the histories; f at the accepted value */
+        for (int j = 4; j > 0; --j) memcpy(H[j], H[j - 1], sizeof(double) * d);
+        for (int j = 3; j > 0; --j) memcpy(F[j], F[j - 1], sizeof(double) * d);
+        memcpy(H[0], x, sizeof(double) * d);
+        or_rhs(model, d, p, mc, rates_fixed, x, theta, F[0], NULL);
+        if (nh < 5) nh++;
+    }
+    memcpy(x_out, H[0], sizeof(double) * d);
+    if (gamma_out) memcpy(gamma_out, gam, sizeof(double) * d);
+    return OR_OK;
+}
+
+/* Psi of either family: lmm 0 BDF, 1 Adams-Moulton */
+int or_psi_lmm(int lmm, int model, int d, int p, const double* mc, const double* rates_fixed,
+               const double* x0, const double* theta, double h, int M, int k,
+               int want_lte, double rtol, int kmax, const double* floor_,
+               const double* hist, int q_hist,
+               double* x_out, double* gamma_out, or_psi_stats* st)
+{
+    if (lmm == 1)
+        return or_psi_am(model, d, p, mc, rates_fixed, x0, theta, h, M, k, want_lte, rtol, kmax, floor_,
+                         hist, q_hist, x_out, gamma_out, st);
+    return or_psi(model, d, p, mc, rates_fixed, x0, theta, h, M, k, want_lte, rtol, kmax, floor_,
+                  hist, q_hist, x_out, gamma_out, st);
+}
+
+/* ------------------------------------------------------------------------- */
 /* Likelihood pi(y | x): Gaussian, independent components, known sd sigma_i, */
 /* observing x_{o_i}.  Normalising constants cancel in both weight           */
 /* normalisations of Algorithm 1 (steps 3(a) and 5) and are dropped.         */
@@ -577,6 +733,7 @@ typedef struct {
     double x0[OR_DMAX];
     double prior_mean[OR_PMAX], prior_sd[OR_PMAX];
     int resampling;             /* 0 systematic (integer CDF), 1 multinomial */
+    int lmm;                    /* 0 BDF, 1 Adams-Moulton */
 } or_config;
 
 typedef struct {
@@ -656,7 +813,7 @@ int or_filter_step(const or_config* cfg, or_state* s, double t_next,
     for (long n = 0; n < N; ++n) {
         for (int i = 0; i < p; ++i) mshr[n * p + i] = a * s->theta[n * p + i] + (1.0 - a) * s->theta_bar[i];
         or_psi_stats st = {0, 0, 0};
-        or_psi(cfg->model, d, p, cfg->mc, cfg->rates_fixed, s->x + n * d, mshr + n * p, h,
+        or_psi_lmm(cfg->lmm, cfg->model, d, p, cfg->mc, cfg->rates_fixed, s->x + n * d, mshr + n * p, h,
                cfg->substeps, cfg->order, 0, cfg->rtol, cfg->kmax, cfg->floor_, NULL, 0,
                xbar + n * d, NULL, &st);
         it_tot += st.newton_iters; fail_tot += st.newton_fails; lu_tot += st.lu_fails;
@@ -696,7 +853,7 @@ int or_filter_step(const or_config* cfg, or_state* s, double t_next,
          * x_{j+1} = Psi(x_j, theta_{j+1}, h) + v */
         double xt[OR_DMAX], gam[OR_DMAX], zz[OR_DMAX];
         or_psi_stats st = {0, 0, 0};
-        or_psi(cfg->model, d, p, cfg->mc, cfg->rates_fixed, xj, thn + n * p, h, cfg->substeps,
+        or_psi_lmm(cfg->lmm, cfg->model, d, p, cfg->mc, cfg->rates_fixed, xj, thn + n * p, h, cfg->substeps,
                cfg->order, 1, cfg->rtol, cfg->kmax, cfg->floor_, NULL, 0, xt, gam, &st);
         it_tot += st.newton_iters; fail_tot += st.newton_fails; lu_tot += st.lu_fails;
         or_normals(cfg->seed, step, (uint64_t)n, PUR_INNOV, d, zz);
@@ -759,7 +916,7 @@ int or_filter_stage1(const or_config* cfg, const or_state* s, double t_next,
     for (long n = 0; n < N; ++n) {
         double mm[OR_PMAX], xb[OR_DMAX];
         for (int i = 0; i < p; ++i) mm[i] = a * s->theta[n * p + i] + (1.0 - a) * s->theta_bar[i];
-        or_psi(cfg->model, d, p, cfg->mc, cfg->rates_fixed, s->x + n * d, mm, h, cfg->substeps,
+        or_psi_lmm(cfg->lmm, cfg->model, d, p, cfg->mc, cfg->rates_fixed, s->x + n * d, mm, h, cfg->substeps,
                cfg->order, 0, cfg->rtol, cfg->kmax, cfg->floor_, NULL, 0, xb, NULL, NULL);
         lg[n] = s->logw[n] + or_loglik(m, cfg->obs, y, sigma, xb);
     }

@@ -73,6 +73,7 @@ class Problem:
     newton_rtol_fp32: float = 2e-6
     state_floor: np.ndarray = None   # (d,) scale floors (Newton test, parity)
     resampling: int = 0              # step 3(b): 0 systematic, 1 multinomial
+    lmm: int = 0                     # 0 BDF (order k), 1 Adams-Moulton (k steps)
 
     @property
     def T(self) -> int:
