@@ -40,6 +40,12 @@ FLOPS = {
     inputs.MODEL_ROBERTSON: {"iter": 60, "sub_predict": 22, "sub_update": 47},
     inputs.MODEL_CHAIN: {"iter": 384, "sub_predict": 177, "sub_update": 305},
 }
+# Adams-Moulton steps add the derivative at the accepted value (Robertson 8,
+# chain 64 + 16 reciprocals) to the same per-step bookkeeping
+FLOPS_AM = {
+    inputs.MODEL_ROBERTSON: {"iter": 60, "sub_predict": 30, "sub_update": 55},
+    inputs.MODEL_CHAIN: {"iter": 384, "sub_predict": 257, "sub_update": 385},
+}
 # HBM bytes of one k_update launch (Robertson, N = 2^17, FP32 propagation)
 # from two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE; KiB per dispatch),
 # each scaled by what the counter reads for a plain 1 GiB device copy in the
@@ -138,7 +144,7 @@ def time_path(pf, ctx, prob, prec, steps, warmup):
     s1 = f.stats()
     f.close()
     n = prob.n_particles
-    fl = FLOPS[prob.model]
+    fl = (FLOPS_AM if getattr(prob, "lmm", 0) else FLOPS)[prob.model]
     iters_upd = s1["newton_update"] - s0["newton_update"]
     iters_pred = s1["newton_predict"] - s0["newton_predict"]
     flop_upd = iters_upd * fl["iter"] + steps * n * prob.substeps * fl["sub_update"]
@@ -286,7 +292,7 @@ def single_filter(pf, args, prob):
     model = "robertson" if prob.model == inputs.MODEL_ROBERTSON else "chain16"
     roofline = {
         "bound": "alu",
-        "kernel": f"k_update<{model}, fp32, BDF{prob.order}> (steps 3c-5: gather, proliferate, "
+        "kernel": f"k_update<{model}, fp32, {'AM' if prob.lmm else 'BDF'}{prob.order}> (steps 3c-5: gather, proliferate, "
                   "repropagation with Newton and local-error innovation, weights, tile moments)",
         "achieved": achieved, "peak": PEAK_VALU_NONPACKED, "unit": "TFLOP/s",
         "frac": achieved / PEAK_VALU_NONPACKED,
@@ -306,11 +312,11 @@ def single_filter(pf, args, prob):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"{model} N={prob.n_particles} T={prob.T} BDF{prob.order} "
+        "config": {"workload": f"{model} N={prob.n_particles} T={prob.T} {'AM' if prob.lmm else 'BDF'}{prob.order} "
                                f"M={prob.substeps} fp32-propagation, fp64 weights/moments"
                                + (", multinomial resampling" if prob.resampling else ""),
                    "resampling": "multinomial" if prob.resampling else "systematic",
-                   "particles": prob.n_particles, "observations": prob.T, "bdf_order": prob.order,
+                   "particles": prob.n_particles, "observations": prob.T, "lmm": "AM" if prob.lmm else "BDF", "order": prob.order,
                    "substeps": prob.substeps},
         "fp32": r32,
         "fp64": r64,
@@ -443,6 +449,10 @@ def main():
     ap.add_argument("--streams", type=int, default=2000)
     ap.add_argument("--resampling", default="systematic", choices=["systematic", "multinomial"],
                     help="index draw of step 3(b) for the single-filter configurations")
+    ap.add_argument("--lmm", default="bdf", choices=["bdf", "am"],
+                    help="LMM family of the single-filter configurations (am: Adams-Moulton)")
+    ap.add_argument("--order", type=int, default=0,
+                    help="BDF order or AM steps (0: the configuration's own)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB (a known-size "
                          "reference for the HBM byte counters of a profiler pass)")
@@ -476,6 +486,9 @@ def main():
             print("--steps must be >= 1", file=sys.stderr)
             sys.exit(2)
         prob.resampling = 1 if args.resampling == "multinomial" else 0
+        prob.lmm = 1 if args.lmm == "am" else 0
+        if args.order:
+            prob.order = args.order
         out = single_filter(pf, args, prob)
     print(json.dumps(out))
 

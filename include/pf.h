@@ -52,7 +52,11 @@ typedef enum {
     PF_MODEL_CHAIN16 = 2    /* 16 compartments, first 12 log-rates estimated */
 } pf_model;
 
-typedef enum { PF_LMM_BDF = 0 } pf_lmm;
+/* Implicit LMM family of the propagation (Sec. 2: AM or BDF).  The order
+ * field is the BDF order k (k steps, order k), or for AM the number of steps
+ * k of the Adams-Moulton formula (order k + 1; AM1 is the trapezoidal rule;
+ * AM2 and AM3 are not A-stable, so stiff models need AM1 or small steps). */
+typedef enum { PF_LMM_BDF = 0, PF_LMM_AM = 1 } pf_lmm;
 
 typedef enum {
     PF_PREC_FP64 = 0,      /* propagation (BDF + Newton + LU) in double */
@@ -89,7 +93,7 @@ typedef struct {
     const double* prior_sd;      /* [p] */
     double shrink_a;             /* Liu-West factor, 0 < a < 1; jitter s = sqrt(1 - a^2) */
     pf_lmm lmm;
-    uint32_t order;              /* BDF order k, 1..3 */
+    uint32_t order;              /* BDF order k, or AM steps k; 1..3 */
     uint32_t substeps;           /* fixed steps per observation interval, 1..65536 */
     uint32_t newton_max_iter;    /* 1..64 */
     double newton_rtol;          /* stopping test max |dx_i| / max(|x_i|, floor_i) */

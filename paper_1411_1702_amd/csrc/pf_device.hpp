@@ -137,6 +137,17 @@ struct Robertson {
         k3 = exp_rate(th[2], R(0));
     }
 
+    // f alone (the Adams-Moulton history needs f at each accepted value)
+    __device__ inline void rhs(const R x[D], R f[D]) const
+    {
+        const R r1 = k1 * x[0];
+        const R r2 = k2 * x[1] * x[1];
+        const R r3 = k3 * x[1] * x[2];
+        f[0] = r3 - r1;
+        f[1] = r1 - r2 - r3;
+        f[2] = r2;
+    }
+
     __device__ inline void eval(const R x[D], R c, R f[D], LU& lu) const
     {
         const R r1 = k1 * x[0];
@@ -191,6 +202,16 @@ struct Chain16 {
         for (int i = 0; i < D; ++i) k[i] = i < P ? exp_rate(th[i], R(0)) : (R)fd.rates_fixed[i];
         if constexpr (sizeof(R) == 4) VK = (const R*)fd.mc_f;
         else VK = (const R*)fd.mc;
+    }
+
+    __device__ inline void rhs(const R x[D], R f[D]) const
+    {
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            const R V = VK[i], K = VK[D + i];
+            const R inflow = i == 0 ? R(1) : k[i - 1] * x[i - 1];
+            f[i] = inflow - k[i] * x[i] - V * x[i] * recip(K + x[i]);
+        }
     }
 
     __device__ inline void eval(const R x[D], R c, R f[D], LU& lu) const
@@ -320,6 +341,124 @@ __device__ inline void integrate(const Model& md, R x[Model::D], R gam[Model::D]
         }
         avail = avail < KORD ? avail + 1 : KORD;
     }
+}
+
+// ---------------------------------------------------------------------------
+// Psi with the Adams-Moulton family: M fixed steps of the q-step formula
+//   x_m = x_{m-1} + h (b0 f_m + b1 f_{m-1} + ... + bq f_{m-q}),
+// q = min(KORD, m) (the derivatives f_0 .. f_{m-1} of the restarted
+// interval), AM1 the trapezoidal rule.  The same Newton iteration as BDF on
+// x = psi + h b0 f(x), started from x_{m-1} at m = 1 and from the degree-r
+// extrapolation afterwards, r = min(q + 1, m - 1, 3).  f_m is evaluated once
+// at the accepted x_m.  With LTE, gam accumulates the squared filtered Milne
+// estimates kappa (I - h b0 J)^{-1} (x_m - x^(0)), x^(0) the extrapolation
+// (error constant 1) or at m = 1 the Euler value (1/2),
+// kappa = |C| / (C* + |C|) with |C| the formula's error constant.
+// ---------------------------------------------------------------------------
+struct AmCoef {
+    double b0, b1, b2, b3;
+    double errc;   // |C_{q+2}|
+};
+
+__device__ inline AmCoef am_coef(int q)
+{
+    if (q == 1) return {1.0 / 2.0, 1.0 / 2.0, 0.0, 0.0, 1.0 / 12.0};
+    if (q == 2) return {5.0 / 12.0, 8.0 / 12.0, -1.0 / 12.0, 0.0, 1.0 / 24.0};
+    return {9.0 / 24.0, 19.0 / 24.0, -5.0 / 24.0, 1.0 / 24.0, 19.0 / 720.0};
+}
+
+template <class Model, class R, int KORD, bool LTE>
+__device__ inline void integrate_am(const Model& md, R x[Model::D], R gam[Model::D], double h_d, int M, R rtol,
+                                    const R* __restrict__ floor_, int kmax, uint32_t& iters, uint32_t& fails)
+{
+    constexpr int D = Model::D;
+    const R h = (R)h_d;
+    R fl[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) fl[i] = floor_[i];
+    R h1[D], h2[D], h3[D];       // x_{m-2}, x_{m-3}, x_{m-4}
+    R f0[D], f1[D], f2[D];       // f_{m-1}, f_{m-2}, f_{m-3}
+    if constexpr (LTE) {
+#pragma unroll
+        for (int i = 0; i < D; ++i) gam[i] = R(0);
+    }
+    md.rhs(x, f0);
+    int avail = 0;               // x history beyond x_{m-1}
+    for (int m = 1; m <= M; ++m) {
+        const int q = m < KORD ? m : KORD;
+        const int r0 = q + 1 < avail ? q + 1 : avail;
+        const int r = r0 < 3 ? r0 : 3;
+        const AmCoef co = am_coef(q);
+        const R c = h * (R)co.b0;
+        R psi[D], xp[D], xn[D];
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            R s = (R)co.b1 * f0[i];
+            if (KORD >= 2 && q >= 2) s += (R)co.b2 * f1[i];
+            if (KORD >= 3 && q >= 3) s += (R)co.b3 * f2[i];
+            psi[i] = x[i] + h * s;
+            R p;
+            if (r == 0) p = x[i] + h * f0[i];
+            else if (r == 1) p = R(2) * x[i] - h1[i];
+            else if (r == 2) p = R(3) * x[i] - R(3) * h1[i] + h2[i];
+            else p = R(4) * x[i] - R(6) * h1[i] + R(4) * h2[i] - h3[i];
+            xp[i] = p;
+            xn[i] = r == 0 ? x[i] : p;
+        }
+        typename Model::LU lu;
+        bool ok = false;
+        int it = 0;
+        do {
+            R f[D];
+            md.eval(xn, c, f, lu);
+            R b[D];
+#pragma unroll
+            for (int i = 0; i < D; ++i) b[i] = (psi[i] + c * f[i]) - xn[i];
+            md.solve(lu, b);
+            ok = true;
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                xn[i] += b[i];
+                ok &= rabs(b[i]) <= rtol * rmax(rabs(xn[i]), fl[i]);
+            }
+            ++it;
+        } while (!ok && it < kmax);
+        iters += (uint32_t)it;
+        fails += ok ? 0u : 1u;
+        if constexpr (LTE) {
+            const R cstar = r == 0 ? R(0.5) : R(1);
+            const R kap = (R)co.errc / (cstar + (R)co.errc);
+            R e[D];
+#pragma unroll
+            for (int i = 0; i < D; ++i) e[i] = xn[i] - xp[i];
+            md.solve(lu, e);
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                const R v = kap * e[i];
+                gam[i] += v * v;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            h3[i] = h2[i];
+            h2[i] = h1[i];
+            h1[i] = x[i];
+            x[i] = xn[i];
+            if (KORD >= 3) f2[i] = f1[i];
+            if (KORD >= 2) f1[i] = f0[i];
+        }
+        md.rhs(x, f0);
+        avail = avail < 3 ? avail + 1 : 3;
+    }
+}
+
+// Psi of either LMM family (LMM 0 BDF, 1 Adams-Moulton)
+template <class Model, class R, int KORD, bool LTE, int LMM>
+__device__ inline void integrate_lmm(const Model& md, R x[Model::D], R gam[Model::D], double h_d, int M, R rtol,
+                                     const R* __restrict__ floor_, int kmax, uint32_t& iters, uint32_t& fails)
+{
+    if constexpr (LMM == 1) integrate_am<Model, R, KORD, LTE>(md, x, gam, h_d, M, rtol, floor_, kmax, iters, fails);
+    else integrate<Model, R, KORD, LTE>(md, x, gam, h_d, M, rtol, floor_, kmax, iters, fails);
 }
 
 // Gaussian log-likelihood of the observed components, constants dropped;

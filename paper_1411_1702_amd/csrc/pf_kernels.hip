@@ -814,7 +814,7 @@ __global__ __launch_bounds__(TILE) void k_init_moments(int slot, const FilterDes
 // ---------------------------------------------------------------------------
 // steps 2 and 3(a): shrink, predictor, first-stage log-weights
 // ---------------------------------------------------------------------------
-template <class Model, class R, int KORD, bool INL>
+template <class Model, class R, int KORD, int LMM, bool INL>
 __global__ __launch_bounds__(TILE) void k_predict(Batch B, const FilterDesc* descs, FilterState* states)
 {
     constexpr int D = Model::D, P = Model::P;
@@ -845,7 +845,7 @@ __global__ __launch_bounds__(TILE) void k_predict(Batch B, const FilterDesc* des
             Model md;
             md.set_params(m, fd);
             const R* fl = sizeof(R) == 4 ? (const R*)fd.floor_f : (const R*)fd.floor_;
-            integrate<Model, R, KORD, false>(md, x, nullptr, h, fd.substeps, (R)fd.rtol, fl, fd.kmax,
+            integrate_lmm<Model, R, KORD, false, LMM>(md, x, nullptr, h, fd.substeps, (R)fd.rtol, fl, fd.kmax,
                                              iters, fails);
             const double lb = loglik<R>(x, fd.obs, rec.y, rec.sigma, fd.m);
             lg = fd.logw[cur][n] + lb;
@@ -1073,7 +1073,7 @@ __global__ __launch_bounds__(TILE) void k_scatter(Batch B, const FilterDesc* des
 // ---------------------------------------------------------------------------
 // steps 3(c)-5 per output slot
 // ---------------------------------------------------------------------------
-template <class Model, class R, int KORD, bool INL>
+template <class Model, class R, int KORD, int LMM, bool INL>
 __global__ __launch_bounds__(TILE) void k_update(Batch B, const FilterDesc* descs, FilterState* states)
 {
     constexpr int D = Model::D, P = Model::P;
@@ -1133,7 +1133,8 @@ __global__ __launch_bounds__(TILE) void k_update(Batch B, const FilterDesc* desc
 #pragma unroll
             for (int i = 0; i < D; ++i) xw[i] = x[i];
             const R* fl = sizeof(R) == 4 ? (const R*)fd.floor_f : (const R*)fd.floor_;
-            integrate<Model, R, KORD, true>(md, xw, gam, h, fd.substeps, (R)fd.rtol, fl, fd.kmax, iters, fails);
+            integrate_lmm<Model, R, KORD, true, LMM>(md, xw, gam, h, fd.substeps, (R)fd.rtol, fl, fd.kmax, iters,
+                                                     fails);
             R zi[D];
             normals<D, R>(fd.seed, step, (uint64_t)n, PUR_INNOV, zi);
             R* xo = (R*)fd.x[nxt];
@@ -1250,7 +1251,7 @@ __global__ void k_test_normals(uint64_t n, uint64_t seed, uint64_t step, uint64_
     for (int s = 0; s < COUNT; ++s) out[i * COUNT + s] = z[s];
 }
 
-template <class Model, class R, int KORD, bool LTE>
+template <class Model, class R, int KORD, bool LTE, int LMM>
 __global__ __launch_bounds__(TILE) void k_test_propagate(const FilterDesc* fdp, uint64_t n, const double* xin,
                                                          const double* theta, double h, double* xout,
                                                          double* gamma, unsigned long long* iters_out)
@@ -1268,8 +1269,8 @@ __global__ __launch_bounds__(TILE) void k_test_propagate(const FilterDesc* fdp, 
         Model md;
         md.set_params(th, fd);
         const R* fl = sizeof(R) == 4 ? (const R*)fd.floor_f : (const R*)fd.floor_;
-        integrate<Model, R, KORD, LTE>(md, x, gam, h, fd.substeps, (R)fd.rtol, fl, fd.kmax, iters,
-                                       fails);
+        integrate_lmm<Model, R, KORD, LTE, LMM>(md, x, gam, h, fd.substeps, (R)fd.rtol, fl, fd.kmax, iters,
+                                                fails);
         for (int c = 0; c < D; ++c) {
             xout[c * n + i] = (double)x[c];
             if (LTE && gamma) gamma[c * n + i] = (double)gam[c];

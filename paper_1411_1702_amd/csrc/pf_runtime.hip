@@ -177,39 +177,51 @@ static pf_status prof_collect(pf_context* ctx);
 typedef void (*StepKernel)(Batch, const FilterDesc*, FilterState*);
 typedef void (*MomentsKernel)(Batch, const FilterDesc*, FilterState*, int32_t*);
 
-template <template <class> class Mdl, class R, bool INL>
+template <template <class> class Mdl, class R, int LMM, bool INL>
 static StepKernel pick_predict(int order)
 {
     switch (order) {
-    case 1: return k_predict<Mdl<R>, R, 1, INL>;
-    case 2: return k_predict<Mdl<R>, R, 2, INL>;
-    default: return k_predict<Mdl<R>, R, 3, INL>;
+    case 1: return k_predict<Mdl<R>, R, 1, LMM, INL>;
+    case 2: return k_predict<Mdl<R>, R, 2, LMM, INL>;
+    default: return k_predict<Mdl<R>, R, 3, LMM, INL>;
     }
 }
-template <template <class> class Mdl, class R, bool INL>
+template <template <class> class Mdl, class R, int LMM, bool INL>
 static StepKernel pick_update(int order)
 {
     switch (order) {
-    case 1: return k_update<Mdl<R>, R, 1, INL>;
-    case 2: return k_update<Mdl<R>, R, 2, INL>;
-    default: return k_update<Mdl<R>, R, 3, INL>;
+    case 1: return k_update<Mdl<R>, R, 1, LMM, INL>;
+    case 2: return k_update<Mdl<R>, R, 2, LMM, INL>;
+    default: return k_update<Mdl<R>, R, 3, LMM, INL>;
     }
 }
-template <bool INL>
-static StepKernel predict_kernel(int model, int prec, int order)
+template <template <class> class Mdl, class R, bool INL>
+static StepKernel predict_of(int lmm, int order)
 {
-    if (model == MODEL_ROBERTSON)
-        return prec == PREC_FP32 ? pick_predict<Robertson, float, INL>(order)
-                                 : pick_predict<Robertson, double, INL>(order);
-    return prec == PREC_FP32 ? pick_predict<Chain16, float, INL>(order) : pick_predict<Chain16, double, INL>(order);
+    return lmm == 1 ? pick_predict<Mdl, R, 1, INL>(order) : pick_predict<Mdl, R, 0, INL>(order);
+}
+template <template <class> class Mdl, class R, bool INL>
+static StepKernel update_of(int lmm, int order)
+{
+    return lmm == 1 ? pick_update<Mdl, R, 1, INL>(order) : pick_update<Mdl, R, 0, INL>(order);
 }
 template <bool INL>
-static StepKernel update_kernel(int model, int prec, int order)
+static StepKernel predict_kernel(int model, int lmm, int prec, int order)
 {
     if (model == MODEL_ROBERTSON)
-        return prec == PREC_FP32 ? pick_update<Robertson, float, INL>(order)
-                                 : pick_update<Robertson, double, INL>(order);
-    return prec == PREC_FP32 ? pick_update<Chain16, float, INL>(order) : pick_update<Chain16, double, INL>(order);
+        return prec == PREC_FP32 ? predict_of<Robertson, float, INL>(lmm, order)
+                                 : predict_of<Robertson, double, INL>(lmm, order);
+    return prec == PREC_FP32 ? predict_of<Chain16, float, INL>(lmm, order)
+                             : predict_of<Chain16, double, INL>(lmm, order);
+}
+template <bool INL>
+static StepKernel update_kernel(int model, int lmm, int prec, int order)
+{
+    if (model == MODEL_ROBERTSON)
+        return prec == PREC_FP32 ? update_of<Robertson, float, INL>(lmm, order)
+                                 : update_of<Robertson, double, INL>(lmm, order);
+    return prec == PREC_FP32 ? update_of<Chain16, float, INL>(lmm, order)
+                             : update_of<Chain16, double, INL>(lmm, order);
 }
 
 typedef void (*InitKernel)(int, const FilterDesc*, FilterState*);
@@ -220,7 +232,8 @@ static InitKernel init_kernel(int model, int prec)
     return prec == PREC_FP32 ? k_init<Chain16<float>, float> : k_init<Chain16<double>, double>;
 }
 
-static int class_of(const FilterDesc& d) { return (d.model - 1) * 8 + d.prec * 4 + d.order; }
+// kernel class: ((model - 1) * 2 + lmm) * 8 + precision * 4 + order
+static int class_of(const FilterDesc& d) { return ((d.model - 1) * 2 + d.lmm) * 8 + d.prec * 4 + d.order; }
 
 // ---------------------------------------------------------------------------
 // configuration checks
@@ -244,7 +257,7 @@ static pf_status check_config(const pf_config* c)
     if (c->n_particles < 1 || c->n_particles > (1ull << 24)) return fail(PF_EINVAL, "n_particles must be 1..2^24");
     if (!c->x0 || !c->prior_mean || !c->prior_sd || !c->state_floor) return fail(PF_EINVAL, "NULL array in config");
     if (!(c->shrink_a > 0.0 && c->shrink_a < 1.0)) return fail(PF_EINVAL, "shrink_a must be in (0,1)");
-    if (c->lmm != PF_LMM_BDF) return fail(PF_EINVAL, "only BDF is implemented");
+    if (c->lmm != PF_LMM_BDF && c->lmm != PF_LMM_AM) return fail(PF_EINVAL, "lmm must be BDF or AM");
     if (c->order < 1 || c->order > 3) return fail(PF_EINVAL, "order must be 1..3");
     if (c->substeps < 1 || c->substeps > SUBSTEPS_MAX) return fail(PF_EINVAL, "substeps must be 1..65536");
     if (c->newton_max_iter < 1 || c->newton_max_iter > KMAX_MAX) return fail(PF_EINVAL, "newton_max_iter must be 1..64");
@@ -271,6 +284,7 @@ static void fill_static(FilterDesc& d, const pf_config* c)
     d.kmax = (int)c->newton_max_iter;
     d.prec = c->precision == PF_PREC_FP32_PROP ? PREC_FP32 : PREC_FP64;
     d.resampling = c->resampling == PF_RESAMPLE_MULTINOMIAL ? 1 : 0;
+    d.lmm = c->lmm == PF_LMM_AM ? 1 : 0;
     for (uint32_t i = 0; i < c->m; ++i) d.obs[i] = (int)c->obs_index[i];
     d.n = (int)c->n_particles;
     d.ntiles = (d.n + TILE - 1) / TILE;
@@ -673,9 +687,9 @@ static pf_status submit(pf_context* ctx, uint32_t count, pf_filter* const* fs, c
         }
         if (timed && (e = hipEventRecord(sg.tev[0], ctx->stream)) != hipSuccess) return e;
         for (const Range& r : ranges) {
-            const int model = r.cls / 8 + 1, prec = (r.cls % 8) / 4, order = r.cls % 4;
-            hipLaunchKernelGGL(inline_rec ? predict_kernel<true>(model, prec, order)
-                                          : predict_kernel<false>(model, prec, order),
+            const int model = r.cls / 16 + 1, lmm = (r.cls / 8) % 2, prec = (r.cls % 8) / 4, order = r.cls % 4;
+            hipLaunchKernelGGL(inline_rec ? predict_kernel<true>(model, lmm, prec, order)
+                                          : predict_kernel<false>(model, lmm, prec, order),
                                dim3(grid_for(ctx, r.cnt)), dim3(TILE), 0,
                                ctx->stream, part(r), ctx->d_desc, ctx->d_state);
         }
@@ -688,9 +702,9 @@ static pf_status submit(pf_context* ctx, uint32_t count, pf_filter* const* fs, c
                            ctx->d_state);
         if (timed && (e = hipEventRecord(sg.tev[2], ctx->stream)) != hipSuccess) return e;
         for (const Range& r : ranges) {
-            const int model = r.cls / 8 + 1, prec = (r.cls % 8) / 4, order = r.cls % 4;
-            hipLaunchKernelGGL(inline_rec ? update_kernel<true>(model, prec, order)
-                                          : update_kernel<false>(model, prec, order),
+            const int model = r.cls / 16 + 1, lmm = (r.cls / 8) % 2, prec = (r.cls % 8) / 4, order = r.cls % 4;
+            hipLaunchKernelGGL(inline_rec ? update_kernel<true>(model, lmm, prec, order)
+                                          : update_kernel<false>(model, lmm, prec, order),
                                dim3(grid_for(ctx, r.cnt)), dim3(TILE), 0,
                                ctx->stream, part(r), ctx->d_desc, ctx->d_state);
         }
@@ -932,14 +946,19 @@ extern "C" pf_status pf_test_normals(uint64_t n, uint64_t seed, uint64_t step, u
 typedef void (*PropKernel)(const FilterDesc*, uint64_t, const double*, const double*, double, double*, double*,
                            unsigned long long*);
 
-template <template <class> class Mdl, class R, bool LTE>
-static PropKernel pick_prop(int order)
+template <template <class> class Mdl, class R, bool LTE, int LMM>
+static PropKernel pick_prop_lmm(int order)
 {
     switch (order) {
-    case 1: return k_test_propagate<Mdl<R>, R, 1, LTE>;
-    case 2: return k_test_propagate<Mdl<R>, R, 2, LTE>;
-    default: return k_test_propagate<Mdl<R>, R, 3, LTE>;
+    case 1: return k_test_propagate<Mdl<R>, R, 1, LTE, LMM>;
+    case 2: return k_test_propagate<Mdl<R>, R, 2, LTE, LMM>;
+    default: return k_test_propagate<Mdl<R>, R, 3, LTE, LMM>;
     }
+}
+template <template <class> class Mdl, class R, bool LTE>
+static PropKernel pick_prop(int lmm, int order)
+{
+    return lmm == 1 ? pick_prop_lmm<Mdl, R, LTE, 1>(order) : pick_prop_lmm<Mdl, R, LTE, 0>(order);
 }
 
 extern "C" pf_status pf_test_propagate(const pf_config* cfg, uint64_t n, const double* x_in, const double* theta,
@@ -960,11 +979,11 @@ extern "C" pf_status pf_test_propagate(const pf_config* cfg, uint64_t n, const d
     PropKernel k;
     const bool f32 = d.prec == PREC_FP32;
     if (d.model == MODEL_ROBERTSON)
-        k = f32 ? (lte ? pick_prop<Robertson, float, true>(d.order) : pick_prop<Robertson, float, false>(d.order))
-                : (lte ? pick_prop<Robertson, double, true>(d.order) : pick_prop<Robertson, double, false>(d.order));
+        k = f32 ? (lte ? pick_prop<Robertson, float, true>(d.lmm, d.order) : pick_prop<Robertson, float, false>(d.lmm, d.order))
+                : (lte ? pick_prop<Robertson, double, true>(d.lmm, d.order) : pick_prop<Robertson, double, false>(d.lmm, d.order));
     else
-        k = f32 ? (lte ? pick_prop<Chain16, float, true>(d.order) : pick_prop<Chain16, float, false>(d.order))
-                : (lte ? pick_prop<Chain16, double, true>(d.order) : pick_prop<Chain16, double, false>(d.order));
+        k = f32 ? (lte ? pick_prop<Chain16, float, true>(d.lmm, d.order) : pick_prop<Chain16, float, false>(d.lmm, d.order))
+                : (lte ? pick_prop<Chain16, double, true>(d.lmm, d.order) : pick_prop<Chain16, double, false>(d.lmm, d.order));
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k, dim3((unsigned)((n + TILE - 1) / TILE)), dim3(TILE), 0, st, dd, n, x_in, theta, h, x_out,
                            lte ? gamma : nullptr, (unsigned long long*)iters);

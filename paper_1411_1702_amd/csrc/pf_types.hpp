@@ -44,7 +44,7 @@ struct FilterDesc {
     int32_t order, substeps, kmax, prec;
     int32_t obs[MMAX];
     int32_t n, npad, ntiles, shift;     // shift: resampling scale 2^shift
-    int32_t nacc, g_direct, resampling, pad1;   // resampling: 0 systematic, 1 multinomial
+    int32_t nacc, g_direct, resampling, lmm;    // resampling: 0 systematic, 1 multinomial; lmm: 0 BDF, 1 AM
     uint64_t seed;
     double a, s, rtol;                  // shrink factor, jitter sqrt(1-a^2), Newton rtol
     double prior_mean[PMAX], prior_sd[PMAX];

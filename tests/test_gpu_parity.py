@@ -99,7 +99,7 @@ def _propagate_oracle(oracle, prob, x, theta, h, lte, rtol):
     for i in range(x.shape[0]):
         xo, go, st = oracle.psi(prob.model, x[i], theta[i], h, prob.substeps, prob.order, lte=lte,
                                 rtol=rtol, kmax=prob.newton_max_iter, floor=prob.state_floor,
-                                mc=prob.model_consts, rates_fixed=prob.rates_fixed)
+                                mc=prob.model_consts, rates_fixed=prob.rates_fixed, lmm=prob.lmm)
         xs.append(xo)
         gs.append(go)
         its += st["newton_iters"]
@@ -125,6 +125,47 @@ def test_propagate_robertson(pf, oracle, prec, lte):
             assert np.all(dev_ <= bound), (h, (dev_ / bound).max())
         if prec == 0:
             assert abs(itg - ito) <= 0.01 * ito + 5
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("lte", [False, True])
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_propagate_robertson_am(pf, oracle, prec, lte, k):
+    # Adams-Moulton k steps; AM2 and AM3 on the first interval only (their
+    # stability intervals do not cover the stiff eigenvalue at later steps)
+    prob, sets = _robertson_inputs(oracle, j_list=(1, 10, 25, 45) if k == 1 else (0,))
+    prob.lmm, prob.order = 1, k
+    rtol = prob.newton_rtol_fp64 if prec == 0 else prob.newton_rtol_fp32
+    for x, th, h in sets:
+        xg, gg, itg = _propagate_gpu(pf, prob, prec, x, th, h, lte)
+        xo, go, ito = _propagate_oracle(oracle, prob, x, th, h, lte, rtol)
+        err = relerr(xg, xo, prob.state_floor)
+        assert err.max() < TOL[prec], (k, h, err.max())
+        if lte:
+            noise = 0.0 if prec == 0 else 4 * np.sqrt(prob.substeps) * 2.0**-23 * np.abs(xo)
+            dev_ = np.abs(np.sqrt(gg) - np.sqrt(go))
+            bound = (1e-7 if prec == 0 else 2e-3) * np.maximum(np.sqrt(go), prob.state_floor) + noise
+            assert np.all(dev_ <= bound), (k, h, (dev_ / bound).max())
+        if prec == 0:
+            assert abs(itg - ito) <= 0.01 * ito + 5
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_propagate_chain_am1(pf, oracle, prec):
+    # The trapezoidal rule is A- but not L-stable: with k h up to ~25 a stiff
+    # component's error is multiplied by |(1 - z/2)/(1 + z/2)| ~ 0.85 per step
+    # instead of ~1/z (BDF), so FP32 rounding in those components persists
+    # over the 40 steps; the FP32 bound is set for that (5e-3), FP64 as BDF.
+    prob, sets = _chain_inputs()
+    prob.lmm, prob.order = 1, 1
+    rtol = prob.newton_rtol_fp64 if prec == 0 else prob.newton_rtol_fp32
+    for x, th, h in sets:
+        xg, gg, _ = _propagate_gpu(pf, prob, prec, x, th, h, True)
+        xo, go, _ = _propagate_oracle(oracle, prob, x, th, h, True, rtol)
+        err = relerr(xg, xo, prob.state_floor)
+        assert err.max() < (TOL[0] if prec == 0 else 5e-3), (h, err.max())
+        if prec == 1:
+            assert np.median(err) < 1e-5
 
 
 def _chain_inputs(n=600, seed=3):
@@ -250,7 +291,7 @@ def _innovation_scale(oracle, prob, x_in, t_in, anc, theta_new, step):
         xt, gam, _ = oracle.psi(prob.model, x_in[k], theta_new[n], h, prob.substeps, prob.order,
                                 lte=True, rtol=prob.newton_rtol_fp64, kmax=prob.newton_max_iter,
                                 floor=prob.state_floor, mc=prob.model_consts,
-                                rates_fixed=prob.rates_fixed)
+                                rates_fixed=prob.rates_fixed, lmm=prob.lmm)
         z = oracle.normals(prob.seed, step, n, oracle.PUR_INNOV, prob.d)
         out[n] = np.maximum(np.abs(xt), np.sqrt(gam) * np.maximum(np.abs(z), 1.0))
     return out
@@ -316,6 +357,24 @@ def test_step_parity_robertson_multinomial(pf, ctx, oracle, prec):
     else:
         assert same.mean() > 0.98
     assert not np.all(np.diff(anc_o) >= 0)     # multinomial ancestors are not sorted
+    err = np.abs(x[same] - ora.x[same]) / scale[same]
+    assert err.max() < TOL[prec], err.max()
+    if prec == 0:
+        mean, cov = ora.moments()
+        assert np.allclose(post["mean"], mean, rtol=1e-10, atol=1e-12)
+        assert np.allclose(post["cov"], cov, rtol=1e-7, atol=1e-12)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_step_parity_robertson_am1(pf, ctx, oracle, prec):
+    prob = inputs.robertson(1000, 50, seed=2)
+    prob.lmm, prob.order = 1, 1
+    ora, out, anc_o, anc_g, x, th, lw, post, scale = _step_case(pf, ctx, oracle, prob, prec, 7)
+    same = anc_o == anc_g
+    if prec == 0:
+        assert same.all()
+    else:
+        assert same.mean() > 0.98
     err = np.abs(x[same] - ora.x[same]) / scale[same]
     assert err.max() < TOL[prec], err.max()
     if prec == 0:
