@@ -79,6 +79,7 @@ def lib():
         L.or_normals.argtypes = [C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint64, C.c_int, dp]
         L.or_bdf.argtypes = [C.c_int, dp, dp, dp]
         L.or_am.argtypes = [C.c_int, dp, dp]
+        L.or_sdirk.argtypes = [C.c_int, dp, C.POINTER(C.c_int)]
         L.or_psi_lmm.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, dp, dp, dp, dp, C.c_double, C.c_int,
                                  C.c_int, C.c_int, C.c_double, C.c_int, dp, dp, C.c_int, dp, dp,
                                  C.POINTER(_PsiStats)]
@@ -184,10 +185,20 @@ def am(q):
     return beta, float(e[0])
 
 
+def sdirk(k):
+    """Butcher matrix (3x3, zero padded) and stage count of the start-up SDIRK of order k."""
+    A = np.zeros(9)
+    ns = C.c_int(0)
+    if lib().or_sdirk(int(k), _dp(A), C.byref(ns)):
+        raise ValueError(k)
+    n = ns.value
+    return A.reshape(3, 3)[:n, :n].copy(), n
+
+
 def psi(model, x0, theta, h, M, k, lte=False, rtol=1e-12, kmax=10, floor=None,
         mc=None, rates_fixed=None, hist=None, lmm=0):
     """One particle over one interval; returns (x, gamma, stats dict).
-    lmm: 0 BDF (order k), 1 Adams-Moulton (k steps)."""
+    lmm: 0 BDF (order k), 1 Adams-Moulton (k steps), 2 BDF with the SDIRK start-up."""
     x0 = _f64(x0)
     theta = _f64(theta)
     d, p = len(x0), len(theta)

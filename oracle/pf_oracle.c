@@ -284,11 +284,106 @@ typedef struct {
     long lu_fails;      /* singular or non-finite pivots */
 } or_psi_stats;
 
+/* ------------------------------------------------------------------------- */
+/* Order-preserving start-up (reading R2-S): the steps of an interval that    */
+/* lack the history for the full BDF order, m = 1 .. k-1, are taken with an   */
+/* L-stable, stiffly accurate SDIRK method of order k (Alexander 1977): for   */
+/* k = 2 two stages with gamma = 1 - 1/sqrt(2); for k = 3 three stages with   */
+/* gamma the root of gamma^3 - 3 gamma^2 + 3 gamma / 2 - 1/6 in (1/6, 1/2).   */
+/* Stage i solves Y = x_{m-1} + h sum_{j<i} a_ij f(Y_j) + h gamma f(Y) by the */
+/* same Newton iteration (started from x_{m-1}, then from the previous        */
+/* stage); x_m is the last stage.  The innovation variance of these steps     */
+/* keeps the ramp's estimator (the comparison value and kappa of the BDF     */
+/* order the ramp would use), with J at x_m.                                  */
+/* ------------------------------------------------------------------------- */
+int or_sdirk(int k, double A[3][3], int* stages)
+{
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) A[i][j] = 0.0;
+    if (k == 2) {
+        const double g = 1.0 - sqrt(0.5);
+        A[0][0] = g;
+        A[1][0] = 1.0 - g; A[1][1] = g;
+        *stages = 2;
+        return 0;
+    }
+    if (k == 3) {
+        /* the root in (1/6, 1/2), by bisection on the cubic */
+        double lo = 1.0 / 6.0, hi = 0.5;
+        for (int it = 0; it < 200; ++it) {
+            double mid = 0.5 * (lo + hi);
+            double v = ((mid - 3.0) * mid + 1.5) * mid - 1.0 / 6.0;
+            double vlo = ((lo - 3.0) * lo + 1.5) * lo - 1.0 / 6.0;
+            if ((v > 0) == (vlo > 0)) lo = mid;
+            else hi = mid;
+        }
+        const double g = 0.5 * (lo + hi);
+        A[0][0] = g;
+        A[1][0] = (1.0 - g) / 2.0; A[1][1] = g;
+        A[2][0] = -(6.0 * g * g - 16.0 * g + 1.0) / 4.0;
+        A[2][1] = (6.0 * g * g - 20.0 * g + 5.0) / 4.0;
+        A[2][2] = g;
+        *stages = 3;
+        return 0;
+    }
+    return OR_EINVAL;
+}
+
+/* one Newton solve of Y = psi + c f(Y) from the guess in x (overwritten); the
+ * matrix of the last iteration is left in Alast */
+static int newton_solve(int model, int d, int p, const double* mc, const double* rates_fixed,
+                        const double* theta, const double* psi, double c, double rtol, int kmax,
+                        const double* floor_, double* x, double* Alast, or_psi_stats* st)
+{
+    int conv = 0;
+    for (int it = 0; it < kmax; ++it) {
+        double f[OR_DMAX], J[OR_DMAX * OR_DMAX], A[OR_DMAX * OR_DMAX], rhs[OR_DMAX];
+        or_rhs(model, d, p, mc, rates_fixed, x, theta, f, J);
+        for (int i = 0; i < d; ++i) rhs[i] = -(x[i] - psi[i] - c * f[i]);
+        for (int a = 0; a < d; ++a)
+            for (int b = 0; b < d; ++b) A[a * d + b] = (a == b ? 1.0 : 0.0) - c * J[a * d + b];
+        if (Alast) memcpy(Alast, A, sizeof(double) * d * d);
+        if (st) st->newton_iters++;
+        if (or_lu_solve(d, A, rhs) != 0) {
+            if (st) st->lu_fails++;
+            for (int i = 0; i < d; ++i) x[i] = NAN;
+            return 0;
+        }
+        double worst = 0.0;
+        for (int i = 0; i < d; ++i) {
+            x[i] += rhs[i];
+            double sc = fabs(x[i]) > floor_[i] ? fabs(x[i]) : floor_[i];
+            double r = fabs(rhs[i]) / sc;
+            if (r != r) r = INFINITY;
+            if (r > worst) worst = r;
+        }
+        if (worst <= rtol) { conv = 1; break; }
+    }
+    if (!conv && st) st->newton_fails++;
+    return conv;
+}
+
+static int or_psi_bdf(int model, int d, int p, const double* mc, const double* rates_fixed,
+                      const double* x0, const double* theta, double h, int M, int k,
+                      int want_lte, double rtol, int kmax, const double* floor_,
+                      const double* hist, int q_hist, int sdirk_start,
+                      double* x_out, double* gamma_out, or_psi_stats* st);
+
 int or_psi(int model, int d, int p, const double* mc, const double* rates_fixed,
            const double* x0, const double* theta, double h, int M, int k,
            int want_lte, double rtol, int kmax, const double* floor_,
            const double* hist, int q_hist,
            double* x_out, double* gamma_out, or_psi_stats* st)
+{
+    return or_psi_bdf(model, d, p, mc, rates_fixed, x0, theta, h, M, k, want_lte, rtol, kmax, floor_, hist,
+                      q_hist, 0, x_out, gamma_out, st);
+}
+
+static int or_psi_bdf(int model, int d, int p, const double* mc, const double* rates_fixed,
+                      const double* x0, const double* theta, double h, int M, int k,
+                      int want_lte, double rtol, int kmax, const double* floor_,
+                      const double* hist, int q_hist, int sdirk_start,
+                      double* x_out, double* gamma_out, or_psi_stats* st)
 {
     /* H[0] = x_{m-1}, H[1] = x_{m-2}, ... (ring of up to 4 values) */
     double H[4][OR_DMAX];
@@ -334,10 +429,49 @@ int or_psi(int model, int d, int p, const double* mc, const double* rates_fixed,
             psi[i] = s;
         }
 
-        /* Newton, from x_0 at step 1 and from the predictor afterwards */
         double x[OR_DMAX], Alast[OR_DMAX * OR_DMAX];
-        memcpy(x, avail == 0 ? H[0] : xp, sizeof(double) * d);
         double c = h * beta;
+        if (sdirk_start && k >= 2 && avail < k - 1) {
+            /* start-up step by SDIRK of order k (x_m = last stage) */
+            double Asd[3][3], F[3][OR_DMAX];
+            int ns;
+            or_sdirk(k, Asd, &ns);
+            memcpy(x, H[0], sizeof(double) * d);
+            for (int sg = 0; sg < ns; ++sg) {
+                double ps[OR_DMAX];
+                for (int i = 0; i < d; ++i) {
+                    double sacc = 0.0;
+                    for (int j = 0; j < sg; ++j) sacc += Asd[sg][j] * F[j][i];
+                    ps[i] = H[0][i] + h * sacc;
+                }
+                newton_solve(model, d, p, mc, rates_fixed, theta, ps, h * Asd[sg][sg], rtol, kmax, floor_, x,
+                             NULL, st);
+                or_rhs(model, d, p, mc, rates_fixed, x, theta, F[sg], NULL);
+            }
+            if (want_lte) {
+                /* the ramp's estimator, with the ramp order's matrix at x_m */
+                double f[OR_DMAX], J[OR_DMAX * OR_DMAX];
+                or_rhs(model, d, p, mc, rates_fixed, x, theta, f, J);
+                for (int a = 0; a < d; ++a)
+                    for (int b = 0; b < d; ++b) Alast[a * d + b] = (a == b ? 1.0 : 0.0) - c * J[a * d + b];
+                double kap = fabs(errc) / (cstar + fabs(errc));
+                double e[OR_DMAX];
+                for (int i = 0; i < d; ++i) e[i] = x[i] - xp[i];
+                if (or_lu_solve(d, Alast, e) != 0)
+                    for (int i = 0; i < d; ++i) e[i] = NAN;
+                for (int i = 0; i < d; ++i) {
+                    double ei = kap * e[i];
+                    gam[i] += ei * ei;
+                }
+            }
+            for (int r = 3; r > 0; --r) memcpy(H[r], H[r - 1], sizeof(double) * d);
+            memcpy(H[0], x, sizeof(double) * d);
+            if (nh < 4) nh++;
+            continue;
+        }
+
+        /* Newton, from x_0 at step 1 and from the predictor afterwards */
+        memcpy(x, avail == 0 ? H[0] : xp, sizeof(double) * d);
         int conv = 0;
         for (int it = 0; it < kmax; ++it) {
             double f[OR_DMAX], J[OR_DMAX * OR_DMAX], A[OR_DMAX * OR_DMAX], rhs[OR_DMAX];
@@ -513,7 +647,7 @@ int or_psi_am(int model, int d, int p, const double* mc, const double* rates_fix
     return OR_OK;
 }
 
-/* Psi of either family: lmm 0 BDF, 1 Adams-Moulton */
+/* Psi of either family: lmm 0 BDF, 1 Adams-Moulton, 2 BDF with the SDIRK start-up */
 int or_psi_lmm(int lmm, int model, int d, int p, const double* mc, const double* rates_fixed,
                const double* x0, const double* theta, double h, int M, int k,
                int want_lte, double rtol, int kmax, const double* floor_,
@@ -523,6 +657,9 @@ int or_psi_lmm(int lmm, int model, int d, int p, const double* mc, const double*
     if (lmm == 1)
         return or_psi_am(model, d, p, mc, rates_fixed, x0, theta, h, M, k, want_lte, rtol, kmax, floor_,
                          hist, q_hist, x_out, gamma_out, st);
+    if (lmm == 2)
+        return or_psi_bdf(model, d, p, mc, rates_fixed, x0, theta, h, M, k, want_lte, rtol, kmax, floor_,
+                          hist, q_hist, 1, x_out, gamma_out, st);
     return or_psi(model, d, p, mc, rates_fixed, x0, theta, h, M, k, want_lte, rtol, kmax, floor_,
                   hist, q_hist, x_out, gamma_out, st);
 }
@@ -733,7 +870,7 @@ typedef struct {
     double x0[OR_DMAX];
     double prior_mean[OR_PMAX], prior_sd[OR_PMAX];
     int resampling;             /* 0 systematic (integer CDF), 1 multinomial */
-    int lmm;                    /* 0 BDF, 1 Adams-Moulton */
+    int lmm;                    /* 0 BDF, 1 Adams-Moulton, 2 BDF with SDIRK start-up */
 } or_config;
 
 typedef struct {
