@@ -55,8 +55,16 @@ typedef enum {
 /* Implicit LMM family of the propagation (Sec. 2: AM or BDF).  The order
  * field is the BDF order k (k steps, order k), or for AM the number of steps
  * k of the Adams-Moulton formula (order k + 1; AM1 is the trapezoidal rule;
- * AM2 and AM3 are not A-stable, so stiff models need AM1 or small steps). */
-typedef enum { PF_LMM_BDF = 0, PF_LMM_AM = 1 } pf_lmm;
+ * AM2 and AM3 are not A-stable, so stiff models need AM1 or small steps).
+ *   BDF:       each interval restarts the history, so its first k-1 steps
+ *              use BDF1 .. BDF(k-1) (the interval is then first order).
+ *   BDF_SDIRK: the first k-1 steps of each interval instead take one step
+ *              each of an L-stable, stiffly accurate SDIRK method of order k
+ *              (k stages; Alexander's order-2 and order-3 methods), then
+ *              BDFk; the interval keeps order k.  The Sec. 2.2 estimate at
+ *              those steps is the ramp's (same comparison value and
+ *              constant).  With order 1 it is plain BDF1. */
+typedef enum { PF_LMM_BDF = 0, PF_LMM_AM = 1, PF_LMM_BDF_SDIRK = 2 } pf_lmm;
 
 typedef enum {
     PF_PREC_FP64 = 0,      /* propagation (BDF + Newton + LU) in double */

@@ -258,7 +258,65 @@ __device__ inline BdfCoef bdf_coef(int q)
     return {-18.0 / 11.0, 9.0 / 11.0, -2.0 / 11.0, 6.0 / 11.0, 3.0 / 25.0};
 }
 
-template <class Model, class R, int KORD, bool LTE>
+// Start-up tables (SD): L-stable, stiffly accurate SDIRK of order KORD for the
+// first KORD-1 steps of each interval (Alexander 1977): order 2 with
+// gamma = 1 - 1/sqrt(2); order 3 with gamma the root of
+// gamma^3 - 3 gamma^2 + 3 gamma/2 - 1/6 in (1/6, 1/2).
+struct Sdirk {
+    double a[3][3];
+};
+template <int K>
+__device__ inline Sdirk sdirk_table()
+{
+    Sdirk t{};
+    if constexpr (K == 2) {
+        const double g = 0.29289321881345254;
+        t.a[0][0] = g;
+        t.a[1][0] = 1.0 - g;
+        t.a[1][1] = g;
+    } else {
+        const double g = 0.43586652150845967;
+        t.a[0][0] = g;
+        t.a[1][0] = (1.0 - g) / 2.0;
+        t.a[1][1] = g;
+        t.a[2][0] = -(6.0 * g * g - 16.0 * g + 1.0) / 4.0;
+        t.a[2][1] = (6.0 * g * g - 20.0 * g + 5.0) / 4.0;
+        t.a[2][2] = g;
+    }
+    return t;
+}
+
+// one Newton solve of y = psi + c f(y) from the guess in y (the same
+// iteration and stopping test as the BDF steps); the last factorisation is
+// left in lu
+template <class Model, class R>
+__device__ inline void newton(const Model& md, R (&y)[Model::D], const R (&psi)[Model::D], R c, R rtol,
+                              const R (&fl)[Model::D], int kmax, typename Model::LU& lu, uint32_t& iters,
+                              uint32_t& fails)
+{
+    constexpr int D = Model::D;
+    bool ok = false;
+    int it = 0;
+    do {
+        R f[D];
+        md.eval(y, c, f, lu);
+        R b[D];
+#pragma unroll
+        for (int i = 0; i < D; ++i) b[i] = (psi[i] + c * f[i]) - y[i];
+        md.solve(lu, b);
+        ok = true;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            y[i] += b[i];
+            ok &= rabs(b[i]) <= rtol * rmax(rabs(y[i]), fl[i]);
+        }
+        ++it;
+    } while (!ok && it < kmax);
+    iters += (uint32_t)it;
+    fails += ok ? 0u : 1u;
+}
+
+template <class Model, class R, int KORD, bool LTE, bool SD = false>
 __device__ inline void integrate(const Model& md, R x[Model::D], R gam[Model::D], double h_d,
                                  int M, R rtol, const R* __restrict__ floor_, int kmax,
                                  uint32_t& iters, uint32_t& fails)
@@ -295,6 +353,58 @@ __device__ inline void integrate(const Model& md, R x[Model::D], R gam[Model::D]
             xn[i] = p;
         }
         typename Model::LU lu;
+        if constexpr (SD && KORD >= 2) {
+            if (avail < KORD - 1) {
+                // start-up step: the SDIRK stages, x_m the last one
+                const Sdirk tb = sdirk_table<KORD>();
+                R y[D], F[KORD][D], ps[D];
+#pragma unroll
+                for (int i = 0; i < D; ++i) y[i] = x[i];
+#pragma unroll
+                for (int sg = 0; sg < KORD; ++sg) {
+#pragma unroll
+                    for (int i = 0; i < D; ++i) {
+                        R acc = R(0);
+#pragma unroll
+                        for (int j = 0; j < sg; ++j) acc += (R)tb.a[sg][j] * F[j][i];
+                        ps[i] = x[i] + h * acc;
+                    }
+                    newton(md, y, ps, h * (R)tb.a[sg][sg], rtol, fl, kmax, lu, iters, fails);
+                    md.rhs(y, F[sg]);
+                }
+                if constexpr (LTE) {
+                    // the ramp's estimator: comparison value as above (Euler
+                    // at m = 1), the ramp order's matrix at x_m
+                    if (avail == 0) {
+                        R f0[D];
+                        md.rhs(x, f0);
+#pragma unroll
+                        for (int i = 0; i < D; ++i) xp[i] = x[i] + h * f0[i];
+                    }
+                    R fm[D];
+                    md.eval(y, c, fm, lu);
+                    const R kap = avail == 0 ? R(0.5) : (R)co.kappa;
+                    R e[D];
+#pragma unroll
+                    for (int i = 0; i < D; ++i) e[i] = y[i] - xp[i];
+                    md.solve(lu, e);
+#pragma unroll
+                    for (int i = 0; i < D; ++i) {
+                        const R v = kap * e[i];
+                        gam[i] += v * v;
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < D; ++i) {
+                    if (KORD >= 3) h3[i] = h2[i];
+                    if (KORD >= 2) h2[i] = h1[i];
+                    h1[i] = x[i];
+                    x[i] = y[i];
+                }
+                avail = avail < KORD ? avail + 1 : KORD;
+                continue;
+            }
+        }
         // one exit (converged or kmax reached), so the loop is a plain
         // while-any-lane-active loop; the counts come from its exit state
         bool ok = false;
@@ -452,12 +562,13 @@ __device__ inline void integrate_am(const Model& md, R x[Model::D], R gam[Model:
     }
 }
 
-// Psi of either LMM family (LMM 0 BDF, 1 Adams-Moulton)
+// Psi of either LMM family (LMM 0 BDF, 1 Adams-Moulton, 2 BDF with the SDIRK start-up)
 template <class Model, class R, int KORD, bool LTE, int LMM>
 __device__ inline void integrate_lmm(const Model& md, R x[Model::D], R gam[Model::D], double h_d, int M, R rtol,
                                      const R* __restrict__ floor_, int kmax, uint32_t& iters, uint32_t& fails)
 {
     if constexpr (LMM == 1) integrate_am<Model, R, KORD, LTE>(md, x, gam, h_d, M, rtol, floor_, kmax, iters, fails);
+    else if constexpr (LMM == 2) integrate<Model, R, KORD, LTE, true>(md, x, gam, h_d, M, rtol, floor_, kmax, iters, fails);
     else integrate<Model, R, KORD, LTE>(md, x, gam, h_d, M, rtol, floor_, kmax, iters, fails);
 }
 

@@ -198,12 +198,16 @@ static StepKernel pick_update(int order)
 template <template <class> class Mdl, class R, bool INL>
 static StepKernel predict_of(int lmm, int order)
 {
-    return lmm == 1 ? pick_predict<Mdl, R, 1, INL>(order) : pick_predict<Mdl, R, 0, INL>(order);
+    if (lmm == 1) return pick_predict<Mdl, R, 1, INL>(order);
+    if (lmm == 2) return pick_predict<Mdl, R, 2, INL>(order);
+    return pick_predict<Mdl, R, 0, INL>(order);
 }
 template <template <class> class Mdl, class R, bool INL>
 static StepKernel update_of(int lmm, int order)
 {
-    return lmm == 1 ? pick_update<Mdl, R, 1, INL>(order) : pick_update<Mdl, R, 0, INL>(order);
+    if (lmm == 1) return pick_update<Mdl, R, 1, INL>(order);
+    if (lmm == 2) return pick_update<Mdl, R, 2, INL>(order);
+    return pick_update<Mdl, R, 0, INL>(order);
 }
 template <bool INL>
 static StepKernel predict_kernel(int model, int lmm, int prec, int order)
@@ -232,8 +236,15 @@ static InitKernel init_kernel(int model, int prec)
     return prec == PREC_FP32 ? k_init<Chain16<float>, float> : k_init<Chain16<double>, double>;
 }
 
-// kernel class: ((model - 1) * 2 + lmm) * 8 + precision * 4 + order
-static int class_of(const FilterDesc& d) { return ((d.model - 1) * 2 + d.lmm) * 8 + d.prec * 4 + d.order; }
+// kernel class: ((model - 1) * 3 + lmm) * 8 + precision * 4 + order
+static int class_of(const FilterDesc& d) { return ((d.model - 1) * 3 + d.lmm) * 8 + d.prec * 4 + d.order; }
+static void class_decode(int cls, int& model, int& lmm, int& prec, int& order)
+{
+    model = cls / 24 + 1;
+    lmm = (cls / 8) % 3;
+    prec = (cls % 8) / 4;
+    order = cls % 4;
+}
 
 // ---------------------------------------------------------------------------
 // configuration checks
@@ -257,7 +268,8 @@ static pf_status check_config(const pf_config* c)
     if (c->n_particles < 1 || c->n_particles > (1ull << 24)) return fail(PF_EINVAL, "n_particles must be 1..2^24");
     if (!c->x0 || !c->prior_mean || !c->prior_sd || !c->state_floor) return fail(PF_EINVAL, "NULL array in config");
     if (!(c->shrink_a > 0.0 && c->shrink_a < 1.0)) return fail(PF_EINVAL, "shrink_a must be in (0,1)");
-    if (c->lmm != PF_LMM_BDF && c->lmm != PF_LMM_AM) return fail(PF_EINVAL, "lmm must be BDF or AM");
+    if (c->lmm != PF_LMM_BDF && c->lmm != PF_LMM_AM && c->lmm != PF_LMM_BDF_SDIRK)
+        return fail(PF_EINVAL, "lmm must be BDF, AM or BDF_SDIRK");
     if (c->order < 1 || c->order > 3) return fail(PF_EINVAL, "order must be 1..3");
     if (c->substeps < 1 || c->substeps > SUBSTEPS_MAX) return fail(PF_EINVAL, "substeps must be 1..65536");
     if (c->newton_max_iter < 1 || c->newton_max_iter > KMAX_MAX) return fail(PF_EINVAL, "newton_max_iter must be 1..64");
@@ -284,7 +296,8 @@ static void fill_static(FilterDesc& d, const pf_config* c)
     d.kmax = (int)c->newton_max_iter;
     d.prec = c->precision == PF_PREC_FP32_PROP ? PREC_FP32 : PREC_FP64;
     d.resampling = c->resampling == PF_RESAMPLE_MULTINOMIAL ? 1 : 0;
-    d.lmm = c->lmm == PF_LMM_AM ? 1 : 0;
+    // BDF1 has no start-up: it is the same propagation either way
+    d.lmm = c->lmm == PF_LMM_AM ? 1 : (c->lmm == PF_LMM_BDF_SDIRK && c->order >= 2 ? 2 : 0);
     for (uint32_t i = 0; i < c->m; ++i) d.obs[i] = (int)c->obs_index[i];
     d.n = (int)c->n_particles;
     d.ntiles = (d.n + TILE - 1) / TILE;
@@ -687,7 +700,8 @@ static pf_status submit(pf_context* ctx, uint32_t count, pf_filter* const* fs, c
         }
         if (timed && (e = hipEventRecord(sg.tev[0], ctx->stream)) != hipSuccess) return e;
         for (const Range& r : ranges) {
-            const int model = r.cls / 16 + 1, lmm = (r.cls / 8) % 2, prec = (r.cls % 8) / 4, order = r.cls % 4;
+            int model, lmm, prec, order;
+            class_decode(r.cls, model, lmm, prec, order);
             hipLaunchKernelGGL(inline_rec ? predict_kernel<true>(model, lmm, prec, order)
                                           : predict_kernel<false>(model, lmm, prec, order),
                                dim3(grid_for(ctx, r.cnt)), dim3(TILE), 0,
@@ -702,7 +716,8 @@ static pf_status submit(pf_context* ctx, uint32_t count, pf_filter* const* fs, c
                            ctx->d_state);
         if (timed && (e = hipEventRecord(sg.tev[2], ctx->stream)) != hipSuccess) return e;
         for (const Range& r : ranges) {
-            const int model = r.cls / 16 + 1, lmm = (r.cls / 8) % 2, prec = (r.cls % 8) / 4, order = r.cls % 4;
+            int model, lmm, prec, order;
+            class_decode(r.cls, model, lmm, prec, order);
             hipLaunchKernelGGL(inline_rec ? update_kernel<true>(model, lmm, prec, order)
                                           : update_kernel<false>(model, lmm, prec, order),
                                dim3(grid_for(ctx, r.cnt)), dim3(TILE), 0,
@@ -958,7 +973,9 @@ static PropKernel pick_prop_lmm(int order)
 template <template <class> class Mdl, class R, bool LTE>
 static PropKernel pick_prop(int lmm, int order)
 {
-    return lmm == 1 ? pick_prop_lmm<Mdl, R, LTE, 1>(order) : pick_prop_lmm<Mdl, R, LTE, 0>(order);
+    if (lmm == 1) return pick_prop_lmm<Mdl, R, LTE, 1>(order);
+    if (lmm == 2) return pick_prop_lmm<Mdl, R, LTE, 2>(order);
+    return pick_prop_lmm<Mdl, R, LTE, 0>(order);
 }
 
 extern "C" pf_status pf_test_propagate(const pf_config* cfg, uint64_t n, const double* x_in, const double* theta,

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libpf_hip.so")
 PF_OK, PF_EINVAL, PF_ENOMEM, PF_EADMIT, PF_EDEGENERATE = 0, 1, 2, 3, 4
 PF_ENONFINITE, PF_EDEVICE, PF_EBUSY, PF_EORDER = 5, 6, 7, 8
 PF_MODEL_ROBERTSON, PF_MODEL_CHAIN16 = 1, 2
-PF_LMM_BDF, PF_LMM_AM = 0, 1
+PF_LMM_BDF, PF_LMM_AM, PF_LMM_BDF_SDIRK = 0, 1, 2
 PF_PREC_FP64, PF_PREC_FP32_PROP = 0, 1
 PF_RESAMPLE_SYSTEMATIC, PF_RESAMPLE_MULTINOMIAL = 0, 1
 PF_TIME_STEP, PF_TIME_PREDICT, PF_TIME_RESAMPLE, PF_TIME_UPDATE, PF_TIME_MOMENTS = 0, 1, 2, 3, 4

@@ -66,7 +66,8 @@ def test_bad_configs_rejected_on_host():
     for mutate in (lambda c: setattr(c.c, "order", 4), lambda c: setattr(c.c, "shrink_a", 1.0),
                    lambda c: setattr(c.c, "n_particles", 0), lambda c: setattr(c.c, "d", 4),
                    lambda c: setattr(c.c, "struct_size", 8), lambda c: setattr(c.c, "m", 0),
-                   lambda c: setattr(c.c, "substeps", 65537), lambda c: setattr(c.c, "newton_max_iter", 65)):
+                   lambda c: setattr(c.c, "substeps", 65537), lambda c: setattr(c.c, "newton_max_iter", 65),
+                   lambda c: setattr(c.c, "lmm", 3), lambda c: setattr(c.c, "resampling", 2)):
         cfg = pf.Config(prob)
         mutate(cfg)
         assert L.pf_filter_bytes(cfg.ptr()) == 0
@@ -74,6 +75,10 @@ def test_bad_configs_rejected_on_host():
     cfg = pf.Config(prob)
     cfg.c.substeps, cfg.c.newton_max_iter = 65536, 64
     assert L.pf_filter_bytes(cfg.ptr()) > 0
+    for lmm in (pf.PF_LMM_BDF, pf.PF_LMM_AM, pf.PF_LMM_BDF_SDIRK):
+        cfg = pf.Config(prob)
+        cfg.c.lmm = lmm
+        assert L.pf_filter_bytes(cfg.ptr()) > 0
 
 
 def test_product_never_loads_the_oracle():

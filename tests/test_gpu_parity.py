@@ -168,6 +168,40 @@ def test_propagate_chain_am1(pf, oracle, prec):
             assert np.median(err) < 1e-5
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("lte", [False, True])
+@pytest.mark.parametrize("k", [2, 3])
+def test_propagate_robertson_sdirk(pf, oracle, prec, lte, k):
+    # BDFk with the SDIRK start-up (k stages per start-up step, then BDFk)
+    prob, sets = _robertson_inputs(oracle)
+    prob.lmm, prob.order = pf.PF_LMM_BDF_SDIRK, k
+    rtol = prob.newton_rtol_fp64 if prec == 0 else prob.newton_rtol_fp32
+    for x, th, h in sets:
+        xg, gg, itg = _propagate_gpu(pf, prob, prec, x, th, h, lte)
+        xo, go, ito = _propagate_oracle(oracle, prob, x, th, h, lte, rtol)
+        err = relerr(xg, xo, prob.state_floor)
+        assert err.max() < TOL[prec], (k, h, err.max())
+        if lte:
+            noise = 0.0 if prec == 0 else 4 * np.sqrt(prob.substeps) * 2.0**-23 * np.abs(xo)
+            dev_ = np.abs(np.sqrt(gg) - np.sqrt(go))
+            bound = (1e-7 if prec == 0 else 2e-3) * np.maximum(np.sqrt(go), prob.state_floor) + noise
+            assert np.all(dev_ <= bound), (k, h, (dev_ / bound).max())
+        if prec == 0:
+            assert abs(itg - ito) <= 0.01 * ito + 5
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_propagate_sdirk_order1_is_bdf1(pf, oracle, prec):
+    # with k = 1 there is no start-up: the result is plain BDF1's, bit for bit
+    prob, sets = _robertson_inputs(oracle, n=300, j_list=(10,))
+    prob.order = 1
+    x, th, h = sets[0]
+    xa, ga, ia = _propagate_gpu(pf, prob, prec, x, th, h, True)
+    prob.lmm = pf.PF_LMM_BDF_SDIRK
+    xb, gb, ib = _propagate_gpu(pf, prob, prec, x, th, h, True)
+    assert np.array_equal(xa, xb) and np.array_equal(ga, gb) and ia == ib
+
+
 def _chain_inputs(n=600, seed=3):
     prob = inputs.chain16(n, 10)
     rng = np.random.default_rng(seed)
@@ -378,6 +412,38 @@ def test_step_parity_robertson_am1(pf, ctx, oracle, prec):
     err = np.abs(x[same] - ora.x[same]) / scale[same]
     assert err.max() < TOL[prec], err.max()
     if prec == 0:
+        mean, cov = ora.moments()
+        assert np.allclose(post["mean"], mean, rtol=1e-10, atol=1e-12)
+        assert np.allclose(post["cov"], cov, rtol=1e-7, atol=1e-12)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_propagate_chain_sdirk(pf, oracle, prec):
+    prob, sets = _chain_inputs()
+    prob.lmm = pf.PF_LMM_BDF_SDIRK        # order 3: two SDIRK3 start-up steps
+    rtol = prob.newton_rtol_fp64 if prec == 0 else prob.newton_rtol_fp32
+    for x, th, h in sets:
+        xg, gg, _ = _propagate_gpu(pf, prob, prec, x, th, h, True)
+        xo, go, _ = _propagate_oracle(oracle, prob, x, th, h, True, rtol)
+        err = relerr(xg, xo, prob.state_floor)
+        assert err.max() < TOL[prec], (h, err.max())
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_step_parity_robertson_sdirk(pf, ctx, oracle, prec):
+    prob = inputs.robertson(1000, 50, seed=2)
+    prob.lmm, prob.order = pf.PF_LMM_BDF_SDIRK, 3
+    ora, out, anc_o, anc_g, x, th, lw, post, scale = _step_case(pf, ctx, oracle, prob, prec, 7)
+    same = anc_o == anc_g
+    if prec == 0:
+        assert same.all()
+    else:
+        assert same.mean() > 0.98
+    err = np.abs(x[same] - ora.x[same]) / scale[same]
+    assert err.max() < TOL[prec], err.max()
+    if prec == 0:
+        fin = np.isfinite(ora.logw)
+        assert np.allclose(lw[fin], ora.logw[fin], rtol=0, atol=1e-8)
         mean, cov = ora.moments()
         assert np.allclose(post["mean"], mean, rtol=1e-10, atol=1e-12)
         assert np.allclose(post["cov"], cov, rtol=1e-7, atol=1e-12)

@@ -72,6 +72,13 @@ def test_small_robertson_am1_within_3_mcse(pf, oracle):
     _check(pf, oracle, prob, (pf.PF_PREC_FP64, pf.PF_PREC_FP32_PROP), R=16, T=50)
 
 
+def test_small_robertson_bdf3_sdirk_within_3_mcse(pf, oracle):
+    """The small configuration with BDF3 and the order-preserving SDIRK start-up."""
+    prob = inputs.config_small()
+    prob.lmm, prob.order = pf.PF_LMM_BDF_SDIRK, 3
+    _check(pf, oracle, prob, (pf.PF_PREC_FP32_PROP,), R=16, T=50)
+
+
 def test_robertson_200_steps_within_3_mcse(pf, oracle):
     """The large Robertson schedule (200 observations) at N=8192, R=8."""
     prob = inputs.robertson(8192, 200, seed=0)

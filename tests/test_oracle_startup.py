@@ -89,3 +89,24 @@ def test_startup_filter_posterior_contracts(oracle):
     assert ess[0] >= 1.0 and np.all(ess[1:] > 10)
     assert np.all(sds[-1] < pr.prior_sd / 5)
     assert np.all(np.abs(means[-1] - pr.theta_true) < 4 * sds[-1] + 0.05)
+
+
+def test_startup_accuracy_on_robertson_interval(oracle):
+    # One observation interval of the large Robertson schedule at M = 20: the
+    # start-up makes BDF3 third order (error ratio ~8 under step halving
+    # instead of ~4) and far more accurate at the same M
+    prob = inputs.config_robertson_large()
+    j = 20
+    x0, H = prob.x_true[j - 1], prob.times[j] - prob.times[j - 1]
+    th = prob.prior_mean
+    kw = dict(lte=False, rtol=1e-13, kmax=20, floor=prob.state_floor)
+    ref, _, _ = oracle.psi(prob.model, x0, th, H / 4000, 4000, 3, lmm=2, **kw)
+
+    def err(lmm, M):
+        x, _, _ = oracle.psi(prob.model, x0, th, H / M, M, 3, lmm=lmm, **kw)
+        return np.max(np.abs(x - ref) / np.maximum(np.abs(ref), prob.state_floor))
+
+    e_bdf, e_sd = err(0, 20), err(2, 20)
+    assert e_sd < e_bdf / 20, (e_bdf, e_sd)
+    assert 6.5 < e_sd / err(2, 40) < 10.0
+    assert 3.0 < e_bdf / err(0, 40) < 5.0
