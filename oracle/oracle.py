@@ -18,8 +18,8 @@ LIB = os.path.join(HERE, "liboracle.so")
 
 OK, EINVAL, EDEGENERATE = 0, 1, 4
 PUR_PRIOR, PUR_RESAMPLE, PUR_PROLIF, PUR_INNOV = 1, 2, 3, 4
-MODEL_DECAY, MODEL_ROBERTSON, MODEL_CHAIN = 0, 1, 2
-DMAX, PMAX, MMAX = 16, 12, 4
+MODEL_DECAY, MODEL_ROBERTSON, MODEL_CHAIN, MODEL_ADVDIFF = 0, 1, 2, 3
+DMAX, PMAX, MMAX = 1521, 12, 32
 
 
 def build(force: bool = True) -> str:
@@ -158,6 +158,8 @@ def rhs(model, x, theta, mc=None, rates_fixed=None, d=None, p=None):
     theta = _f64(theta)
     d = len(x) if d is None else d
     p = len(theta) if p is None else p
+    if not 1 <= d <= DMAX:
+        raise ValueError(f"state dimension {d} outside 1..{DMAX}")
     mc = _f64(mc if mc is not None else np.zeros(1))
     rf = _f64(rates_fixed if rates_fixed is not None and len(rates_fixed) else np.zeros(1))
     f = np.zeros(d)
@@ -213,9 +215,11 @@ def psi(model, x0, theta, h, M, k, lte=False, rtol=1e-12, kmax=10, floor=None,
         hptr, nq = _dp(hh), hh.shape[0]
     else:
         hptr, nq = None, 0
-    lib().or_psi_lmm(int(lmm), model, d, p, _dp(mc), _dp(rf), _dp(x0), _dp(theta), float(h), int(M), int(k),
-                     1 if lte else 0, float(rtol), int(kmax), _dp(floor), hptr, nq, _dp(xo), _dp(go),
-                     C.byref(st))
+    rc = lib().or_psi_lmm(int(lmm), model, d, p, _dp(mc), _dp(rf), _dp(x0), _dp(theta), float(h), int(M),
+                          int(k), 1 if lte else 0, float(rtol), int(kmax), _dp(floor), hptr, nq, _dp(xo),
+                          _dp(go), C.byref(st))
+    if rc:
+        raise ValueError(f"oracle psi rejected its arguments (status {rc})")
     return xo, go, {"newton_iters": st.newton_iters, "newton_fails": st.newton_fails,
                     "lu_fails": st.lu_fails}
 

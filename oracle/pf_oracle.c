@@ -13,6 +13,10 @@
  * (x[n*d + i], theta[n*p + i]) because that is the plainest layout; loops over
  * particles carry an OpenMP pragma and nothing else.
  *
+ * Models: Robertson kinetics and the compartment chain (stiffness that
+ * depends on the parameters), and the 2D periodic advection-diffusion system
+ * of Sec. 4 (uniform stiffness, up to 39 x 39 grid values per particle).
+ *
  * Readings of points the paper leaves open are marked "Reading:" where they
  * are used.  Parity status of each function is in its comment; the one piece
  * with no pin beyond internal consistency is the innovation-variance reading
@@ -27,9 +31,12 @@
 #include <omp.h>
 #endif
 
-#define OR_DMAX 16
+/* largest sizes: states (the 39 x 39 advection-diffusion grid), parameters,
+ * observed components.  Vectors of these sizes live on the stack; d x d
+ * matrices are allocated per call. */
+#define OR_DMAX 1521
 #define OR_PMAX 12
-#define OR_MMAX 4
+#define OR_MMAX 32
 
 /* status codes (plain ints; mirrored by the Python wrapper) */
 #define OR_OK 0
@@ -144,7 +151,7 @@ static void or_extrap_weights(int q, double w[4])
 /* Models: right-hand side f(x; k) and Jacobian J = df/dx (row-major d x d).  */
 /* `k` is the full vector of rate constants; `mc` the fixed model constants. */
 /* ------------------------------------------------------------------------- */
-enum { MODEL_DECAY = 0, MODEL_ROBERTSON = 1, MODEL_CHAIN = 2 };
+enum { MODEL_DECAY = 0, MODEL_ROBERTSON = 1, MODEL_CHAIN = 2, MODEL_ADVDIFF = 3 };
 
 /* x_i' = -k_i x_i (test problem with a closed form; d = p) */
 static void rhs_decay(int d, const double* x, const double* k, double* f, double* J)
@@ -193,9 +200,70 @@ static void rhs_chain(int d, const double* x, const double* k, const double* mc,
     }
 }
 
+/* 2D periodic advection-diffusion (Sec. 4), semi-discretised as dU/dt = L U:
+ *   L = -(k1^2 B1^T B1 + k1 k3 (B1^T B2 + B2^T B1) + (k2^2 + k3^2) B2^T B2)
+ *       + c1 B1 + c2 B2,
+ * B1 = I (x) l, B2 = l (x) I, with l the nt x nt periodic difference matrix
+ * of Sec. 4 (1 on the diagonal, -1 below it and in the top-right corner):
+ * (l v)_i = v_i - v_{i-1 mod nt}, (l^T v)_i = v_i - v_{i+1 mod nt}.
+ * Reading (stacking): U[iy * nt + ix], x fastest, so that the Kronecker
+ * factor I (x) l acts along x as B1 stands for d/dx.  Reading (scale): l as
+ * printed, without a 1/dx factor (coefficients in grid units).
+ * theta = (k1, k2, k3, c1, c2) is used as is (the paper estimates these
+ * parameters, not their logarithms); mc[0] = nt, d = nt^2.
+ * f = L x through the factors; J = L, assembled column by column as L e_j. */
+static void diff_x(int nt, const double* v, double* o, int transposed)
+{
+    for (int iy = 0; iy < nt; ++iy)
+        for (int ix = 0; ix < nt; ++ix) {
+            int nb = transposed ? (ix + 1) % nt : (ix + nt - 1) % nt;
+            o[iy * nt + ix] = v[iy * nt + ix] - v[iy * nt + nb];
+        }
+}
+
+static void diff_y(int nt, const double* v, double* o, int transposed)
+{
+    for (int iy = 0; iy < nt; ++iy) {
+        int nb = transposed ? (iy + 1) % nt : (iy + nt - 1) % nt;
+        for (int ix = 0; ix < nt; ++ix) o[iy * nt + ix] = v[iy * nt + ix] - v[nb * nt + ix];
+    }
+}
+
+static void advdiff_apply(int nt, const double* th, const double* v, double* o)
+{
+    int d = nt * nt;
+    double b1[OR_DMAX], b2[OR_DMAX], t11[OR_DMAX], t12[OR_DMAX], t21[OR_DMAX], t22[OR_DMAX];
+    double k1 = th[0], k2 = th[1], k3 = th[2], c1 = th[3], c2 = th[4];
+    diff_x(nt, v, b1, 0);       /* B1 v */
+    diff_y(nt, v, b2, 0);       /* B2 v */
+    diff_x(nt, b1, t11, 1);     /* B1^T B1 v */
+    diff_x(nt, b2, t12, 1);     /* B1^T B2 v */
+    diff_y(nt, b1, t21, 1);     /* B2^T B1 v */
+    diff_y(nt, b2, t22, 1);     /* B2^T B2 v */
+    for (int i = 0; i < d; ++i)
+        o[i] = -(k1 * k1 * t11[i] + k1 * k3 * (t12[i] + t21[i]) + (k2 * k2 + k3 * k3) * t22[i])
+               + c1 * b1[i] + c2 * b2[i];
+}
+
+static void rhs_advdiff(int d, const double* x, const double* theta, const double* mc, double* f, double* J)
+{
+    int nt = (int)mc[0];
+    advdiff_apply(nt, theta, x, f);
+    if (J) {
+        double e[OR_DMAX], col[OR_DMAX];
+        for (int i = 0; i < d; ++i) e[i] = 0.0;
+        for (int j = 0; j < d; ++j) {
+            e[j] = 1.0;
+            advdiff_apply(nt, theta, e, col);
+            e[j] = 0.0;
+            for (int i = 0; i < d; ++i) J[i * d + j] = col[i];
+        }
+    }
+}
+
 /*
- * Model description.  Rate constants: the first p are exp(theta); the rest
- * (chain only) are fixed and come from `rates_fixed`.
+ * Model description.  Rate constants of the kinetic models: the first p are
+ * exp(theta); the rest (chain only) are fixed and come from `rates_fixed`.
  */
 typedef struct {
     int model;          /* MODEL_* */
@@ -208,6 +276,10 @@ typedef struct {
 void or_rhs(int model, int d, int p, const double* mc, const double* rates_fixed,
             const double* x, const double* theta, double* f, double* J)
 {
+    if (model == MODEL_ADVDIFF) {
+        rhs_advdiff(d, x, theta, mc, f, J);
+        return;
+    }
     double k[OR_DMAX];
     int nk = (model == MODEL_ROBERTSON) ? 3 : d;
     for (int i = 0; i < nk; ++i) k[i] = (i < p) ? exp(theta[i]) : rates_fixed[i];
@@ -272,7 +344,12 @@ int or_lu_solve(int d, double* A, double* b)
 /*   e_m = |C_{q+1}| / (C* + |C_{q+1}|) * (I - h beta J)^{-1} (x_m - x_m^(0)), */
 /* with x^(0) the degree-q extrapolation (error constant C* = 1) or, at step  */
 /* 1, the Euler value x_0 + h f(x_0) (C* = 1/2); J is the Jacobian of the     */
-/* last Newton iteration.  Steps add as independent variances:                */
+/* last Newton iteration.  At step 1 the filter is applied twice: the Euler   */
+/* value's own error in a stiff mode is (1 - h lambda) times larger than a    */
+/* stable predictor's, so a single filter leaves an estimate of half the      */
+/* mode's amplitude, while two bring it to the order of the true local error  */
+/* (1 / |h lambda| of the amplitude) and still tend to Milne's estimate as    */
+/* h -> 0.  Steps add as independent variances:                               */
 /*   Gamma = diag(sum_m e_m^2).                                               */
 /*                                                                            */
 /* `hist` (optional, pins only): q_hist earlier values x_{-1},...,x_{-q_hist} */
@@ -333,11 +410,12 @@ int or_sdirk(int k, double A[3][3], int* stages)
  * matrix of the last iteration is left in Alast */
 static int newton_solve(int model, int d, int p, const double* mc, const double* rates_fixed,
                         const double* theta, const double* psi, double c, double rtol, int kmax,
-                        const double* floor_, double* x, double* Alast, or_psi_stats* st)
+                        const double* floor_, double* x, double* Alast, double* J, double* A,
+                        or_psi_stats* st)
 {
     int conv = 0;
     for (int it = 0; it < kmax; ++it) {
-        double f[OR_DMAX], J[OR_DMAX * OR_DMAX], A[OR_DMAX * OR_DMAX], rhs[OR_DMAX];
+        double f[OR_DMAX], rhs[OR_DMAX];
         or_rhs(model, d, p, mc, rates_fixed, x, theta, f, J);
         for (int i = 0; i < d; ++i) rhs[i] = -(x[i] - psi[i] - c * f[i]);
         for (int a = 0; a < d; ++a)
@@ -375,6 +453,7 @@ int or_psi(int model, int d, int p, const double* mc, const double* rates_fixed,
            const double* hist, int q_hist,
            double* x_out, double* gamma_out, or_psi_stats* st)
 {
+    if (d < 1 || d > OR_DMAX) return OR_EINVAL;
     return or_psi_bdf(model, d, p, mc, rates_fixed, x0, theta, h, M, k, want_lte, rtol, kmax, floor_, hist,
                       q_hist, 0, x_out, gamma_out, st);
 }
@@ -395,6 +474,11 @@ static int or_psi_bdf(int model, int d, int p, const double* mc, const double* r
     }
     double gam[OR_DMAX];
     for (int i = 0; i < d; ++i) gam[i] = 0.0;
+    /* d x d work matrices: the last Newton matrix, J, A */
+    double* Alast = (double*)malloc(sizeof(double) * 3 * (size_t)d * d);
+    if (!Alast) return OR_EINVAL;
+    double* J = Alast + (size_t)d * d;
+    double* A = J + (size_t)d * d;
 
     for (int m = 1; m <= M; ++m) {
         int avail = nh - 1;               /* past values beyond x_{m-1} */
@@ -429,7 +513,7 @@ static int or_psi_bdf(int model, int d, int p, const double* mc, const double* r
             psi[i] = s;
         }
 
-        double x[OR_DMAX], Alast[OR_DMAX * OR_DMAX];
+        double x[OR_DMAX];
         double c = h * beta;
         if (sdirk_start && k >= 2 && avail < k - 1) {
             /* start-up step by SDIRK of order k (x_m = last stage) */
@@ -445,19 +529,20 @@ static int or_psi_bdf(int model, int d, int p, const double* mc, const double* r
                     ps[i] = H[0][i] + h * sacc;
                 }
                 newton_solve(model, d, p, mc, rates_fixed, theta, ps, h * Asd[sg][sg], rtol, kmax, floor_, x,
-                             NULL, st);
+                             NULL, J, A, st);
                 or_rhs(model, d, p, mc, rates_fixed, x, theta, F[sg], NULL);
             }
             if (want_lte) {
                 /* the ramp's estimator, with the ramp order's matrix at x_m */
-                double f[OR_DMAX], J[OR_DMAX * OR_DMAX];
+                double f[OR_DMAX];
                 or_rhs(model, d, p, mc, rates_fixed, x, theta, f, J);
                 for (int a = 0; a < d; ++a)
                     for (int b = 0; b < d; ++b) Alast[a * d + b] = (a == b ? 1.0 : 0.0) - c * J[a * d + b];
                 double kap = fabs(errc) / (cstar + fabs(errc));
                 double e[OR_DMAX];
                 for (int i = 0; i < d; ++i) e[i] = x[i] - xp[i];
-                if (or_lu_solve(d, Alast, e) != 0)
+                if (avail == 0) memcpy(A, Alast, sizeof(double) * d * d);
+                if (or_lu_solve(d, Alast, e) != 0 || (avail == 0 && or_lu_solve(d, A, e) != 0))
                     for (int i = 0; i < d; ++i) e[i] = NAN;
                 for (int i = 0; i < d; ++i) {
                     double ei = kap * e[i];
@@ -474,7 +559,7 @@ static int or_psi_bdf(int model, int d, int p, const double* mc, const double* r
         memcpy(x, avail == 0 ? H[0] : xp, sizeof(double) * d);
         int conv = 0;
         for (int it = 0; it < kmax; ++it) {
-            double f[OR_DMAX], J[OR_DMAX * OR_DMAX], A[OR_DMAX * OR_DMAX], rhs[OR_DMAX];
+            double f[OR_DMAX], rhs[OR_DMAX];
             or_rhs(model, d, p, mc, rates_fixed, x, theta, f, J);
             for (int i = 0; i < d; ++i) rhs[i] = -(x[i] - psi[i] - c * f[i]);
             for (int r = 0; r < d; ++r)
@@ -502,7 +587,9 @@ static int or_psi_bdf(int model, int d, int p, const double* mc, const double* r
             double kap = fabs(errc) / (cstar + fabs(errc));
             double e[OR_DMAX];
             for (int i = 0; i < d; ++i) e[i] = x[i] - xp[i];
-            if (or_lu_solve(d, Alast, e) != 0)
+            /* step 1: the Euler comparison is filtered twice */
+            if (avail == 0) memcpy(A, Alast, sizeof(double) * d * d);
+            if (or_lu_solve(d, Alast, e) != 0 || (avail == 0 && or_lu_solve(d, A, e) != 0))
                 for (int i = 0; i < d; ++i) e[i] = NAN;
             for (int i = 0; i < d; ++i) {
                 double ei = kap * e[i];
@@ -515,6 +602,7 @@ static int or_psi_bdf(int model, int d, int p, const double* mc, const double* r
         memcpy(H[0], x, sizeof(double) * d);
         if (nh < 4) nh++;
     }
+    free(Alast);
     memcpy(x_out, H[0], sizeof(double) * d);
     if (gamma_out) memcpy(gamma_out, gam, sizeof(double) * d);
     return OR_OK;
@@ -538,7 +626,8 @@ static int or_psi_bdf(int model, int d, int p, const double* mc, const double* r
 /* explicit derivative-based predictor is unstable for the stiff components   */
 /* when h |lambda| >> 1): x^(0) the degree-r extrapolation through            */
 /* x_{m-1} .. x_{m-1-r}, r = min(q + 1, m - 1, 3) (error constant 1), or at   */
-/* step 1 the Euler value x_0 + h f_0 (error constant 1/2);                   */
+/* step 1 the Euler value x_0 + h f_0 (error constant 1/2), filtered twice   */
+/* as for BDF;                                                                */
 /*   e_m = |C| / (C* + |C|) (I - h beta_0 J)^{-1} (x_m - x^(0)),              */
 /*   Gamma = diag(sum_m e_m^2).                                               */
 /* `hist` (pins only): earlier values x_{-1}, ... on the same grid; their     */
@@ -551,6 +640,7 @@ int or_psi_am(int model, int d, int p, const double* mc, const double* rates_fix
               double* x_out, double* gamma_out, or_psi_stats* st)
 {
     /* H[0] = x_{m-1}, H[1] = x_{m-2}, ...; F[r] = f(H[r]) */
+    if (d < 1 || d > OR_DMAX) return OR_EINVAL;
     double H[5][OR_DMAX], F[4][OR_DMAX];
     int nh = 1;
     memcpy(H[0], x0, sizeof(double) * d);
@@ -561,6 +651,11 @@ int or_psi_am(int model, int d, int p, const double* mc, const double* rates_fix
     for (int r = 0; r < nh && r < 4; ++r) or_rhs(model, d, p, mc, rates_fixed, H[r], theta, F[r], NULL);
     double gam[OR_DMAX];
     for (int i = 0; i < d; ++i) gam[i] = 0.0;
+    /* d x d work matrices: the last Newton matrix, J, A */
+    double* Alast = (double*)malloc(sizeof(double) * 3 * (size_t)d * d);
+    if (!Alast) return OR_EINVAL;
+    double* J = Alast + (size_t)d * d;
+    double* A = J + (size_t)d * d;
 
     for (int m = 1; m <= M; ++m) {
         int nf = nh < 4 ? nh : 4;             /* derivatives available: f_{m-1} .. */
@@ -594,12 +689,12 @@ int or_psi_am(int model, int d, int p, const double* mc, const double* rates_fix
             psi[i] = H[0][i] + h * s;
         }
 
-        double x[OR_DMAX], Alast[OR_DMAX * OR_DMAX];
+        double x[OR_DMAX];
         memcpy(x, r == 0 ? H[0] : xp, sizeof(double) * d);
         double c = h * beta[0];
         int conv = 0;
         for (int it = 0; it < kmax; ++it) {
-            double f[OR_DMAX], J[OR_DMAX * OR_DMAX], A[OR_DMAX * OR_DMAX], rhs[OR_DMAX];
+            double f[OR_DMAX], rhs[OR_DMAX];
             or_rhs(model, d, p, mc, rates_fixed, x, theta, f, J);
             for (int i = 0; i < d; ++i) rhs[i] = -(x[i] - psi[i] - c * f[i]);
             for (int a = 0; a < d; ++a)
@@ -627,7 +722,9 @@ int or_psi_am(int model, int d, int p, const double* mc, const double* rates_fix
             double kap = errc / (cstar + errc);
             double e[OR_DMAX];
             for (int i = 0; i < d; ++i) e[i] = x[i] - xp[i];
-            if (or_lu_solve(d, Alast, e) != 0)
+            /* step 1: the Euler comparison is filtered twice */
+            if (r == 0) memcpy(A, Alast, sizeof(double) * d * d);
+            if (or_lu_solve(d, Alast, e) != 0 || (r == 0 && or_lu_solve(d, A, e) != 0))
                 for (int i = 0; i < d; ++i) e[i] = NAN;
             for (int i = 0; i < d; ++i) {
                 double ei = kap * e[i];
@@ -642,6 +739,7 @@ int or_psi_am(int model, int d, int p, const double* mc, const double* rates_fix
         or_rhs(model, d, p, mc, rates_fixed, x, theta, F[0], NULL);
         if (nh < 5) nh++;
     }
+    free(Alast);
     memcpy(x_out, H[0], sizeof(double) * d);
     if (gamma_out) memcpy(gamma_out, gam, sizeof(double) * d);
     return OR_OK;
@@ -654,6 +752,7 @@ int or_psi_lmm(int lmm, int model, int d, int p, const double* mc, const double*
                const double* hist, int q_hist,
                double* x_out, double* gamma_out, or_psi_stats* st)
 {
+    if (d < 1 || d > OR_DMAX) return OR_EINVAL;
     if (lmm == 1)
         return or_psi_am(model, d, p, mc, rates_fixed, x0, theta, h, M, k, want_lte, rtol, kmax, floor_,
                          hist, q_hist, x_out, gamma_out, st);

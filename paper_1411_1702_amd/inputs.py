@@ -10,10 +10,16 @@ Michaelis-Menten system of Sec. 2.1 prints no constants), so the workloads are:
 
 * Robertson stiff kinetics, 3 states, log-rates estimated;
 * a 16-compartment chain with Michaelis-Menten losses, 12 log-rates estimated;
-* mixes of the two for many independent filters (batched and served forms).
+* the 2D periodic advection-diffusion problem of Sec. 4 (six-plume initial
+  field of Table 3, fixed parameters K and c of Sec. 4, 20 fixed observation
+  sites), 5 parameters estimated;
+* mixes of the first two for many independent filters (batched and served
+  forms).
 
-True trajectories come from scipy's Radau integrator at tight tolerance; the
-model right-hand sides below exist only for that purpose.  Observation noise,
+True trajectories come from scipy's Radau integrator at tight tolerance (the
+kinetic models) or from the exact matrix exponential of the discretised
+operator (advection-diffusion); the model right-hand sides below exist only
+for that purpose.  Observation noise,
 chain constants and the mixes are drawn from numpy's Philox4x64-10 streams
 keyed by (seed, purpose).
 """
@@ -26,6 +32,7 @@ import numpy as np
 
 MODEL_ROBERTSON = 1
 MODEL_CHAIN = 2
+MODEL_ADVDIFF = 3
 
 # RNG purposes (second key word of the input streams)
 PURPOSE_DATA = 5
@@ -52,10 +59,10 @@ class Problem:
     p: int
     m: int
     obs_index: np.ndarray        # (m,) observed state components
-    model_consts: np.ndarray     # chain: [V(d), K(d)]; Robertson: empty
+    model_consts: np.ndarray     # chain: [V(d), K(d)]; advection-diffusion: [grid side]; Robertson: empty
     rates_fixed: np.ndarray      # chain: all d rates (first p are estimated); Robertson: empty
     x0: np.ndarray               # (d,)
-    prior_mean: np.ndarray       # (p,) Gaussian prior on log-parameters
+    prior_mean: np.ndarray       # (p,) Gaussian prior on the parameters (log-rates for the kinetic models)
     prior_sd: np.ndarray         # (p,)
     theta_true: np.ndarray       # (p,)
     t0: float
@@ -73,7 +80,7 @@ class Problem:
     newton_rtol_fp32: float = 2e-6
     state_floor: np.ndarray = None   # (d,) scale floors (Newton test, parity)
     resampling: int = 0              # step 3(b): 0 systematic, 1 multinomial
-    lmm: int = 0                     # 0 BDF (order k), 1 Adams-Moulton (k steps)
+    lmm: int = 0                     # 0 BDF (order k), 1 Adams-Moulton (k steps), 2 BDF + SDIRK start-up
 
     @property
     def T(self) -> int:
@@ -205,6 +212,81 @@ def chain16(n_particles: int = 65536, T: int = 100, seed: int = 0, model_seed: i
         state_floor=1e-6 * scale)
 
 
+# --------------------------------------------------------------------------
+# 2D periodic advection-diffusion (Sec. 4)
+# --------------------------------------------------------------------------
+# Table 3: plume standard deviations and centres
+PLUME_GAMMA = (0.04, 0.08, 0.07, 0.10, 0.05, 0.06)
+PLUME_XC = (0.20, 0.30, 0.40, 0.50, 0.50, 0.70)
+PLUME_YC = (0.80, 0.40, 0.40, 0.50, 0.60, 0.50)
+# the fixed parameters that generate the data: K = [[k1, k3], [0, k2]] =
+# [[9, 6], [0, 4]], c = (2.5, -1.5); theta = (k1, k2, k3, c1, c2)
+ADVDIFF_THETA = (9.0, 4.0, 6.0, 2.5, -1.5)
+ADVDIFF_P = 5
+
+
+def advdiff_initial(n: int) -> np.ndarray:
+    """Six Gaussian plumes on the periodic (n-1) x (n-1) grid of [0, 1)^2,
+    x_i = i / (n - 1), stacked with x fastest: u[iy * (n-1) + ix]."""
+    nt = n - 1
+    g = np.arange(nt) / nt
+    X, Y = np.meshgrid(g, g)            # X[iy, ix] = x_ix, Y[iy, ix] = y_iy
+    u = np.zeros((nt, nt))
+    for gam, xc, yc in zip(PLUME_GAMMA, PLUME_XC, PLUME_YC):
+        u += np.exp(-((X - xc) ** 2 + (Y - yc) ** 2) / (2 * gam * gam)) / (gam * np.sqrt(2 * np.pi))
+    return u.reshape(-1)
+
+
+def _advdiff_operator(nt: int, theta):
+    """Sparse L(theta) of the semi-discrete system dU/dt = L U (Sec. 4), for
+    the truth only: B1 = I (x) l, B2 = l (x) I with the periodic backward
+    difference l."""
+    import scipy.sparse as sp
+    k1, k2, k3, c1, c2 = theta
+    ell = sp.eye(nt, format="csr") - sp.eye(nt, k=-1, format="csr") - sp.eye(nt, k=nt - 1, format="csr")
+    I = sp.eye(nt, format="csr")
+    B1 = sp.kron(I, ell, format="csr")
+    B2 = sp.kron(ell, I, format="csr")
+    return (-(k1 * k1 * (B1.T @ B1) + k1 * k3 * (B1.T @ B2 + B2.T @ B1) + (k2 * k2 + k3 * k3) * (B2.T @ B2))
+            + c1 * B1 + c2 * B2).tocsc()
+
+
+@functools.lru_cache(maxsize=16)
+def _advdiff_truth(n: int, T: int, dt: float):
+    from scipy.sparse.linalg import expm_multiply
+    nt = n - 1
+    L = _advdiff_operator(nt, ADVDIFF_THETA)
+    u0 = advdiff_initial(n)
+    times = dt * np.arange(1, T + 1)
+    x_true = expm_multiply(L, u0, start=dt, stop=dt * T, num=T, endpoint=True)
+    return times, np.asarray(x_true)
+
+
+def advdiff(n_particles: int = 5000, T: int = 30, seed: int = 0, n: int = 20, sites: int = 20,
+            substeps: int = 10, order: int = 2, prior_sd: float = 1.0) -> Problem:
+    """The advection-diffusion workload of Sec. 4 on an n x n grid ((n-1)^2
+    states): observe the field at `sites` fixed grid points drawn without
+    replacement, every time unit (T observations); noise sd = the largest
+    initial value at the sites / 50.  BDF2 with h = 0.1 (10 steps per unit).
+    theta = (k1, k2, k3, c1, c2) with a Gaussian prior N(truth, prior_sd^2 I)."""
+    nt = n - 1
+    d = nt * nt
+    times, x_true = _advdiff_truth(int(n), int(T), 1.0)
+    u0 = advdiff_initial(n)
+    obs = np.sort(_stream(seed, PURPOSE_MODEL).choice(d, size=min(sites, d), replace=False)).astype(np.int32)
+    sd = np.abs(u0[obs]).max() / 50.0
+    sigma = np.full((len(times), len(obs)), sd)
+    y = x_true[:, obs] + sigma * _stream(seed, PURPOSE_DATA).standard_normal(sigma.shape)
+    theta = np.array(ADVDIFF_THETA)
+    return Problem(
+        name=f"advdiff_n{n}_N{n_particles}_T{T}", model=MODEL_ADVDIFF, d=d, p=ADVDIFF_P, m=len(obs),
+        obs_index=obs, model_consts=np.array([float(nt)]), rates_fixed=np.zeros(0),
+        x0=u0, prior_mean=theta.copy(), prior_sd=np.full(ADVDIFF_P, prior_sd),
+        theta_true=theta, t0=0.0, times=times, x_true=x_true, y=y, sigma=sigma,
+        order=order, substeps=substeps, n_particles=int(n_particles), seed=int(seed),
+        state_floor=np.full(d, 1e-6 * np.abs(u0).max()))
+
+
 def decay_consts():
     return np.zeros(0)
 
@@ -225,6 +307,12 @@ def config_robertson_large() -> Problem:
 def config_chain() -> Problem:
     """16-state chain, N = 2^16, 100 observations, BDF3 with 40 steps."""
     return chain16(1 << 16, 100, seed=0)
+
+
+def config_advdiff(n: int = 20) -> Problem:
+    """Advection-diffusion of Sec. 4 on the n x n grid (n = 20: 361 states;
+    n = 40: 1521), N = 5000, 30 observations at 20 sites, BDF2 with h = 0.1."""
+    return advdiff(5000, 30, seed=0, n=n)
 
 
 # Constant sets of the chain used by the many-filter mixes.  A random draw of

@@ -119,14 +119,29 @@ def test_lte_estimate_start_step(oracle):
 def test_lte_filtered_for_stiff_components(oracle):
     # h*lambda = z >> 1.  Step 1 compares x1 = 1/(1+z) with the explicit Euler
     # value 1 - z: the distance z^2/(1+z), which the Newton matrix divides by
-    # (1 + z), so the estimate is (1/2) (z/(1+z))^2 ~ x0/2 instead of the raw
-    # z x0/2.  Later steps see damped history and add (almost) nothing.
+    # (1 + z) twice at this step, so the estimate is (1/2) z^2/(1+z)^3 ~
+    # x0/(2z), of the order of the true local error 1/(1+z) - e^-z ~ x0/z
+    # (one division would leave (1/2)(z/(1+z))^2 ~ x0/2).
     lam, h = 1e6, 0.25
-    x, gam, _ = _decay(oracle, lam, 1.0, 4 * h, 4, 2, lte=True)
     z = h * lam
-    first = 0.5 * (z / (1 + z)) ** 2
-    assert np.sqrt(gam[0]) == pytest.approx(first, rel=1e-9)
+    x, gam, _ = _decay(oracle, lam, 1.0, h, 1, 2, lte=True)
+    assert np.sqrt(gam[0]) == pytest.approx(0.5 * z * z / (1 + z) ** 3, rel=1e-9)
+    # over four steps every step adds O(1/z): 1/(2z) at step 1, 1/(3z) at
+    # step 2 (q = 1), about 0.27/z at step 3 (q = 2), much less at step 4;
+    # in quadrature about 0.66/z
+    x, gam, _ = _decay(oracle, lam, 1.0, 4 * h, 4, 2, lte=True)
+    assert 0.62 / z < np.sqrt(gam[0]) < 0.70 / z
     assert abs(x[0]) < 1e-10
+
+
+def test_lte_start_step_tracks_true_error_at_every_stiffness(oracle):
+    # one BDF1 step on x' = -lambda x from x0 = 1, z = h lambda from 1e-3 to
+    # 1e5: the estimate stays within a factor 3 of the true local error
+    # 1/(1+z) - e^-z (it tends to it as z -> 0 and to half of it as z -> inf)
+    for z in np.logspace(-3, 5, 33):
+        x, gam, _ = _decay(oracle, z, 1.0, 1.0, 1, 1, lte=True)
+        ratio = np.sqrt(gam[0]) / abs(1 / (1 + z) - np.exp(-z))
+        assert 0.33 < ratio < 1.01, (z, ratio)
 
 
 # ---------------------------------------------------------------- LU
