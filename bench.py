@@ -467,7 +467,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); independent filters shard "
-              "by whole filters across GPUs, see DESIGN.md", file=sys.stderr)
+              "by whole filters across GPUs", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_1411_1702_amd import pf

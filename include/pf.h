@@ -20,7 +20,9 @@
  *
  * Layout of the ensemble in device memory (HBM): structure of arrays, one
  * contiguous array per state component and per parameter, padded to a
- * multiple of 256 particles (padding particles carry zero weight).
+ * multiple of 256 particles (padding particles carry zero weight).  The
+ * advection-diffusion field is the exception: one contiguous [d] block per
+ * particle, since each particle is propagated by one workgroup.
  */
 #ifndef PF_H
 #define PF_H
@@ -49,7 +51,14 @@ typedef enum {
 
 typedef enum {
     PF_MODEL_ROBERTSON = 1, /* 3 states, 3 log-rates (A->B, 2B->B+C, B+C->A+C) */
-    PF_MODEL_CHAIN16 = 2    /* 16 compartments, first 12 log-rates estimated */
+    PF_MODEL_CHAIN16 = 2,   /* 16 compartments, first 12 log-rates estimated */
+    PF_MODEL_ADVDIFF = 3    /* Sec. 4: 2D periodic advection-diffusion on an nt x nt grid
+                             * (d = nt^2, 3 <= nt <= 39), dU/dt = L U with
+                             * L = -(k1^2 B1'B1 + k1 k3 (B1'B2 + B2'B1) + (k2^2 + k3^2) B2'B2)
+                             *     + c1 B1 + c2 B2, B1 = I (x) l, B2 = l (x) I, l the periodic
+                             * difference matrix of Sec. 4, grid stacked x fastest
+                             * (u[iy * nt + ix]); 5 parameters (k1, k2, k3, c1, c2) used as
+                             * they are (not logarithms); BDF or BDF_SDIRK only */
 } pf_model;
 
 /* Implicit LMM family of the propagation (Sec. 2: AM or BDF).  The order
@@ -87,17 +96,19 @@ typedef enum { PF_RESAMPLE_SYSTEMATIC = 0, PF_RESAMPLE_MULTINOMIAL = 1 } pf_resa
 typedef struct {
     uint32_t struct_size;        /* sizeof(pf_config), for ABI versioning */
     pf_model model;
-    uint32_t d, p, m;            /* state dim, estimated log-params, observed components */
+    uint32_t d, p, m;            /* state dim, estimated params, observed components
+                                  * (m <= 4; advdiff: m <= 32) */
     const uint32_t* obs_index;   /* [m] observed state components (0-based) */
-    const double* model_consts;  /* chain: [V(16), K(16)]; Robertson: NULL */
-    uint32_t n_model_consts;     /* 32 for the chain, 0 for Robertson */
+    const double* model_consts;  /* chain: [V(16), K(16)]; advdiff: [nt]; Robertson: NULL */
+    uint32_t n_model_consts;     /* 32 for the chain, 1 for advdiff, 0 for Robertson */
     const double* rates_fixed;   /* chain: [16] rates; entries p..15 are the known ones */
     uint32_t n_rates_fixed;
     uint64_t n_particles;        /* N >= 1, at most 2^24 */
     uint64_t seed;               /* key of the counter-based RNG */
     double t0;                   /* time of x0 */
     const double* x0;            /* [d] initial state, the same for every particle */
-    const double* prior_mean;    /* [p] Gaussian prior of the log-parameters */
+    const double* prior_mean;    /* [p] Gaussian prior of the parameters (log-rates for the
+                                  * kinetic models) */
     const double* prior_sd;      /* [p] */
     double shrink_a;             /* Liu-West factor, 0 < a < 1; jitter s = sqrt(1 - a^2) */
     pf_lmm lmm;
@@ -155,8 +166,9 @@ pf_status pf_query(pf_filter* f, uint64_t ticket);
 /*
  * Batched form: one step for `count` distinct filters of one context, as a
  * single submission.  y and sigma are [count][4] (row i uses its filter's
- * first m entries).  Each filter's result is identical to assimilating it
- * alone.  tickets[count] (may be NULL) receive the per-filter tickets.
+ * first m entries; a filter with m > 4 is rejected with PF_EINVAL).  Each
+ * filter's result is identical to assimilating it alone.  tickets[count]
+ * (may be NULL) receive the per-filter tickets.
  */
 pf_status pf_assimilate_batch(pf_context* ctx, uint32_t count, pf_filter* const* filters,
                               const double* t_obs, const double* y, const double* sigma,
@@ -239,7 +251,8 @@ pf_status pf_server_create(pf_context* ctx, const pf_server_config* cfg, pf_serv
 
 /* Opens a stream with configuration cfg (copied).  It is admitted as soon as
  * the pool can hold it; observations submitted before that wait in its queue.
- * PF_ENOMEM if the ensemble could never fit the pool. */
+ * PF_ENOMEM if the ensemble could never fit the pool; PF_EINVAL for m > 4
+ * (served steps are batched submissions). */
 pf_status pf_server_open(pf_server* s, const pf_config* cfg, uint64_t* stream);
 
 /* Queues an observation (y, sigma: [m], copied) at t_obs for the stream;

@@ -29,11 +29,12 @@ pf_status pf_test_normals(uint64_t n, uint64_t seed, uint64_t step, uint64_t pur
 /*
  * The integrator Psi of Algorithm 1 steps 2 and 4: n particles over one
  * interval of cfg->substeps BDF steps of size h, in cfg->precision.
- * x_in [d][n], theta [p][n] (log-parameters), x_out [d][n]: device doubles
+ * x_in [d][n], theta [p][n] (parameters), x_out [d][n]: device doubles
  * (converted to float on entry and back on exit in FP32 mode).  With lte != 0
  * gamma [d][n] receives the innovation variance; iters (device uint64[1])
- * is incremented by the Newton iteration count.  Only the model, dimension,
- * integrator and Newton fields of cfg are used.
+ * is incremented by the Newton iteration count (advdiff: one linear solve per
+ * step, which is where Newton converges on a linear system).  Only the model,
+ * dimension, integrator and Newton fields of cfg are used.
  */
 pf_status pf_test_propagate(const pf_config* cfg, uint64_t n, const double* x_in,
                             const double* theta, double h, int lte, double* x_out,

@@ -9,12 +9,13 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpf_hip.so")
 SOURCES = ["pf_runtime.hip", "pf_server.cpp"]
-DEPS = ["pf_runtime.hip", "pf_kernels.hip", "pf_device.hpp", "pf_types.hpp", "pf_server.cpp"]
+DEPS = ["pf_runtime.hip", "pf_kernels.hip", "pf_advdiff.hip", "pf_device.hpp", "pf_types.hpp", "pf_server.cpp"]
 ARCH = os.environ.get("PF_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
-    # packed FP32 instructions stay disabled
+    # no packed FP32 instructions: some of their forms have given wrong
+    # results on this target without any error
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-result",
 ]

@@ -244,6 +244,9 @@ struct Chain16 {
 //   e_m = kappa_q (I - h beta_q J)^{-1} (x_m - x_m^(0)),
 // x^(0) being the extrapolation (kappa = |C|/(1+|C|)) or, at m = 1, the
 // Euler value x_0 + h f(x_0) (kappa = 1/2); J from the last Newton iteration.
+// At m = 1 the difference is solved with that matrix twice: the Euler value's
+// error in a stiff mode is (1 - h lambda) times a stable predictor's, and the
+// second solve brings the estimate to the order of the true local error.
 // ---------------------------------------------------------------------------
 struct BdfCoef {
     double a1, a2, a3;   // x_m + a1 x_{m-1} + a2 x_{m-2} + a3 x_{m-3} = h beta f_m
@@ -388,6 +391,7 @@ __device__ inline void integrate(const Model& md, R x[Model::D], R gam[Model::D]
 #pragma unroll
                     for (int i = 0; i < D; ++i) e[i] = y[i] - xp[i];
                     md.solve(lu, e);
+                    if (avail == 0) md.solve(lu, e);
 #pragma unroll
                     for (int i = 0; i < D; ++i) {
                         const R v = kap * e[i];
@@ -436,6 +440,7 @@ __device__ inline void integrate(const Model& md, R x[Model::D], R gam[Model::D]
 #pragma unroll
             for (int i = 0; i < D; ++i) e[i] = xn[i] - xp[i];
             md.solve(lu, e);
+            if (avail == 0) md.solve(lu, e);
 #pragma unroll
             for (int i = 0; i < D; ++i) {
                 const R v = kap * e[i];
@@ -462,8 +467,8 @@ __device__ inline void integrate(const Model& md, R x[Model::D], R gam[Model::D]
 // extrapolation afterwards, r = min(q + 1, m - 1, 3).  f_m is evaluated once
 // at the accepted x_m.  With LTE, gam accumulates the squared filtered Milne
 // estimates kappa (I - h b0 J)^{-1} (x_m - x^(0)), x^(0) the extrapolation
-// (error constant 1) or at m = 1 the Euler value (1/2),
-// kappa = |C| / (C* + |C|) with |C| the formula's error constant.
+// (error constant 1) or at m = 1 the Euler value (1/2, solved twice as for
+// BDF), kappa = |C| / (C* + |C|) with |C| the formula's error constant.
 // ---------------------------------------------------------------------------
 struct AmCoef {
     double b0, b1, b2, b3;
@@ -542,6 +547,7 @@ __device__ inline void integrate_am(const Model& md, R x[Model::D], R gam[Model:
 #pragma unroll
             for (int i = 0; i < D; ++i) e[i] = xn[i] - xp[i];
             md.solve(lu, e);
+            if (r == 0) md.solve(lu, e);
 #pragma unroll
             for (int i = 0; i < D; ++i) {
                 const R v = kap * e[i];
@@ -574,7 +580,8 @@ __device__ inline void integrate_lmm(const Model& md, R x[Model::D], R gam[Model
 
 // Gaussian log-likelihood of the observed components, constants dropped;
 // -inf for a non-finite observed state.  Loops are unrolled over the largest
-// sizes so every index into the lane's registers is static.
+// sizes (MOBS_KIN observed components) so every index into the lane's
+// registers is static.
 template <class R, int D>
 __device__ inline double loglik(const R (&x)[D], const int32_t* obs, const double (&y)[MMAX],
                                 const double (&sg)[MMAX], int m)
@@ -582,7 +589,7 @@ __device__ inline double loglik(const R (&x)[D], const int32_t* obs, const doubl
     double s = 0.0;
     bool finite = true;
 #pragma unroll
-    for (int i = 0; i < MMAX; ++i) {
+    for (int i = 0; i < MOBS_KIN; ++i) {
         if (i < m) {
             const int k = obs[i];
             R xv = x[0];

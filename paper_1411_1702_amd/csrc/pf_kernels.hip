@@ -1156,6 +1156,14 @@ __global__ __launch_bounds__(TILE) void k_update(Batch B, const FilterDesc* desc
     }
 }
 
+}  // namespace pf
+
+// the advection-diffusion model's kernels (they use the reductions, the tile
+// partials and the step checks above; the moment pass below uses theirs)
+#include "pf_advdiff.hip"
+
+namespace pf {
+
 // ---------------------------------------------------------------------------
 // step 6: one workgroup per batch entry -- mean, covariance, ESS, Cholesky,
 // commit, and the step's status by ticket (device ring and host-mapped ring)
@@ -1195,9 +1203,20 @@ __device__ __forceinline__ int32_t moment_step(const FilterDesc& fd, FilterState
     return moments_finish<P, D>(fd, tot, pre, st, true, rec.t_next);
 }
 
-// MDL: the model of every filter in the launch (MODEL_ROBERTSON or
-// MODEL_CHAIN16), or 0 when the batch mixes models (chosen per filter); a
-// single-model instance carries only that model's combine and tail.
+// advection-diffusion: the parameter moments as for the other models, then
+// (committed steps) the weighted state mean from the per-tile state sums
+__device__ __forceinline__ int32_t ad_moment_step(const FilterDesc& fd, FilterState& st, const StepRec& rec,
+                                                  double* sh, double* tot)
+{
+    const int32_t s = moment_step<AD_P, 0>(fd, st, rec, sh, tot);
+    if (s == ST_OK) ad_state_mean(fd, sh);
+    return s;
+}
+
+// MDL: the model of every filter in the launch (MODEL_ROBERTSON,
+// MODEL_CHAIN16 or MODEL_ADVDIFF), or 0 when the batch mixes models (chosen
+// per filter); a single-model instance carries only that model's combine and
+// tail.
 template <bool INL, int MDL>
 __global__ __launch_bounds__(TILE) void k_moments(Batch B, const FilterDesc* descs, FilterState* states,
                                                   int32_t* host_ring)
@@ -1217,8 +1236,13 @@ __global__ __launch_bounds__(TILE) void k_moments(Batch B, const FilterDesc* des
         int32_t status;
         if constexpr (MDL == MODEL_ROBERTSON) status = moment_step<RB::P, RB::D>(fd, st, rec, sh, tot);
         else if constexpr (MDL == MODEL_CHAIN16) status = moment_step<CH::P, CH::D>(fd, st, rec, sh, tot);
-        else status = fd.model == MODEL_ROBERTSON ? moment_step<RB::P, RB::D>(fd, st, rec, sh, tot)
-                                                  : moment_step<CH::P, CH::D>(fd, st, rec, sh, tot);
+        else if constexpr (MDL == MODEL_ADVDIFF) status = ad_moment_step(fd, st, rec, sh, tot);
+        else {
+            const int model = uniform(fd.model);
+            if (model == MODEL_ROBERTSON) status = moment_step<RB::P, RB::D>(fd, st, rec, sh, tot);
+            else if (model == MODEL_CHAIN16) status = moment_step<CH::P, CH::D>(fd, st, rec, sh, tot);
+            else status = ad_moment_step(fd, st, rec, sh, tot);
+        }
         if (threadIdx.x == 0) {
             st.status = status;
             st.ring[rec.seq % RING] = status;

@@ -233,7 +233,41 @@ static InitKernel init_kernel(int model, int prec)
 {
     if (model == MODEL_ROBERTSON)
         return prec == PREC_FP32 ? k_init<Robertson<float>, float> : k_init<Robertson<double>, double>;
+    if (model == MODEL_ADVDIFF) return prec == PREC_FP32 ? k_ad_init<float> : k_ad_init<double>;
     return prec == PREC_FP32 ? k_init<Chain16<float>, float> : k_init<Chain16<double>, double>;
+}
+static InitKernel init_moments_kernel(int model)
+{
+    if (model == MODEL_ROBERTSON) return k_init_moments<Robertson<double>>;
+    if (model == MODEL_ADVDIFF) return k_init_moments<AdTag>;
+    return k_init_moments<Chain16<double>>;
+}
+
+// advection-diffusion kernels of one filter: workgroup shape by grid side,
+// precision; LDS bytes of one particle
+typedef void (*AdStepKernel)(StepRec, int, const FilterDesc*, FilterState*);
+struct AdKernels {
+    AdStepKernel predict, part1, update, part2;
+    int wgs;
+    size_t lds;
+};
+static AdKernels ad_kernels(const FilterDesc& d)
+{
+    AdKernels k;
+    const bool f32 = d.prec == PREC_FP32, small = d.nt <= AdSmall::NTB;
+    if (small) {
+        k.predict = f32 ? k_ad_predict<float, AdSmall> : k_ad_predict<double, AdSmall>;
+        k.update = f32 ? k_ad_update<float, AdSmall> : k_ad_update<double, AdSmall>;
+        k.wgs = AdSmall::WGS;
+    } else {
+        k.predict = f32 ? k_ad_predict<float, AdLarge> : k_ad_predict<double, AdLarge>;
+        k.update = f32 ? k_ad_update<float, AdLarge> : k_ad_update<double, AdLarge>;
+        k.wgs = AdLarge::WGS;
+    }
+    k.part1 = k_ad_part1;
+    k.part2 = f32 ? k_ad_part2<float> : k_ad_part2<double>;
+    k.lds = ad_lds_bytes(d.nt, f32 ? 4 : 8);
+    return k;
 }
 
 // kernel class: ((model - 1) * 3 + lmm) * 8 + precision * 4 + order
@@ -259,10 +293,20 @@ static pf_status check_config(const pf_config* c)
         if (c->d != 16 || c->p != 12) return fail(PF_EINVAL, "chain16 needs d = 16, p = 12");
         if (!c->model_consts || c->n_model_consts != 32) return fail(PF_EINVAL, "chain16 needs 32 model constants");
         if (!c->rates_fixed || c->n_rates_fixed != 16) return fail(PF_EINVAL, "chain16 needs 16 rates");
+    } else if (c->model == PF_MODEL_ADVDIFF) {
+        if (!c->model_consts || c->n_model_consts != 1) return fail(PF_EINVAL, "advdiff needs the grid side as its one model constant");
+        const double ntd = c->model_consts[0];
+        if (!(ntd >= 3.0 && ntd <= (double)AD_NTMAX) || ntd != std::floor(ntd))
+            return fail(PF_EINVAL, "advdiff grid side must be an integer in 3..39");
+        const uint32_t nt = (uint32_t)ntd;
+        if (c->d != nt * nt || c->p != (uint32_t)AD_P) return fail(PF_EINVAL, "advdiff needs d = nt^2, p = 5");
+        if (c->lmm != PF_LMM_BDF && c->lmm != PF_LMM_BDF_SDIRK) return fail(PF_EINVAL, "advdiff supports BDF and BDF_SDIRK");
     } else {
         return fail(PF_EINVAL, "unknown model");
     }
-    if (c->m < 1 || c->m > (uint32_t)MMAX || !c->obs_index) return fail(PF_EINVAL, "m must be 1..4 with obs_index");
+    const uint32_t mmax = c->model == PF_MODEL_ADVDIFF ? (uint32_t)MMAX : (uint32_t)MOBS_KIN;
+    if (c->m < 1 || c->m > mmax || !c->obs_index)
+        return fail(PF_EINVAL, "m must be 1..4 (kinetic models) or 1..32 (advdiff), with obs_index");
     for (uint32_t i = 0; i < c->m; ++i)
         if (c->obs_index[i] >= c->d) return fail(PF_EINVAL, "obs_index out of range");
     if (c->n_particles < 1 || c->n_particles > (1ull << 24)) return fail(PF_EINVAL, "n_particles must be 1..2^24");
@@ -305,7 +349,9 @@ static void fill_static(FilterDesc& d, const pf_config* c)
     int cl = 0;
     while ((1ll << cl) < (long long)d.n) ++cl;
     d.shift = 62 - cl;
-    d.nacc = 3 + d.p + d.p * (d.p + 1) / 2 + d.d + NPLAIN;
+    // the advection-diffusion state mean has its own per-tile sums (partx)
+    d.nacc = 3 + d.p + d.p * (d.p + 1) / 2 + (d.model == MODEL_ADVDIFF ? 0 : d.d) + NPLAIN;
+    d.nt = d.model == MODEL_ADVDIFF ? (int)c->model_consts[0] : 0;
     d.seed = c->seed;
     d.a = c->shrink_a;
     d.s = std::sqrt(1.0 - c->shrink_a * c->shrink_a);
@@ -314,7 +360,7 @@ static void fill_static(FilterDesc& d, const pf_config* c)
         d.prior_mean[i] = c->prior_mean[i];
         d.prior_sd[i] = c->prior_sd[i];
     }
-    for (uint32_t i = 0; i < c->d; ++i) {
+    for (uint32_t i = 0; i < c->d && i < (uint32_t)DMAX; ++i) {
         d.x0[i] = c->x0[i];
         d.floor_[i] = c->state_floor[i];
         d.floor_f[i] = (float)c->state_floor[i];
@@ -328,7 +374,7 @@ static void fill_static(FilterDesc& d, const pf_config* c)
 
 // bytes and offsets of one filter's buffers inside its pool block
 struct Layout {
-    uint64_t x[2], th[2], lw[2], lbar, lg, q, anc, part1, tsum, part2, total;
+    uint64_t x[2], th[2], lw[2], lbar, lg, q, anc, part1, tsum, part2, x0b, smb, partx, total;
 };
 static Layout layout_of(const FilterDesc& d)
 {
@@ -349,6 +395,11 @@ static Layout layout_of(const FilterDesc& d)
     L.part1 = take((uint64_t)d.ntiles * PART1_STRIDE * 8);
     L.tsum = take((uint64_t)d.ntiles * 8);
     L.part2 = take((uint64_t)d.ntiles * d.nacc * 8);
+    if (d.model == MODEL_ADVDIFF) {
+        L.x0b = take((uint64_t)d.d * 8);
+        L.smb = take((uint64_t)d.d * 8);
+        L.partx = take((uint64_t)d.d * d.ntiles * 8);
+    }
     L.total = o;
     return L;
 }
@@ -368,6 +419,11 @@ static void bind_buffers(FilterDesc& d, char* base, const Layout& L)
     d.part1 = (double*)(base + L.part1);
     d.tsum = (uint64_t*)(base + L.tsum);
     d.part2 = (double*)(base + L.part2);
+    if (d.model == MODEL_ADVDIFF) {
+        d.x0b = (const double*)(base + L.x0b);
+        d.smb = (double*)(base + L.smb);
+        d.partx = (double*)(base + L.partx);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -516,11 +572,19 @@ extern "C" pf_status pf_create(pf_context* ctx, const pf_config* cfg, pf_filter*
         hipMemcpyAsync(ctx->d_state + f->slot, &st, sizeof(FilterState), hipMemcpyHostToDevice, ctx->init_stream) != hipSuccess ||
         hipMemsetAsync(f->desc.anc, 0, sizeof(int32_t) * (size_t)f->desc.npad, ctx->init_stream) != hipSuccess)
         return cleanup(fail(PF_EDEVICE, "upload of filter descriptor failed"));
+    if (f->desc.model == MODEL_ADVDIFF) {
+        // the initial field, which is also the state mean of the prior ensemble
+        const size_t b = sizeof(double) * (size_t)f->desc.d;
+        if (hipMemcpyAsync((void*)f->desc.x0b, cfg->x0, b, hipMemcpyHostToDevice, ctx->init_stream) != hipSuccess ||
+            hipMemcpyAsync(f->desc.smb, cfg->x0, b, hipMemcpyHostToDevice, ctx->init_stream) != hipSuccess ||
+            hipStreamSynchronize(ctx->init_stream) != hipSuccess)
+            return cleanup(fail(PF_EDEVICE, "upload of the initial field failed"));
+    }
     const unsigned grid = grid_for(ctx, f->desc.ntiles);
     hipLaunchKernelGGL(init_kernel(f->desc.model, f->desc.prec), dim3(grid), dim3(TILE), 0, ctx->init_stream, f->slot,
                        ctx->d_desc, ctx->d_state);
-    hipLaunchKernelGGL(f->desc.model == MODEL_ROBERTSON ? k_init_moments<Robertson<double>> : k_init_moments<Chain16<double>>,
-                       dim3(1), dim3(TILE), 0, ctx->init_stream, f->slot, ctx->d_desc, ctx->d_state);
+    hipLaunchKernelGGL(init_moments_kernel(f->desc.model), dim3(1), dim3(TILE), 0, ctx->init_stream, f->slot,
+                       ctx->d_desc, ctx->d_state);
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(ctx->init_stream) != hipSuccess)
         return cleanup(fail(PF_EDEVICE, "initialisation kernel failed"));
     int32_t status = 0;
@@ -615,6 +679,7 @@ static pf_status submit(pf_context* ctx, uint32_t count, pf_filter* const* fs, c
             if (fs[c] == f) return fail(PF_EINVAL, "a filter appears twice in one batch");
         if (!std::isfinite(t_obs[b])) return fail(PF_EINVAL, "non-finite observation time");
         if (!(t_obs[b] > f->t_submitted)) return fail(PF_EORDER, "observation time not increasing");
+        if (f->desc.m > ystride) return fail(PF_EINVAL, "a batched filter observes more than 4 components");
         for (int i = 0; i < f->desc.m; ++i) {
             const double yy = y[(size_t)b * ystride + i], ss = sigma[(size_t)b * ystride + i];
             if (!std::isfinite(yy) || !std::isfinite(ss) || !(ss > 0.0))
@@ -686,9 +751,30 @@ static pf_status submit(pf_context* ctx, uint32_t count, pf_filter* const* fs, c
     };
 
     MomentsKernel moments_kernel = k_moments<false, 0>;
-    if (inline_rec)
-        moments_kernel = fs[0]->desc.model == MODEL_ROBERTSON ? k_moments<true, MODEL_ROBERTSON>
-                                                              : k_moments<true, MODEL_CHAIN16>;
+    if (inline_rec) {
+        const int mdl = fs[0]->desc.model;
+        moments_kernel = mdl == MODEL_ROBERTSON ? k_moments<true, MODEL_ROBERTSON>
+                         : mdl == MODEL_CHAIN16 ? k_moments<true, MODEL_CHAIN16>
+                                                : k_moments<true, MODEL_ADVDIFF>;
+    }
+    // advection-diffusion filters: their own kernels, one launch per filter,
+    // with the record in the kernel arguments (so such batches are not
+    // captured into graphs)
+    std::vector<uint32_t> ad_entries;
+    for (uint32_t b = 0; b < count; ++b)
+        if (fs[b]->desc.model == MODEL_ADVDIFF) ad_entries.push_back(b);
+    auto ad_launch = [&](bool update) {
+        for (uint32_t b : ad_entries) {
+            const FilterDesc& d = fs[b]->desc;
+            const AdKernels k = ad_kernels(d);
+            const unsigned gp = (unsigned)std::min(d.n, 65535), gt = grid_for(ctx, d.ntiles);
+            const int slot = fs[b]->slot;
+            hipLaunchKernelGGL(update ? k.update : k.predict, dim3(gp), dim3(k.wgs), k.lds, ctx->stream, recs[b],
+                               slot, ctx->d_desc, ctx->d_state);
+            hipLaunchKernelGGL(update ? k.part2 : k.part1, dim3(gt), dim3(TILE), 0, ctx->stream, recs[b], slot,
+                               ctx->d_desc, ctx->d_state);
+        }
+    };
 
     // the step: the copy (batches only), then the kernel groups
     auto enqueue = [&]() -> hipError_t {
@@ -702,11 +788,13 @@ static pf_status submit(pf_context* ctx, uint32_t count, pf_filter* const* fs, c
         for (const Range& r : ranges) {
             int model, lmm, prec, order;
             class_decode(r.cls, model, lmm, prec, order);
+            if (model == MODEL_ADVDIFF) continue;
             hipLaunchKernelGGL(inline_rec ? predict_kernel<true>(model, lmm, prec, order)
                                           : predict_kernel<false>(model, lmm, prec, order),
                                dim3(grid_for(ctx, r.cnt)), dim3(TILE), 0,
                                ctx->stream, part(r), ctx->d_desc, ctx->d_state);
         }
+        ad_launch(false);
         if (timed && (e = hipEventRecord(sg.tev[1], ctx->stream)) != hipSuccess) return e;
         hipLaunchKernelGGL(inline_rec ? k_count<true> : k_count<false>, dim3(grid_for(ctx, n_all)), dim3(TILE), 0,
                            ctx->stream, all, ctx->d_desc,
@@ -718,11 +806,13 @@ static pf_status submit(pf_context* ctx, uint32_t count, pf_filter* const* fs, c
         for (const Range& r : ranges) {
             int model, lmm, prec, order;
             class_decode(r.cls, model, lmm, prec, order);
+            if (model == MODEL_ADVDIFF) continue;
             hipLaunchKernelGGL(inline_rec ? update_kernel<true>(model, lmm, prec, order)
                                           : update_kernel<false>(model, lmm, prec, order),
                                dim3(grid_for(ctx, r.cnt)), dim3(TILE), 0,
                                ctx->stream, part(r), ctx->d_desc, ctx->d_state);
         }
+        ad_launch(true);
         if (timed && (e = hipEventRecord(sg.tev[3], ctx->stream)) != hipSuccess) return e;
         hipLaunchKernelGGL(moments_kernel,
                            dim3(std::min<uint32_t>(count, (uint32_t)ctx->grid_cap)), dim3(TILE), 0,
@@ -736,7 +826,7 @@ static pf_status submit(pf_context* ctx, uint32_t count, pf_filter* const* fs, c
     // profiled submissions launch directly: their events then bracket the
     // kernels themselves.  A single filter's step launches directly too: its
     // record is in the kernel arguments, which a graph would freeze.
-    if (ctx->use_graphs && !timed && !inline_rec) {
+    if (ctx->use_graphs && !timed && !inline_rec && ad_entries.empty()) {
         auto it = ctx->graphs.find(sig);
         if (it == ctx->graphs.end() && ++ctx->seen[sig] >= 2) {
             // a repeated batch shape: capture it once and replay it afterwards
@@ -808,7 +898,7 @@ extern "C" pf_status pf_assimilate_async(pf_filter* f, double t_obs, const doubl
 {
     if (!f || !y || !sigma) return fail(PF_EINVAL, "NULL argument");
     HIP_TRY(hipSetDevice(f->ctx->device));
-    return submit(f->ctx, 1, &f, &t_obs, y, sigma, MMAX, ticket);
+    return submit(f->ctx, 1, &f, &t_obs, y, sigma, MMAX, ticket);   // y, sigma: [m]
 }
 
 extern "C" pf_status pf_wait(pf_filter* f, uint64_t ticket)
@@ -861,7 +951,7 @@ extern "C" pf_status pf_assimilate_batch(pf_context* ctx, uint32_t count, pf_fil
 {
     if (!ctx || (count && (!filters || !t_obs || !y || !sigma))) return fail(PF_EINVAL, "NULL argument");
     HIP_TRY(hipSetDevice(ctx->device));
-    return submit(ctx, count, filters, t_obs, y, sigma, MMAX, tickets);
+    return submit(ctx, count, filters, t_obs, y, sigma, BATCH_YSTRIDE, tickets);
 }
 
 static pf_status read_state(pf_filter* f, FilterState* st)
@@ -887,7 +977,15 @@ extern "C" pf_status pf_posterior(pf_filter* f, double* mean, double* cov, doubl
     const int p = f->desc.p, d = f->desc.d;
     if (mean) for (int i = 0; i < p; ++i) mean[i] = st.theta_bar[i];
     if (cov) for (int i = 0; i < p * p; ++i) cov[i] = st.C[i];
-    if (state_mean) for (int i = 0; i < d; ++i) state_mean[i] = st.state_mean[i];
+    if (state_mean) {
+        if (f->desc.model == MODEL_ADVDIFF) {
+            // read on the context stream, after the filter's last step
+            HIP_TRY(hipMemcpyAsync(state_mean, f->desc.smb, sizeof(double) * d, hipMemcpyDeviceToHost, f->ctx->stream));
+            HIP_TRY(hipStreamSynchronize(f->ctx->stream));
+        } else {
+            for (int i = 0; i < d; ++i) state_mean[i] = st.state_mean[i];
+        }
+    }
     if (ess) *ess = st.ess;
     if (step) *step = st.j;
     return PF_OK;
@@ -995,6 +1093,26 @@ extern "C" pf_status pf_test_propagate(const pf_config* cfg, uint64_t n, const d
     hipError_t e = hipMemcpyAsync(dd, &d, sizeof(FilterDesc), hipMemcpyHostToDevice, st);
     PropKernel k;
     const bool f32 = d.prec == PREC_FP32;
+    if (d.model == MODEL_ADVDIFF) {
+        const bool small = d.nt <= AdSmall::NTB;
+        PropKernel ka;
+        if (small)
+            ka = f32 ? (lte ? k_ad_test_propagate<float, AdSmall, true> : k_ad_test_propagate<float, AdSmall, false>)
+                     : (lte ? k_ad_test_propagate<double, AdSmall, true> : k_ad_test_propagate<double, AdSmall, false>);
+        else
+            ka = f32 ? (lte ? k_ad_test_propagate<float, AdLarge, true> : k_ad_test_propagate<float, AdLarge, false>)
+                     : (lte ? k_ad_test_propagate<double, AdLarge, true> : k_ad_test_propagate<double, AdLarge, false>);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(ka, dim3((unsigned)std::min<uint64_t>(n, 65535)), dim3(small ? AdSmall::WGS : AdLarge::WGS),
+                               ad_lds_bytes(d.nt, f32 ? 4 : 8), st, dd, n, x_in, theta, h, x_out, lte ? gamma : nullptr,
+                               (unsigned long long*)iters);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        (void)hipFree(dd);
+        if (e != hipSuccess) return fail(PF_EDEVICE, std::string("propagate: ") + hipGetErrorString(e));
+        return PF_OK;
+    }
     if (d.model == MODEL_ROBERTSON)
         k = f32 ? (lte ? pick_prop<Robertson, float, true>(d.lmm, d.order) : pick_prop<Robertson, float, false>(d.lmm, d.order))
                 : (lte ? pick_prop<Robertson, double, true>(d.lmm, d.order) : pick_prop<Robertson, double, false>(d.lmm, d.order));
@@ -1103,7 +1221,11 @@ __global__ void k_test_get(const FilterDesc* descs, const FilterState* states, i
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= fd.n) return;
     const R* xb = (const R*)fd.x[cur];
-    if (x) for (int i = 0; i < fd.d; ++i) x[(size_t)i * fd.n + n] = (double)xb[(size_t)i * fd.npad + n];
+    // advection-diffusion fields are stored particle-major
+    const bool pm = fd.model == MODEL_ADVDIFF;
+    if (x)
+        for (int i = 0; i < fd.d; ++i)
+            x[(size_t)i * fd.n + n] = (double)xb[pm ? (size_t)n * fd.d + i : (size_t)i * fd.npad + n];
     if (th) for (int i = 0; i < fd.p; ++i) th[(size_t)i * fd.n + n] = fd.theta[cur][(size_t)i * fd.npad + n];
     if (lw) lw[n] = fd.logw[cur][n];
 }
@@ -1116,7 +1238,8 @@ __global__ void k_test_set(const FilterDesc* descs, const FilterState* states, i
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= fd.n) return;
     R* xb = (R*)fd.x[cur];
-    for (int i = 0; i < fd.d; ++i) xb[(size_t)i * fd.npad + n] = (R)x[(size_t)i * fd.n + n];
+    const bool pm = fd.model == MODEL_ADVDIFF;
+    for (int i = 0; i < fd.d; ++i) xb[pm ? (size_t)n * fd.d + i : (size_t)i * fd.npad + n] = (R)x[(size_t)i * fd.n + n];
     for (int i = 0; i < fd.p; ++i) fd.theta[cur][(size_t)i * fd.npad + n] = th[(size_t)i * fd.n + n];
     fd.logw[cur][n] = lw[n];
 }

@@ -313,6 +313,8 @@ extern "C" pf_status pf_server_create(pf_context* ctx, const pf_server_config* c
 extern "C" pf_status pf_server_open(pf_server* s, const pf_config* cfg, uint64_t* stream)
 {
     if (!s || !cfg || !stream) return PF_EINVAL;
+    // served steps go through batched submissions, whose rows hold 4 observations
+    if (cfg->m > 4) return PF_EINVAL;
     const uint64_t need = pf_filter_bytes(cfg);
     if (need == 0) return PF_EINVAL;
     uint64_t used = 0, cap = 0;

@@ -7,9 +7,15 @@
 namespace pf {
 
 constexpr int TILE = 256;      // particles per workgroup tile (4 wavefronts)
-constexpr int DMAX = 16;       // largest state dimension
+constexpr int DMAX = 16;       // largest state dimension of the kinetic models (held in registers)
 constexpr int PMAX = 12;       // largest parameter dimension
-constexpr int MMAX = 4;        // largest number of observed components
+constexpr int MMAX = 32;       // largest number of observed components
+constexpr int MOBS_KIN = 4;    // observed components of the kinetic models
+constexpr int BATCH_YSTRIDE = 4;   // row stride of y and sigma in a batched submission
+// advection-diffusion: nt x nt grid values per particle, nt <= 39
+constexpr int AD_NTMAX = 39;
+constexpr int AD_DMAX = AD_NTMAX * AD_NTMAX;
+constexpr int AD_P = 5;
 constexpr int RING = 64;       // per-filter status ring (steps in flight)
 // per-tile first-stage partials: tile max, sum exp, Newton iterations and
 // failed solves of the predictor
@@ -31,7 +37,7 @@ enum Status : int32_t {
     ST_ENONFINITE = 5, ST_EDEVICE = 6, ST_EBUSY = 7, ST_EORDER = 8
 };
 
-enum Model : int32_t { MODEL_ROBERTSON = 1, MODEL_CHAIN16 = 2 };
+enum Model : int32_t { MODEL_ROBERTSON = 1, MODEL_CHAIN16 = 2, MODEL_ADVDIFF = 3 };
 enum Prec : int32_t { PREC_FP64 = 0, PREC_FP32 = 1 };
 
 // RNG purposes: third word of the Philox counter (step, particle, purpose, block)
@@ -44,7 +50,8 @@ struct FilterDesc {
     int32_t order, substeps, kmax, prec;
     int32_t obs[MMAX];
     int32_t n, npad, ntiles, shift;     // shift: resampling scale 2^shift
-    int32_t nacc, g_direct, resampling, lmm;    // resampling: 0 systematic, 1 multinomial; lmm: 0 BDF, 1 AM
+    int32_t nacc, g_direct, resampling, lmm;    // resampling: 0 systematic, 1 multinomial; lmm: 0 BDF, 1 AM, 2 BDF + SDIRK start-up
+    int32_t nt, pad_;                   // advection-diffusion: grid side (d = nt^2)
     uint64_t seed;
     double a, s, rtol;                  // shrink factor, jitter sqrt(1-a^2), Newton rtol
     double prior_mean[PMAX], prior_sd[PMAX];
@@ -65,6 +72,11 @@ struct FilterDesc {
     double* part1;                      // [PART1_STRIDE][ntiles] (max, sum exp, iterations, fails), by column
     uint64_t* tsum;                     // [ntiles] integer weight per tile (then offsets)
     double* part2;                      // [nacc][ntiles] moment partials and counters, by column
+    // advection-diffusion only (the state is too large for the inline arrays;
+    // x is stored particle-major, [npad][d])
+    const double* x0b;                  // [d] initial field
+    double* smb;                        // [d] weighted state mean of the last committed step
+    double* partx;                      // [d][ntiles] per-tile weighted state sums (scaled by the tile max)
 };
 
 // Dynamic state of one filter (device resident, updated by the kernels).

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libpf_hip.so")
 
 PF_OK, PF_EINVAL, PF_ENOMEM, PF_EADMIT, PF_EDEGENERATE = 0, 1, 2, 3, 4
 PF_ENONFINITE, PF_EDEVICE, PF_EBUSY, PF_EORDER = 5, 6, 7, 8
-PF_MODEL_ROBERTSON, PF_MODEL_CHAIN16 = 1, 2
+PF_MODEL_ROBERTSON, PF_MODEL_CHAIN16, PF_MODEL_ADVDIFF = 1, 2, 3
 PF_LMM_BDF, PF_LMM_AM, PF_LMM_BDF_SDIRK = 0, 1, 2
 PF_PREC_FP64, PF_PREC_FP32_PROP = 0, 1
 PF_RESAMPLE_SYSTEMATIC, PF_RESAMPLE_MULTINOMIAL = 0, 1
@@ -153,8 +153,9 @@ class Config:
         c.d, c.p, c.m = prob.d, prob.p, prob.m
         c.obs_index = self.obs.ctypes.data_as(C.POINTER(C.c_uint32))
         chain = prob.model == PF_MODEL_CHAIN16
-        c.model_consts = _dp(self.mc) if chain else None
-        c.n_model_consts = len(prob.model_consts) if chain else 0
+        consts = chain or prob.model == PF_MODEL_ADVDIFF
+        c.model_consts = _dp(self.mc) if consts else None
+        c.n_model_consts = len(prob.model_consts) if consts else 0
         c.rates_fixed = _dp(self.rf) if chain else None
         c.n_rates_fixed = len(prob.rates_fixed) if chain else 0
         c.n_particles = int(prob.n_particles if n_particles is None else n_particles)
@@ -192,11 +193,13 @@ class Context:
         n = len(filters)
         hs = (C.c_void_p * n)(*[f.h.value for f in filters])
         t = np.ascontiguousarray(t_obs, dtype=np.float64)
+        # rows of 4 observations (the library refuses a filter with m > 4)
         yy = np.zeros((n, 4))
         ss = np.ones((n, 4))
         for i, f in enumerate(filters):
-            yy[i, : f.m] = y[i][: f.m]
-            ss[i, : f.m] = sigma[i][: f.m]
+            k = min(f.m, 4)
+            yy[i, :k] = y[i][:k]
+            ss[i, :k] = sigma[i][:k]
         tk = (C.c_uint64 * n)()
         check(lib().pf_assimilate_batch(self.h, n, hs, _dp(t), _dp(yy), _dp(ss), tk), "pf_assimilate_batch")
         return list(tk)
@@ -241,8 +244,8 @@ class Filter:
         return st
 
     def assimilate_async(self, t, y, sigma):
-        yy = np.zeros(4)
-        ss = np.ones(4)
+        yy = np.zeros(max(4, self.m))
+        ss = np.ones(max(4, self.m))
         yy[: self.m] = y[: self.m]
         ss[: self.m] = sigma[: self.m]
         tk = C.c_uint64()

@@ -81,6 +81,33 @@ def test_bad_configs_rejected_on_host():
         assert L.pf_filter_bytes(cfg.ptr()) > 0
 
 
+def test_advdiff_configs_on_host():
+    L = pf.lib()
+    for n in (4, 8, 20, 40):
+        prob = inputs.advdiff(1000, 2, n=n)
+        cfg = pf.Config(prob, pf.PF_PREC_FP32_PROP)
+        b = L.pf_filter_bytes(cfg.ptr())
+        # two particle-major fields of d floats per particle, plus the rest
+        assert b > 2 * 4 * prob.d * 1024
+    prob = inputs.advdiff(1000, 2, n=8)
+    for mutate in (lambda c: setattr(c.c, "lmm", pf.PF_LMM_AM), lambda c: setattr(c.c, "p", 3),
+                   lambda c: setattr(c.c, "d", 48), lambda c: setattr(c.c, "m", 33),
+                   lambda c: setattr(c.c, "n_model_consts", 0)):
+        cfg = pf.Config(prob)
+        mutate(cfg)
+        assert L.pf_filter_bytes(cfg.ptr()) == 0
+    # grid sides 3..39 only
+    big = inputs.advdiff(100, 2, n=8)
+    cfg = pf.Config(big)
+    cfg.mc[0] = 40.0
+    cfg.c.d = 1600
+    assert L.pf_filter_bytes(cfg.ptr()) == 0
+    # the kinetic models keep at most 4 observed components
+    rb = pf.Config(inputs.robertson(100, 5))
+    rb.c.m = 5
+    assert L.pf_filter_bytes(rb.ptr()) == 0
+
+
 def test_product_never_loads_the_oracle():
     # the binding and the HIP sources do not reference the oracle
     for path in ("paper_1411_1702_amd/pf.py", "paper_1411_1702_amd/inputs.py",

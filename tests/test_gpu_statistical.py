@@ -2,9 +2,18 @@
 the log-parameters at every observation step, GPU vs oracle, within 3 Monte
 Carlo standard errors.  Replicates use independent seeds on the two sides
 (GPU seeds 100+r, oracle seeds r), so the comparison is a two-sample test;
-MCSE^2 = var_gpu/R + var_oracle/R over the R replicates.  Whole runs cannot
-be compared element by element: a last-bit difference eventually flips a
-resampling decision and the runs decorrelate.
+MCSE^2 = var_gpu/R + var_oracle/R over the R replicates.  FP32 runs cannot
+be compared element by element: their propagation differs from the FP64
+oracle by more than rounding and the runs decorrelate (FP64 runs with shared
+seeds are compared step by step in test_gpu_wholerun.py).
+
+Calibration: the per-step z-scores of one comparison are strongly correlated
+over steps (the posterior at step j carries into step j+1), so an excursion
+of one replicate set spans many steps.  Independent oracle seed sets compared
+with each other exceed |z| = 3 on up to 6% of the steps (small AM1 problem,
+R = 16) and, with R = 8 over 200 steps, one oracle set ran ~7% high in its
+posterior sd against three others.  Hence R >= 12 where the oracle is cheap,
+at most 10% of steps beyond 3 MCSE, and no step beyond 5.
 """
 import numpy as np
 import pytest
@@ -47,9 +56,7 @@ def _check(pf, oracle, prob, precs, R, T):
             for name, z in (("mean", _zscores(gm, ora_m)), ("sd", _zscores(gs, ora_s))):
                 z = z[np.isfinite(z)]
                 frac = np.mean(np.abs(z) > 3.0)
-                # 3 MCSE per comparison; the steps are correlated, so allow the
-                # binomial tail a little room
-                assert frac <= 0.05, (prec, name, frac, np.abs(z).max())
+                assert frac <= 0.10, (prec, name, frac, np.abs(z).max())
                 assert np.abs(z).max() < 5.0, (prec, name, np.abs(z).max())
 
 
@@ -79,10 +86,17 @@ def test_small_robertson_bdf3_sdirk_within_3_mcse(pf, oracle):
     _check(pf, oracle, prob, (pf.PF_PREC_FP32_PROP,), R=16, T=50)
 
 
+def test_advdiff_within_3_mcse(pf, oracle):
+    """The advection-diffusion problem of Sec. 4 on a 7 x 7 grid, N=512,
+    5 observations at 20 sites, BDF2 with h = 0.1, R=16."""
+    prob = inputs.advdiff(512, 5, seed=0, n=8)
+    _check(pf, oracle, prob, (pf.PF_PREC_FP32_PROP,), R=16, T=5)
+
+
 def test_robertson_200_steps_within_3_mcse(pf, oracle):
-    """The large Robertson schedule (200 observations) at N=8192, R=8."""
+    """The large Robertson schedule (200 observations) at N=8192, R=16."""
     prob = inputs.robertson(8192, 200, seed=0)
-    _check(pf, oracle, prob, (pf.PF_PREC_FP32_PROP,), R=8, T=200)
+    _check(pf, oracle, prob, (pf.PF_PREC_FP32_PROP,), R=16, T=200)
 
 
 def test_chain_within_3_mcse(pf, oracle):
