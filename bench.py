@@ -46,6 +46,33 @@ FLOPS_AM = {
     inputs.MODEL_ROBERTSON: {"iter": 60, "sub_predict": 30, "sub_update": 55},
     inputs.MODEL_CHAIN: {"iter": 384, "sub_predict": 257, "sub_update": 385},
 }
+
+
+def advdiff_flops(prob, update):
+    """Algorithmic flops of one particle's pass on the advection-diffusion
+    model: the 2D transforms (each 12 nt^2 (nt/2 + 1): a real-to-half-spectrum
+    row pass of 4 flop per term and a complex column pass of 8, and the same
+    back) -- one forward and one inverse per pass, plus one inverse per step
+    for the local-error estimate in the repropagation -- and the per-mode
+    recurrence (about 25 flop per mode and step in the predictor, 45 with the
+    estimate).  RNG, likelihood and moments are not counted."""
+    nt = int(prob.model_consts[0])
+    modes = nt * (nt // 2 + 1)
+    M = prob.substeps
+    transforms = (2 + M) if update else 2
+    return transforms * 12 * nt * nt * (nt // 2 + 1) + M * modes * (45 if update else 25)
+
+
+def algorithmic_bytes(prob):
+    """HBM bytes one update launch must move per particle: Robertson 92 (the
+    gathered state, parameters and weights, the new state, parameters and
+    weight, the ancestor); advection-diffusion: the ancestor's field and the
+    new field (4 d bytes each in FP32) plus the same parameter traffic."""
+    if prob.model == inputs.MODEL_ADVDIFF:
+        return (8 * prob.d + 2 * 8 * prob.p + 3 * 8 + 4) * prob.n_particles
+    return 92 * prob.n_particles
+
+
 # HBM bytes of one k_update launch (Robertson, N = 2^17, FP32 propagation)
 # from two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE; KiB per dispatch),
 # each scaled by what the counter reads for a plain 1 GiB device copy in the
@@ -54,7 +81,7 @@ FLOPS_AM = {
 # sources: once they change, the figure no longer applies and bench reports
 # null until the counters are taken again.
 TRAFFIC = {
-    "1619723d46498aa3": {"fetch_kib": 3439.4, "write_kib": 5720.0, "fetch_scale": 2.0, "write_scale": 1.0},
+    "d26da6bb72b1c3fd": {"fetch_kib": 3427.0, "write_kib": 5936.0, "fetch_scale": 2.0, "write_scale": 1.0},
 }
 KERNEL_SOURCES = ("pf_kernels.hip", "pf_device.hpp", "pf_types.hpp")
 
@@ -82,6 +109,11 @@ def update_traffic_bytes(prob):
 # MI355X vector ALU peak: 256 CU x 4 SIMD x 16 lanes x 2 flop (fma) x 2.4 GHz
 PEAK_VALU_NONPACKED = 256 * 4 * 16 * 2 * 2.4e9 / 1e12      # 78.6 TFLOP/s (fp32 and fp64)
 PEAK_FP32_PUBLISHED = 157.3                                   # TFLOP/s, packed fp32
+
+
+def progress(msg):
+    """One line per finished phase on stderr (a long run shows it is alive)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def _percentile(v, q):
@@ -144,13 +176,17 @@ def time_path(pf, ctx, prob, prec, steps, warmup):
     s1 = f.stats()
     f.close()
     n = prob.n_particles
-    # BDF with the SDIRK start-up is priced with the BDF model: its extra
-    # per-stage right-hand sides are not counted (a lower bound)
-    fl = (FLOPS_AM if getattr(prob, "lmm", 0) == 1 else FLOPS)[prob.model]
     iters_upd = s1["newton_update"] - s0["newton_update"]
     iters_pred = s1["newton_predict"] - s0["newton_predict"]
-    flop_upd = iters_upd * fl["iter"] + steps * n * prob.substeps * fl["sub_update"]
-    flop_pred = iters_pred * fl["iter"] + steps * n * prob.substeps * fl["sub_predict"]
+    if prob.model == inputs.MODEL_ADVDIFF:
+        flop_upd = steps * n * advdiff_flops(prob, True)
+        flop_pred = steps * n * advdiff_flops(prob, False)
+    else:
+        # BDF with the SDIRK start-up is priced with the BDF model: its extra
+        # per-stage right-hand sides are not counted (a lower bound)
+        fl = (FLOPS_AM if getattr(prob, "lmm", 0) == 1 else FLOPS)[prob.model]
+        flop_upd = iters_upd * fl["iter"] + steps * n * prob.substeps * fl["sub_update"]
+        flop_pred = iters_pred * fl["iter"] + steps * n * prob.substeps * fl["sub_predict"]
     wall = t1 - t0
     return {
         "wall_s": wall,
@@ -208,6 +244,8 @@ def cpu_baseline(prob, target_s):
     from oracle import oracle as O
     O.lib()
     threads = O.num_threads()
+    if prob.model == inputs.MODEL_ADVDIFF:
+        return cpu_baseline_particles(O, prob, target_s, threads)
     F = O.Filter(prob)
     t0 = time.perf_counter()
     F.step(prob.times[0], prob.y[0], prob.sigma[0])
@@ -240,6 +278,25 @@ def cpu_baseline(prob, target_s):
         res["speedup_S_P"] = sp
         res["efficiency_E_P"] = sp / threads
     return res
+
+
+def cpu_baseline_particles(O, prob, target_s, threads):
+    """The oracle on the advection-diffusion workload: its dense LU makes one
+    step of the full ensemble far longer than the budget, so the sample is
+    the first observation step for a subset of the particles (its cost is
+    linear in their number: the per-particle integrations dominate), sized
+    from a pilot of one particle per thread."""
+    t0 = time.perf_counter()
+    O.Filter(prob.with_particles(threads)).step(prob.times[0], prob.y[0], prob.sigma[0])
+    pilot = time.perf_counter() - t0
+    n = max(threads, min(prob.n_particles, int(threads * max(1.0, 0.8 * target_s / max(pilot, 1e-3)))))
+    t0 = time.perf_counter()
+    O.Filter(prob.with_particles(n)).step(prob.times[0], prob.y[0], prob.sigma[0])
+    el = time.perf_counter() - t0
+    return {"value": n / el, "unit": "particle-steps/s", "cores": threads, "kind": "oracle",
+            "cpu_model": _cpu_model(),
+            "sample": f"first observation step with N={n} of the workload's {prob.n_particles} particles "
+                      f"(FP64 C oracle, OpenMP over particles, {el:.1f} s)"}
 
 
 def precision_error(pf, ctx, prob, steps, reps=8):
@@ -291,22 +348,34 @@ def single_filter(pf, args, prob):
     warm = min(args.warmup, prob.T)
     with pf.Context(0, 4 << 30) as ctx:
         r32 = time_path(pf, ctx, prob, pf.PF_PREC_FP32_PROP, steps, warm)
+        progress(f"fp32 path timed: {r32['ms_per_step']:.4f} ms/step")
         r64 = None if args.no_fp64 else time_path(pf, ctx, prob, pf.PF_PREC_FP64, steps, warm)
+        if r64:
+            progress(f"fp64 path timed: {r64['ms_per_step']:.4f} ms/step")
         lat = latency(pf, ctx, prob, pf.PF_PREC_FP32_PROP, min(60, prob.T))
+        progress("latency done")
         err = None if args.no_fp64 else precision_error(pf, ctx, prob, steps)
+        if err:
+            progress("precision comparison done")
     upd_ms = r32["kernel_ms"]["update"]
     achieved = r32["flop_update_per_launch"] / (upd_ms * 1e-3) / 1e12
-    model = "robertson" if prob.model == inputs.MODEL_ROBERTSON else "chain16"
+    model = {inputs.MODEL_ROBERTSON: "robertson", inputs.MODEL_CHAIN: "chain16"}.get(prob.model)
+    if prob.model == inputs.MODEL_ADVDIFF:
+        nt = int(prob.model_consts[0])
+        model = f"advdiff {nt}x{nt}"
     roofline = {
         "bound": "alu",
-        "kernel": f"k_update<{model}, fp32, {lmm_label(prob)}> (steps 3c-5: gather, proliferate, "
-                  "repropagation with Newton and local-error innovation, weights, tile moments)",
+        "kernel": (f"k_ad_update + k_ad_part2 <{model}, fp32, {lmm_label(prob)}> (steps 3c-5: gather, "
+                   "proliferate, repropagation mode by mode with the local-error innovation, weights, "
+                   "tile moments and state sums)" if prob.model == inputs.MODEL_ADVDIFF else
+                   f"k_update<{model}, fp32, {lmm_label(prob)}> (steps 3c-5: gather, proliferate, "
+                   "repropagation with Newton and local-error innovation, weights, tile moments)"),
         "achieved": achieved, "peak": PEAK_VALU_NONPACKED, "unit": "TFLOP/s",
         "frac": achieved / PEAK_VALU_NONPACKED,
         "frac_of_published_fp32": achieved / PEAK_FP32_PUBLISHED,
         "traffic": update_traffic_bytes(prob),
         "traffic_unit": "bytes per launch (HBM, counter-measured)",
-        "algorithmic_bytes": 92 * prob.n_particles,
+        "algorithmic_bytes": algorithmic_bytes(prob),
         "avg_launch_ms": upd_ms,
         "flop_per_launch": r32["flop_update_per_launch"],
     }
@@ -335,6 +404,7 @@ def single_filter(pf, args, prob):
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
+        progress("cpu baseline done")
     return out
 
 
@@ -451,7 +521,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--config", default="robertson",
-                    choices=["robertson", "small", "chain", "batched", "serving"])
+                    choices=["robertson", "small", "chain", "advdiff", "advdiff40", "batched", "serving"])
     ap.add_argument("--filters", type=int, default=256)
     ap.add_argument("--streams", type=int, default=2000)
     ap.add_argument("--resampling", default="systematic", choices=["systematic", "multinomial"],
@@ -489,12 +559,16 @@ def main():
         out = serving(pf, args)
     else:
         prob = {"robertson": inputs.config_robertson_large, "small": inputs.config_small,
-                "chain": inputs.config_chain}[args.config]()
+                "chain": inputs.config_chain, "advdiff": lambda: inputs.config_advdiff(20),
+                "advdiff40": lambda: inputs.config_advdiff(40)}[args.config]()
         if args.steps < 1:
             print("--steps must be >= 1", file=sys.stderr)
             sys.exit(2)
         prob.resampling = 1 if args.resampling == "multinomial" else 0
         prob.lmm = {"bdf": 0, "am": 1, "bdf_sdirk": 2}[args.lmm]
+        if prob.model == inputs.MODEL_ADVDIFF and prob.lmm == 1:
+            print("the advection-diffusion model runs BDF or BDF with the SDIRK start-up", file=sys.stderr)
+            sys.exit(2)
         if args.order:
             prob.order = args.order
         out = single_filter(pf, args, prob)

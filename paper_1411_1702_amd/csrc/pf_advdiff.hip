@@ -523,49 +523,62 @@ __global__ __launch_bounds__(S::WGS) void k_ad_update(StepRec rec, int slot, con
     }
 }
 
-// tile partials of step 6: the parameter moments (tile_moments, shift
-// theta_bar_j) and the weighted state sums, both scaled by the tile's
-// largest log-weight; counters: one linear solve per integration step
+// tile partials of step 6, one workgroup per (tile, chunk of 64 grid
+// points): the weighted state sums of the chunk over the tile's particles,
+// scaled by the tile's largest log-weight (each of the four wavefronts sums
+// every fourth particle, then the four are added); chunk 0 also writes the
+// parameter moments (tile_moments, shift theta_bar_j) and the counters (one
+// linear solve per integration step).
+constexpr int AD_CHUNK = 64;
+
 template <class R>
 __global__ __launch_bounds__(TILE) void k_ad_part2(StepRec rec, int slot, const FilterDesc* descs,
                                                    FilterState* states)
 {
     __shared__ double sh[TILE];
     __shared__ double ew[TILE];
+    __shared__ double red[NWAVE][AD_CHUNK];
     const FilterDesc& fd = descs[slot];
     const FilterState& st = states[slot];
     if (!step_valid(rec, st) || st.T == 0) return;
     const int nxt = st.cur ^ 1, d = fd.d;
+    const int nch = (d + AD_CHUNK - 1) / AD_CHUNK;
     const R* x = (const R*)fd.x[nxt];
-    for (int tile = blockIdx.x; tile < fd.ntiles; tile += gridDim.x) {
+    for (int b = blockIdx.x; b < fd.ntiles * nch; b += gridDim.x) {
+        const int tile = b / nch, chunk = b - tile * nch;
         const int n = tile * TILE + threadIdx.x;
         const bool valid = n < fd.n;
-        double l = -INFINITY;
-        double th[AD_P];
+        const double l = valid ? fd.logw[nxt][n] : -INFINITY;
+        if (chunk == 0) {
+            double th[AD_P];
 #pragma unroll
-        for (int i = 0; i < AD_P; ++i) th[i] = 0.0;
-        if (valid) {
-            l = fd.logw[nxt][n];
-#pragma unroll
-            for (int i = 0; i < AD_P; ++i) th[i] = fd.theta[nxt][(size_t)i * fd.npad + n];
+            for (int i = 0; i < AD_P; ++i) th[i] = valid ? fd.theta[nxt][(size_t)i * fd.npad + n] : 0.0;
+            const uint32_t nonf = valid && !(l > -INFINITY) ? 1u : 0u;
+            const uint64_t counts = pack_counts(valid ? (uint32_t)fd.substeps : 0u, 0u, nonf);
+            tile_moments<R, AD_P, 0>(l, valid, th, nullptr, st.theta_bar, counts,
+                                     fd.part1 + (size_t)2 * fd.ntiles + tile, fd.part2 + tile, fd.ntiles, sh);
         }
-        const uint32_t nonf = valid && !(l > -INFINITY) ? 1u : 0u;
-        const uint64_t counts = pack_counts(valid ? (uint32_t)fd.substeps : 0u, 0u, nonf);
-        tile_moments<R, AD_P, 0>(l, valid, th, nullptr, st.theta_bar, counts,
-                                 fd.part1 + (size_t)2 * fd.ntiles + tile, fd.part2 + tile, fd.ntiles, sh);
-        const double lv = valid ? l : -INFINITY;
-        const double Mt = block_max(lv, sh);
-        ew[threadIdx.x] = lv > -INFINITY ? exp(lv - Mt) : 0.0;
+        const double Mt = block_max(l, sh);
+        ew[threadIdx.x] = l > -INFINITY ? exp(l - Mt) : 0.0;
         __syncthreads();
         const int cnt = min(TILE, fd.n - tile * TILE);
-        const R* xt = x + (size_t)tile * TILE * d;
-        for (int i = threadIdx.x; i < d; i += TILE) {
-            double s = 0.0;
-            for (int r = 0; r < cnt; ++r) {
+        const int c = threadIdx.x % AD_CHUNK, g = threadIdx.x / AD_CHUNK;
+        const int i = chunk * AD_CHUNK + c;
+        double s = 0.0;
+        if (i < d) {
+            const R* xt = x + (size_t)tile * TILE * d + i;
+            for (int r = g; r < cnt; r += NWAVE) {
                 const double e = ew[r];
-                if (e > 0.0) s += e * (double)xt[(size_t)r * d + i];
+                if (e > 0.0) s += e * (double)xt[(size_t)r * d];
             }
-            fd.partx[(size_t)i * fd.ntiles + tile] = s;
+        }
+        red[g][c] = s;
+        __syncthreads();
+        if (g == 0 && i < d) {
+            double t = red[0][c];
+#pragma unroll
+            for (int w = 1; w < NWAVE; ++w) t += red[w][c];
+            fd.partx[(size_t)i * fd.ntiles + tile] = t;
         }
         __syncthreads();
     }

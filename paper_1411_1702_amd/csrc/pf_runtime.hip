@@ -767,7 +767,10 @@ static pf_status submit(pf_context* ctx, uint32_t count, pf_filter* const* fs, c
         for (uint32_t b : ad_entries) {
             const FilterDesc& d = fs[b]->desc;
             const AdKernels k = ad_kernels(d);
-            const unsigned gp = (unsigned)std::min(d.n, 65535), gt = grid_for(ctx, d.ntiles);
+            const unsigned gp = (unsigned)std::min(d.n, 65535);
+            // part2: one workgroup per (tile, chunk of grid points)
+            const int nch = (d.d + AD_CHUNK - 1) / AD_CHUNK;
+            const unsigned gt = grid_for(ctx, update ? d.ntiles * nch : d.ntiles);
             const int slot = fs[b]->slot;
             hipLaunchKernelGGL(update ? k.update : k.predict, dim3(gp), dim3(k.wgs), k.lds, ctx->stream, recs[b],
                                slot, ctx->d_desc, ctx->d_state);
