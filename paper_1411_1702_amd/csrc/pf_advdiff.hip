@@ -105,14 +105,16 @@ __device__ inline void ad_twiddles(const AdLds<R>& L, int nt)
 
 // forward transform along x (real field -> half spectrum rows):
 //   Y[iy][q] = sum_ix P[iy][ix] exp(-2 pi i q ix / nt)
-template <class R, int WGS>
-__device__ inline void dft_rows_fwd(const AdLds<R>& L, int nt, int kx)
+template <class R, int WGS, int NTC>
+__device__ inline void dft_rows_fwd(const AdLds<R>& L, int nt_rt, int kx_rt)
 {
+    const int nt = NTC > 0 ? NTC : nt_rt, kx = NTC > 0 ? NTC / 2 + 1 : kx_rt;
     for (int o = threadIdx.x; o < nt * kx; o += WGS) {
         const int iy = o / kx, q = o - iy * kx;
         const R* row = L.P + iy * nt;
         R sr = R(0), si = R(0);
         int t = 0;
+#pragma unroll(NTC > 0 ? NTC : 1)
         for (int ix = 0; ix < nt; ++ix) {
             const R v = row[ix];
             sr += v * L.tc[t];
@@ -126,13 +128,15 @@ __device__ inline void dft_rows_fwd(const AdLds<R>& L, int nt, int kx)
 }
 
 // forward transform along y: Z[ky][q] = sum_iy Y[iy][q] exp(-2 pi i ky iy / nt)
-template <class R, int WGS>
-__device__ inline void dft_cols_fwd(const AdLds<R>& L, int nt, int kx)
+template <class R, int WGS, int NTC>
+__device__ inline void dft_cols_fwd(const AdLds<R>& L, int nt_rt, int kx_rt)
 {
+    const int nt = NTC > 0 ? NTC : nt_rt, kx = NTC > 0 ? NTC / 2 + 1 : kx_rt;
     for (int o = threadIdx.x; o < nt * kx; o += WGS) {
         const int ky = o / kx, q = o - ky * kx;
         R sr = R(0), si = R(0);
         int t = 0;
+#pragma unroll(NTC > 0 ? NTC : 1)
         for (int iy = 0; iy < nt; ++iy) {
             const R yr = L.Yr[iy * kx + q], yi = L.Yi[iy * kx + q];
             const R c = L.tc[t], s = L.ts[t];
@@ -147,13 +151,15 @@ __device__ inline void dft_cols_fwd(const AdLds<R>& L, int nt, int kx)
 }
 
 // inverse transform along y: Y[iy][q] = sum_ky Z[ky][q] exp(+2 pi i ky iy / nt)
-template <class R, int WGS>
-__device__ inline void dft_cols_inv(const AdLds<R>& L, int nt, int kx)
+template <class R, int WGS, int NTC>
+__device__ inline void dft_cols_inv(const AdLds<R>& L, int nt_rt, int kx_rt)
 {
+    const int nt = NTC > 0 ? NTC : nt_rt, kx = NTC > 0 ? NTC / 2 + 1 : kx_rt;
     for (int o = threadIdx.x; o < nt * kx; o += WGS) {
         const int iy = o / kx, q = o - iy * kx;
         R sr = R(0), si = R(0);
         int t = 0;
+#pragma unroll(NTC > 0 ? NTC : 1)
         for (int ky = 0; ky < nt; ++ky) {
             const R zr = L.Zr[ky * kx + q], zi = L.Zi[ky * kx + q];
             const R c = L.tc[t], s = L.ts[t];
@@ -170,9 +176,10 @@ __device__ inline void dft_cols_inv(const AdLds<R>& L, int nt, int kx)
 // inverse transform along x back to the real field, with the 1/nt^2 of the
 // inverse: P[iy][ix] = scale sum_q w_q Re(Y[iy][q] exp(+2 pi i q ix / nt)),
 // w_q = 1 for q = 0 and (even nt) q = nt/2, else 2 (the conjugate half)
-template <class R, int WGS>
-__device__ inline void dft_rows_inv(const AdLds<R>& L, int nt, int kx, R scale)
+template <class R, int WGS, int NTC>
+__device__ inline void dft_rows_inv(const AdLds<R>& L, int nt_rt, int kx_rt, R scale)
 {
+    const int nt = NTC > 0 ? NTC : nt_rt, kx = NTC > 0 ? NTC / 2 + 1 : kx_rt;
     for (int o = threadIdx.x; o < nt * nt; o += WGS) {
         const int iy = o / nt, ix = o - iy * nt;
         const R* yr = L.Yr + iy * kx;
@@ -180,6 +187,7 @@ __device__ inline void dft_rows_inv(const AdLds<R>& L, int nt, int kx, R scale)
         R s = yr[0];
         int t = ix;
         if (t >= nt) t -= nt;
+#pragma unroll(NTC > 0 ? NTC / 2 : 1)
         for (int q = 1; q < kx; ++q) {
             const R w = 2 * q == nt ? R(1) : R(2);
             s += w * (yr[q] * L.tc[t] - yi[q] * L.ts[t]);
@@ -194,11 +202,14 @@ __device__ inline void dft_rows_inv(const AdLds<R>& L, int nt, int kx, R scale)
 // synchronised): M steps of size h, BDF of order `korder` with the restart
 // ramp, or with the SDIRK start-up when `sd`.  Leaves x_M in L.P; with LTE,
 // gq receives the innovation variance at the thread's point quads.
-template <class R, class S, bool LTE>
-__device__ void ad_propagate(const AdLds<R>& L, int nt, const double (&th)[AD_P], double h_d, int M, int korder,
+template <class R, class S, bool LTE, int NTC>
+__device__ void ad_propagate(const AdLds<R>& L, int nt_rt, const double (&th)[AD_P], double h_d, int M, int korder,
                              bool sd, R (&gq)[S::QPT][4])
 {
+    const int nt = NTC > 0 ? NTC : nt_rt;
     const int kx = nt / 2 + 1, hm = nt * kx, d = nt * nt;
+    // modes per thread: from the grid side when it is known at compile time
+    constexpr int MPT = NTC > 0 ? (NTC * (NTC / 2 + 1) + S::WGS - 1) / S::WGS : S::MPT;
     const int tid = threadIdx.x;
     const R h = (R)h_d;
     const R scale = R(1) / (R)(nt * nt);
@@ -208,15 +219,15 @@ __device__ void ad_propagate(const AdLds<R>& L, int nt, const double (&th)[AD_P]
 #pragma unroll
             for (int s = 0; s < 4; ++s) gq[v][s] = R(0);
     }
-    dft_rows_fwd<R, S::WGS>(L, nt, kx);
+    dft_rows_fwd<R, S::WGS, NTC>(L, nt, kx);
     __syncthreads();
-    dft_cols_fwd<R, S::WGS>(L, nt, kx);
+    dft_cols_fwd<R, S::WGS, NTC>(L, nt, kx);
     __syncthreads();
     // the thread's modes: eigenvalue and history x_{m-1} .. x_{m-4}
     const R k1 = (R)th[0], k2 = (R)th[1], k3 = (R)th[2], c1 = (R)th[3], c2 = (R)th[4];
-    Cx<R> lam[S::MPT], h0[S::MPT], h1[S::MPT], h2[S::MPT], h3[S::MPT];
+    Cx<R> lam[MPT], h0[MPT], h1[MPT], h2[MPT], h3[MPT];
 #pragma unroll
-    for (int u = 0; u < S::MPT; ++u) {
+    for (int u = 0; u < MPT; ++u) {
         const int j = tid + S::WGS * u;
         const int jj = j < hm ? j : 0;
         const int ky = jj / kx, q = jj - ky * kx;
@@ -236,7 +247,7 @@ __device__ void ad_propagate(const AdLds<R>& L, int nt, const double (&th)[AD_P]
         const R c = h * (R)co.beta;
         const bool start = sd && korder >= 2 && avail < korder - 1;
 #pragma unroll
-        for (int u = 0; u < S::MPT; ++u) {
+        for (int u = 0; u < MPT; ++u) {
             const Cx<R> one = cx(R(1), R(0));
             const Cx<R> inv = cinv(one - c * lam[u]);
             Cx<R> xn;
@@ -285,9 +296,9 @@ __device__ void ad_propagate(const AdLds<R>& L, int nt, const double (&th)[AD_P]
         avail = avail < 3 ? avail + 1 : 3;
         if constexpr (LTE) {
             __syncthreads();
-            dft_cols_inv<R, S::WGS>(L, nt, kx);
+            dft_cols_inv<R, S::WGS, NTC>(L, nt, kx);
             __syncthreads();
-            dft_rows_inv<R, S::WGS>(L, nt, kx, scale);
+            dft_rows_inv<R, S::WGS, NTC>(L, nt, kx, scale);
             __syncthreads();
 #pragma unroll
             for (int v = 0; v < S::QPT; ++v)
@@ -303,7 +314,7 @@ __device__ void ad_propagate(const AdLds<R>& L, int nt, const double (&th)[AD_P]
     }
     // x_M back on the grid
 #pragma unroll
-    for (int u = 0; u < S::MPT; ++u) {
+    for (int u = 0; u < MPT; ++u) {
         const int j = tid + S::WGS * u;
         if (j < hm) {
             L.Zr[j] = h0[u].re;
@@ -311,9 +322,9 @@ __device__ void ad_propagate(const AdLds<R>& L, int nt, const double (&th)[AD_P]
         }
     }
     __syncthreads();
-    dft_cols_inv<R, S::WGS>(L, nt, kx);
+    dft_cols_inv<R, S::WGS, NTC>(L, nt, kx);
     __syncthreads();
-    dft_rows_inv<R, S::WGS>(L, nt, kx, scale);
+    dft_rows_inv<R, S::WGS, NTC>(L, nt, kx, scale);
     __syncthreads();
 }
 
@@ -374,7 +385,7 @@ __global__ __launch_bounds__(TILE) void k_ad_init(int slot, const FilterDesc* de
 // steps 2 and 3(a): shrink, predictor, first-stage log-weights (one
 // workgroup per particle), then the tile partials of the first stage
 // ---------------------------------------------------------------------------
-template <class R, class S>
+template <class R, class S, int NTC>
 __global__ __launch_bounds__(S::WGS) void k_ad_predict(StepRec rec, int slot, const FilterDesc* descs,
                                                        FilterState* states)
 {
@@ -382,7 +393,7 @@ __global__ __launch_bounds__(S::WGS) void k_ad_predict(StepRec rec, int slot, co
     const FilterDesc& fd = descs[slot];
     const FilterState& st = states[slot];
     if (!step_valid(rec, st)) return;
-    const int nt = fd.nt, d = fd.d;
+    const int nt = NTC > 0 ? NTC : fd.nt, d = nt * nt;
     const AdLds<R> L = ad_lds<R>((R*)ad_smem, nt);
     const double h = (rec.t_next - st.t) / fd.substeps;
     const int cur = st.cur;
@@ -396,7 +407,7 @@ __global__ __launch_bounds__(S::WGS) void k_ad_predict(StepRec rec, int slot, co
         for (int i = 0; i < AD_P; ++i)
             m[i] = fd.a * fd.theta[cur][(size_t)i * fd.npad + n] + (1.0 - fd.a) * st.theta_bar[i];
         __syncthreads();
-        ad_propagate<R, S, false>(L, nt, m, h, fd.substeps, fd.order, fd.lmm == 2, gq);
+        ad_propagate<R, S, false, NTC>(L, nt, m, h, fd.substeps, fd.order, fd.lmm == 2, gq);
         if (threadIdx.x < WAVE) {
             const double lb = ad_loglik<R>(L.P, fd, rec);
             if (threadIdx.x == 0) {
@@ -438,7 +449,7 @@ __global__ __launch_bounds__(TILE) void k_ad_part1(StepRec rec, int slot, const 
 // ---------------------------------------------------------------------------
 // steps 3(c), 4, 5: one workgroup per output slot
 // ---------------------------------------------------------------------------
-template <class R, class S>
+template <class R, class S, int NTC>
 __global__ __launch_bounds__(S::WGS) void k_ad_update(StepRec rec, int slot, const FilterDesc* descs,
                                                       FilterState* states)
 {
@@ -446,7 +457,7 @@ __global__ __launch_bounds__(S::WGS) void k_ad_update(StepRec rec, int slot, con
     const FilterDesc& fd = descs[slot];
     const FilterState& st = states[slot];
     if (!step_valid(rec, st) || st.T == 0) return;
-    const int nt = fd.nt, d = fd.d;
+    const int nt = NTC > 0 ? NTC : fd.nt, d = nt * nt;
     const AdLds<R> L = ad_lds<R>((R*)ad_smem, nt);
     const double h = (rec.t_next - st.t) / fd.substeps;
     const uint64_t step = st.j + 1;
@@ -483,7 +494,7 @@ __global__ __launch_bounds__(S::WGS) void k_ad_update(StepRec rec, int slot, con
         const double lb = fd.lbar[k];
         __syncthreads();
         // 4(b)-(d): Psi with the local-error variance, then the innovation
-        ad_propagate<R, S, true>(L, nt, th, h, fd.substeps, fd.order, fd.lmm == 2, gq);
+        ad_propagate<R, S, true, NTC>(L, nt, th, h, fd.substeps, fd.order, fd.lmm == 2, gq);
         R* xo = (R*)fd.x[nxt] + (size_t)n * d;
 #pragma unroll
         for (int v = 0; v < S::QPT; ++v) {
@@ -611,14 +622,14 @@ __device__ inline void ad_state_mean(const FilterDesc& fd, double* sh)
 // ---------------------------------------------------------------------------
 // test-only: Psi for n particles, x_in / x_out / gamma [d][n], theta [p][n]
 // ---------------------------------------------------------------------------
-template <class R, class S, bool LTE>
+template <class R, class S, bool LTE, int NTC>
 __global__ __launch_bounds__(S::WGS) void k_ad_test_propagate(const FilterDesc* fdp, uint64_t n, const double* xin,
                                                               const double* theta, double h, double* xout,
                                                               double* gamma, unsigned long long* iters_out)
 {
     extern __shared__ double ad_smem[];
     const FilterDesc& fd = *fdp;
-    const int nt = fd.nt, d = fd.d;
+    const int nt = NTC > 0 ? NTC : fd.nt, d = nt * nt;
     const AdLds<R> L = ad_lds<R>((R*)ad_smem, nt);
     const int tid = threadIdx.x;
     ad_twiddles<R, S::WGS>(L, nt);
@@ -629,7 +640,7 @@ __global__ __launch_bounds__(S::WGS) void k_ad_test_propagate(const FilterDesc* 
 #pragma unroll
         for (int i = 0; i < AD_P; ++i) th[i] = theta[(size_t)i * n + p];
         __syncthreads();
-        ad_propagate<R, S, LTE>(L, nt, th, h, fd.substeps, fd.order, fd.lmm == 2, gq);
+        ad_propagate<R, S, LTE, NTC>(L, nt, th, h, fd.substeps, fd.order, fd.lmm == 2, gq);
         for (int i = tid; i < d; i += S::WGS) xout[(size_t)i * n + p] = (double)L.P[i];
         if (LTE && gamma) {
 #pragma unroll

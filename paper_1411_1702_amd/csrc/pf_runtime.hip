@@ -255,15 +255,22 @@ static AdKernels ad_kernels(const FilterDesc& d)
 {
     AdKernels k;
     const bool f32 = d.prec == PREC_FP32, small = d.nt <= AdSmall::NTB;
-    if (small) {
-        k.predict = f32 ? k_ad_predict<float, AdSmall> : k_ad_predict<double, AdSmall>;
-        k.update = f32 ? k_ad_update<float, AdSmall> : k_ad_update<double, AdSmall>;
-        k.wgs = AdSmall::WGS;
+    // the grid sides of Sec. 4 (n = 20, 40) have their own instances with the
+    // transform loops unrolled; other sides run the generic ones
+    if (small && d.nt == 19) {
+        k.predict = f32 ? k_ad_predict<float, AdSmall, 19> : k_ad_predict<double, AdSmall, 19>;
+        k.update = f32 ? k_ad_update<float, AdSmall, 19> : k_ad_update<double, AdSmall, 19>;
+    } else if (small) {
+        k.predict = f32 ? k_ad_predict<float, AdSmall, 0> : k_ad_predict<double, AdSmall, 0>;
+        k.update = f32 ? k_ad_update<float, AdSmall, 0> : k_ad_update<double, AdSmall, 0>;
+    } else if (d.nt == 39) {
+        k.predict = f32 ? k_ad_predict<float, AdLarge, 39> : k_ad_predict<double, AdLarge, 39>;
+        k.update = f32 ? k_ad_update<float, AdLarge, 39> : k_ad_update<double, AdLarge, 39>;
     } else {
-        k.predict = f32 ? k_ad_predict<float, AdLarge> : k_ad_predict<double, AdLarge>;
-        k.update = f32 ? k_ad_update<float, AdLarge> : k_ad_update<double, AdLarge>;
-        k.wgs = AdLarge::WGS;
+        k.predict = f32 ? k_ad_predict<float, AdLarge, 0> : k_ad_predict<double, AdLarge, 0>;
+        k.update = f32 ? k_ad_update<float, AdLarge, 0> : k_ad_update<double, AdLarge, 0>;
     }
+    k.wgs = small ? AdSmall::WGS : AdLarge::WGS;
     k.part1 = k_ad_part1;
     k.part2 = f32 ? k_ad_part2<float> : k_ad_part2<double>;
     k.lds = ad_lds_bytes(d.nt, f32 ? 4 : 8);
@@ -1099,12 +1106,18 @@ extern "C" pf_status pf_test_propagate(const pf_config* cfg, uint64_t n, const d
     if (d.model == MODEL_ADVDIFF) {
         const bool small = d.nt <= AdSmall::NTB;
         PropKernel ka;
-        if (small)
-            ka = f32 ? (lte ? k_ad_test_propagate<float, AdSmall, true> : k_ad_test_propagate<float, AdSmall, false>)
-                     : (lte ? k_ad_test_propagate<double, AdSmall, true> : k_ad_test_propagate<double, AdSmall, false>);
+        if (small && d.nt == 19)
+            ka = f32 ? (lte ? k_ad_test_propagate<float, AdSmall, true, 19> : k_ad_test_propagate<float, AdSmall, false, 19>)
+                     : (lte ? k_ad_test_propagate<double, AdSmall, true, 19> : k_ad_test_propagate<double, AdSmall, false, 19>);
+        else if (small)
+            ka = f32 ? (lte ? k_ad_test_propagate<float, AdSmall, true, 0> : k_ad_test_propagate<float, AdSmall, false, 0>)
+                     : (lte ? k_ad_test_propagate<double, AdSmall, true, 0> : k_ad_test_propagate<double, AdSmall, false, 0>);
+        else if (d.nt == 39)
+            ka = f32 ? (lte ? k_ad_test_propagate<float, AdLarge, true, 39> : k_ad_test_propagate<float, AdLarge, false, 39>)
+                     : (lte ? k_ad_test_propagate<double, AdLarge, true, 39> : k_ad_test_propagate<double, AdLarge, false, 39>);
         else
-            ka = f32 ? (lte ? k_ad_test_propagate<float, AdLarge, true> : k_ad_test_propagate<float, AdLarge, false>)
-                     : (lte ? k_ad_test_propagate<double, AdLarge, true> : k_ad_test_propagate<double, AdLarge, false>);
+            ka = f32 ? (lte ? k_ad_test_propagate<float, AdLarge, true, 0> : k_ad_test_propagate<float, AdLarge, false, 0>)
+                     : (lte ? k_ad_test_propagate<double, AdLarge, true, 0> : k_ad_test_propagate<double, AdLarge, false, 0>);
         if (e == hipSuccess) {
             hipLaunchKernelGGL(ka, dim3((unsigned)std::min<uint64_t>(n, 65535)), dim3(small ? AdSmall::WGS : AdLarge::WGS),
                                ad_lds_bytes(d.nt, f32 ? 4 : 8), st, dd, n, x_in, theta, h, x_out, lte ? gamma : nullptr,
