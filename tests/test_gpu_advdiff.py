@@ -228,3 +228,33 @@ def test_batched_equals_alone(pf, ctx):
         assert np.array_equal(a["mean"], b["mean"]) and np.array_equal(a["cov"], b["cov"])
         assert np.array_equal(a["state_mean"], b["state_mean"])
         f.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("n", [4, 23, 24, 26])
+def test_propagate_generic_grid_sides(pf, oracle, prec, n):
+    # the generic instances (grid side not a compile-time constant): the
+    # smallest grid (3 x 3), the one-wavefront shape at its limit (22 x 22),
+    # and the four-wavefront shape below 39 (23 x 23, 25 x 25)
+    prob, x, th = _inputs(n, 8 if n < 24 else 4, seed=n)
+    xg, gg, _ = _propagate_gpu(pf, prob, prec, x, th, 0.1, True)
+    xo, go = _propagate_oracle(oracle, prob, x, th, 0.1, True)
+    _check_prop(xg, gg, xo, go, prec, True, ("generic", n))
+
+
+@pytest.mark.parametrize("N,sites,lmm,order", [(257, 20, 0, 2), (1013, 32, 0, 2), (700, 20, 2, 3)])
+def test_step_ragged_max_sites_startup(pf, ctx, oracle, N, sites, lmm, order):
+    # a ragged last tile, the largest number of observed sites, and BDF3 with
+    # the SDIRK start-up, through a whole FP64 step
+    prob = inputs.advdiff(N, 3, seed=5, n=8, sites=sites)
+    prob.lmm, prob.order = lmm, order
+    ora, out, anc_o, anc_g, x, th, lw, post = _step_case(pf, ctx, oracle, prob, 0, 1)
+    assert np.array_equal(anc_o, anc_g)
+    ex = (np.abs(x - ora.x).max(axis=1) / np.abs(ora.x).max(axis=1)).max()
+    assert ex < 1e-10, ex
+    fin = np.isfinite(ora.logw)
+    assert np.allclose(lw[fin], ora.logw[fin], rtol=0, atol=1e-8)
+    mean, cov = ora.moments()
+    assert np.allclose(post["mean"], mean, rtol=1e-10, atol=1e-12)
+    assert np.allclose(post["cov"], cov, rtol=1e-7, atol=1e-12)
+    assert np.allclose(post["state_mean"], out["state_mean"], rtol=1e-9, atol=1e-12)
