@@ -122,12 +122,29 @@ typedef struct {
 } pf_config;
 
 /*
+ * Caller-provided device memory for a context's pool: alloc(user, bytes,
+ * stream) returns device memory of at least `bytes` bytes on the context's
+ * device, aligned to 256 bytes (NULL on failure); free(user, p, stream)
+ * returns it.  `stream` is the context's hipStream_t.  The library calls
+ * alloc once in pf_context_create and free once in pf_context_destroy.
+ */
+typedef struct {
+    void* (*alloc)(void* user, uint64_t bytes, void* stream);
+    void (*free)(void* user, void* p, void* stream);
+    void* user;
+} pf_allocator;
+
+/*
  * Context: one device, one HIP stream, a device memory pool of pool_bytes
  * (0 = 1/4 of free device memory) from which every filter's ensemble is
- * carved.  hip_stream: a hipStream_t to submit on (NULL: the context creates
- * its own).
+ * carved.  alloc: where the pool comes from (NULL, or alloc->alloc == NULL:
+ * hipMalloc); the allocator is copied.  hip_stream: a hipStream_t to submit
+ * on (NULL: the context creates its own).  PF_ENOMEM if the pool cannot be
+ * allocated, PF_EINVAL for an allocator with only one of its functions or a
+ * pool not aligned to 256 bytes.
  */
-pf_status pf_context_create(int device, uint64_t pool_bytes, void* hip_stream, pf_context** out);
+pf_status pf_context_create(int device, uint64_t pool_bytes, const pf_allocator* alloc, void* hip_stream,
+                            pf_context** out);
 void pf_context_destroy(pf_context* ctx);
 
 /* Bytes of pool memory one filter with this configuration needs. */
@@ -139,8 +156,9 @@ pf_status pf_context_memory(pf_context* ctx, uint64_t* used, uint64_t* capacity)
 /*
  * Algorithm 1, step 1: draw the ensemble from the prior (theta = mean + sd z,
  * x = x0, w = 1/N) and compute the parameter mean, covariance and Cholesky
- * factor.  Returns PF_ENOMEM when the pool cannot hold the ensemble.
- * Synchronous.
+ * factor.  Returns PF_ENOMEM when the ensemble is larger than the whole pool,
+ * PF_EADMIT when the pool (or the context's table of 4096 filters) is full
+ * now: try again after a filter is destroyed.  Synchronous.
  */
 pf_status pf_create(pf_context* ctx, const pf_config* cfg, pf_filter** out);
 

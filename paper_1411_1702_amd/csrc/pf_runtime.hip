@@ -166,6 +166,7 @@ struct pf_context {
     Stage stage[NSTAGE];
     int stage_next = 0;
     int grid_cap = 2048;
+    pf_allocator alloc{};        // caller's allocator of the pool (alloc == NULL: hipMalloc)
     std::mutex mu;
 };
 
@@ -436,7 +437,8 @@ static void bind_buffers(FilterDesc& d, char* base, const Layout& L)
 // ---------------------------------------------------------------------------
 // context
 // ---------------------------------------------------------------------------
-extern "C" pf_status pf_context_create(int device, uint64_t pool_bytes, void* hip_stream, pf_context** out)
+extern "C" pf_status pf_context_create(int device, uint64_t pool_bytes, const pf_allocator* alloc,
+                                       void* hip_stream, pf_context** out)
 {
     if (!out) return fail(PF_EINVAL, "out is NULL");
     *out = nullptr;
@@ -460,7 +462,19 @@ extern "C" pf_status pf_context_create(int device, uint64_t pool_bytes, void* hi
     }
     pool_bytes = Pool::align(pool_bytes);
     void* p = nullptr;
-    if (hipMalloc(&p, pool_bytes) != hipSuccess) return fail(PF_ENOMEM, "cannot allocate the device pool");
+    if (alloc && (alloc->alloc || alloc->free) && !(alloc->alloc && alloc->free))
+        return fail(PF_EINVAL, "allocator needs both alloc and free");
+    if (alloc && alloc->alloc) {
+        ctx->alloc = *alloc;
+        p = alloc->alloc(alloc->user, pool_bytes, (void*)ctx->stream);
+        if (!p) return fail(PF_ENOMEM, "the caller's allocator returned no pool");
+        if (((uintptr_t)p & 255) != 0) {
+            alloc->free(alloc->user, p, (void*)ctx->stream);
+            return fail(PF_EINVAL, "the caller's allocator returned a pool not aligned to 256 bytes");
+        }
+    } else if (hipMalloc(&p, pool_bytes) != hipSuccess) {
+        return fail(PF_ENOMEM, "cannot allocate the device pool");
+    }
     ctx->pool.base = (char*)p;
     ctx->pool.cap = pool_bytes;
     ctx->pool.free_[0] = pool_bytes;
@@ -506,7 +520,8 @@ extern "C" void pf_context_destroy(pf_context* ctx)
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     (void)hipFree(ctx->d_desc);
     (void)hipFree(ctx->d_state);
-    (void)hipFree(ctx->pool.base);
+    if (ctx->alloc.alloc) ctx->alloc.free(ctx->alloc.user, ctx->pool.base, (void*)ctx->stream);
+    else (void)hipFree(ctx->pool.base);
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
     (void)hipStreamDestroy(ctx->init_stream);
     delete ctx;
@@ -552,9 +567,10 @@ extern "C" pf_status pf_create(pf_context* ctx, const pf_config* cfg, pf_filter*
         int slot = -1;
         for (int i = 0; i < MAX_SLOTS; ++i)
             if (!ctx->slot_used[i]) { slot = i; break; }
-        if (slot < 0) return fail(PF_ENOMEM, "filter table full");
+        if (Pool::align(L.total) > ctx->pool.cap) return fail(PF_ENOMEM, "filter larger than the device pool");
+        if (slot < 0) return fail(PF_EADMIT, "filter table full");
         uint64_t off = 0;
-        if (!ctx->pool.alloc(L.total, &off)) return fail(PF_ENOMEM, "device pool exhausted");
+        if (!ctx->pool.alloc(L.total, &off)) return fail(PF_EADMIT, "device pool full now");
         ctx->slot_used[slot] = 1;
         f->slot = slot;
         f->pool_off = off;

@@ -162,7 +162,7 @@ bool pf_server::admit_locked()
         }
         pf_filter* f = nullptr;
         const pf_status st = pf_create(ctx, &s->conf.cfg, &f);
-        if (st == PF_ENOMEM) break;   // head of line waits for memory
+        if (st == PF_EADMIT) break;   // head of line waits for memory
         admit_queue.pop_front();
         progress = true;
         if (st != PF_OK) {

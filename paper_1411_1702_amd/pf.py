@@ -40,6 +40,14 @@ class PfError(RuntimeError):
         self.status = status
 
 
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+class pf_allocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", C.c_void_p)]
+
+
 class pf_config(C.Structure):
     _fields_ = [
         ("struct_size", C.c_uint32), ("model", C.c_int), ("d", C.c_uint32), ("p", C.c_uint32),
@@ -80,7 +88,7 @@ def lib():
             raise ImportError(f"HIP library not built: {LIB_PATH} (run paper_1411_1702_amd/build.py)")
         L = C.CDLL(LIB_PATH)
         vp, dp, u64 = C.c_void_p, C.POINTER(C.c_double), C.c_uint64
-        L.pf_context_create.argtypes = [C.c_int, u64, vp, C.POINTER(vp)]
+        L.pf_context_create.argtypes = [C.c_int, u64, C.POINTER(pf_allocator), vp, C.POINTER(vp)]
         L.pf_context_destroy.argtypes = [vp]
         L.pf_context_destroy.restype = None
         L.pf_filter_bytes.argtypes = [C.POINTER(pf_config)]
@@ -179,9 +187,18 @@ class Config:
 
 
 class Context:
-    def __init__(self, device=0, pool_bytes=0, stream=None):
+    def __init__(self, device=0, pool_bytes=0, stream=None, allocator=None):
+        """allocator: optional (alloc(bytes, stream) -> device pointer, free(ptr, stream))
+        pair of Python callables that provide the context's device pool."""
         h = C.c_void_p()
-        check(lib().pf_context_create(device, int(pool_bytes), stream, C.byref(h)), "pf_context_create")
+        self._alloc = None
+        if allocator is not None:
+            fa, ff = allocator
+            # the ctypes callbacks must outlive the context
+            self._alloc = pf_allocator(ALLOC_FN(lambda user, n, st: fa(int(n), st)),
+                                       FREE_FN(lambda user, p, st: ff(p, st)), None)
+        check(lib().pf_context_create(device, int(pool_bytes), C.byref(self._alloc) if self._alloc else None,
+                                      stream, C.byref(h)), "pf_context_create")
         self.h = h
 
     def memory(self):

@@ -40,6 +40,14 @@ def test_config_struct_layout():
     assert hdr == names
 
 
+def test_allocator_struct_layout():
+    txt = open(os.path.join(ROOT, "include", "pf.h")).read()
+    body = txt[txt.index("typedef struct {\n    void* (*alloc)"):txt.index("} pf_allocator;")]
+    hdr = re.findall(r"\(\*(\w+)\)|void\* (\w+);", body)
+    names = [a or b for a, b in hdr]
+    assert names == [f[0] for f in pf.pf_allocator._fields_] == ["alloc", "free", "user"]
+
+
 def test_status_strings():
     L = pf.lib()
     for s in range(9):

@@ -183,3 +183,50 @@ def test_error_paths(pf):
         assert 0 < used <= cap
         small.close()
         assert ctx.memory()[0] == 0
+
+
+def test_pool_full_now_is_admit_not_enomem(pf):
+    # a pool that holds one filter: the second is refused with PF_EADMIT
+    # (retry later) and admitted once the first is destroyed
+    cfg = pf.Config(inputs.robertson(5000, 4, seed=1))
+    need = pf.lib().pf_filter_bytes(cfg.ptr())
+    with _ctx(pf, True, pool=need + 4096) as ctx:
+        f1 = pf.Filter(ctx, cfg)
+        with pytest.raises(pf.PfError) as e:
+            pf.Filter(ctx, pf.Config(inputs.robertson(5000, 4, seed=2)))
+        assert e.value.status == pf.PF_EADMIT
+        f1.close()
+        f2 = pf.Filter(ctx, pf.Config(inputs.robertson(5000, 4, seed=2)))
+        f2.close()
+
+
+def test_caller_allocator_provides_the_pool(pf):
+    # the pool from the caller's allocator (device memory from torch here):
+    # one alloc at creation, one free at destruction, and the filter's
+    # results are those of a hipMalloc'ed pool, bit for bit
+    prob = inputs.robertson(3000, 4, seed=3)
+    held, calls = {}, []
+
+    def alloc(n, stream):
+        t = torch.empty(n, dtype=torch.uint8, device="cuda")
+        held[t.data_ptr()] = t
+        calls.append(("alloc", n))
+        return t.data_ptr()
+
+    def free(p, stream):
+        calls.append(("free", p))
+        held.pop(p)
+
+    posts = []
+    for a in (None, (alloc, free)):
+        with pf.Context(0, 64 << 20, allocator=a) as ctx:
+            f = pf.Filter(ctx, pf.Config(prob))
+            for j in range(prob.T):
+                assert f.assimilate(prob.times[j], prob.y[j], prob.sigma[j]) == pf.PF_OK
+            posts.append(f.posterior())
+            f.close()
+            if a is not None:
+                assert calls == [("alloc", 64 << 20)]
+    assert [c[0] for c in calls] == ["alloc", "free"] and not held
+    for k in ("mean", "cov", "state_mean"):
+        assert np.array_equal(posts[0][k], posts[1][k])
