@@ -55,6 +55,18 @@ pf_status pf_test_resample(uint64_t n, const double* g, uint64_t r, int32_t* anc
 pf_status pf_test_resample_multinomial(uint64_t n, const double* g, uint64_t seed, uint64_t step,
                                        int32_t* anc, void* hip_stream);
 
+/* Algorithm 1 step 6 on given particles, through the filter's own tile
+ * partials and moment pass: the mean, covariance (row-major) and Cholesky
+ * factor (row-major, lower; with the jitter rule: C + delta I, delta =
+ * 1e-10 tr(C)/p, times 10 up to five times) of theta [p][n] under the weights
+ * exp(logw) [n] (device doubles; logw need not be normalised, -inf = weight
+ * zero), and the ESS (sum w)^2 / sum w^2.  p is one of the models' parameter
+ * counts: 3, 5 or 12.  mean [p], cov [p*p], chol [p*p], ess: host outputs,
+ * any may be NULL.  PF_EDEGENERATE when every weight is zero or no jitter
+ * makes the covariance factorable.  Synchronous. */
+pf_status pf_test_moments(uint64_t n, uint32_t p, const double* theta, const double* logw, double* mean,
+                          double* cov, double* chol, double* ess, void* hip_stream);
+
 /* The three filter-based calls below run on the context's own stream: each
  * first waits for all work on the device (so buffers the caller produced on
  * any stream are ready) and returns after its own work is done. */

@@ -1277,6 +1277,93 @@ __global__ void k_test_set(const FilterDesc* descs, const FilterState* states, i
 }
 }  // namespace pf
 
+namespace pf {
+// step 6 on given particles: tile partials of theta [p][n] under exp(logw),
+// shift zero (the descriptor's prior mean is zero), then the moment pass
+template <int P>
+__global__ __launch_bounds__(TILE) void k_test_tile_moments(const FilterDesc* fdp, const double* theta,
+                                                           const double* logw)
+{
+    __shared__ double sh[TILE];
+    const FilterDesc& fd = *fdp;
+    for (int tile = blockIdx.x; tile < fd.ntiles; tile += gridDim.x) {
+        const int n = tile * TILE + threadIdx.x;
+        const bool valid = n < fd.n;
+        double th[P];
+#pragma unroll
+        for (int i = 0; i < P; ++i) th[i] = valid ? theta[(size_t)i * fd.n + n] : 0.0;
+        const double l = valid ? logw[n] : -INFINITY;
+        tile_moments<double, P, 0>(l, valid, th, nullptr, fd.prior_mean, 0, nullptr, fd.part2 + tile, fd.ntiles,
+                                   sh);
+    }
+}
+template <int P>
+__global__ __launch_bounds__(TILE) void k_test_moments_finish(const FilterDesc* fdp, FilterState* st)
+{
+    __shared__ double sh[TILE];
+    __shared__ double tot[NACC_MAX];
+    const FilterDesc& fd = *fdp;
+    const MomPre pre = mom_prefetch<P>(*st);
+    moments_combine<P, 0>(fd, tot, sh);
+    const int32_t status = moments_finish<P, 0>(fd, tot, pre, *st, false, pre.t);
+    if (threadIdx.x == 0) st->status = status;
+}
+}  // namespace pf
+
+extern "C" pf_status pf_test_moments(uint64_t n, uint32_t p, const double* theta, const double* logw, double* mean,
+                                     double* cov, double* chol, double* ess, void* hip_stream)
+{
+    if (!theta || !logw) return fail(PF_EINVAL, "NULL buffer");
+    if (n == 0 || n > (1ull << 24)) return fail(PF_EINVAL, "n must be 1..2^24");
+    if (p != 3 && p != 5 && p != 12) return fail(PF_EINVAL, "p must be 3, 5 or 12");
+    hipStream_t st = (hipStream_t)hip_stream;
+    FilterDesc d;
+    std::memset(&d, 0, sizeof(d));
+    d.n = (int)n;
+    d.p = (int)p;
+    d.ntiles = (d.n + TILE - 1) / TILE;
+    d.npad = d.ntiles * TILE;
+    d.nacc = 3 + d.p + d.p * (d.p + 1) / 2 + NPLAIN;
+    char* buf = nullptr;
+    const size_t part_bytes = sizeof(double) * (size_t)d.nacc * d.ntiles;
+    HIP_TRY(hipMalloc(&buf, 512 + sizeof(FilterDesc) + sizeof(FilterState) + part_bytes));
+    FilterDesc* dd = (FilterDesc*)buf;
+    FilterState* ds = (FilterState*)(buf + ((sizeof(FilterDesc) + 255) & ~size_t(255)));
+    d.part2 = (double*)((char*)ds + ((sizeof(FilterState) + 255) & ~size_t(255)));
+    FilterState hs;
+    std::memset(&hs, 0, sizeof(hs));
+    hipError_t e = hipMemcpyAsync(dd, &d, sizeof(d), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(ds, &hs, sizeof(hs), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) {
+        const unsigned g = (unsigned)std::min(d.ntiles, 2048);
+        if (p == 3) {
+            hipLaunchKernelGGL(k_test_tile_moments<3>, dim3(g), dim3(TILE), 0, st, dd, theta, logw);
+            hipLaunchKernelGGL(k_test_moments_finish<3>, dim3(1), dim3(TILE), 0, st, dd, ds);
+        } else if (p == 5) {
+            hipLaunchKernelGGL(k_test_tile_moments<5>, dim3(g), dim3(TILE), 0, st, dd, theta, logw);
+            hipLaunchKernelGGL(k_test_moments_finish<5>, dim3(1), dim3(TILE), 0, st, dd, ds);
+        } else {
+            hipLaunchKernelGGL(k_test_tile_moments<12>, dim3(g), dim3(TILE), 0, st, dd, theta, logw);
+            hipLaunchKernelGGL(k_test_moments_finish<12>, dim3(1), dim3(TILE), 0, st, dd, ds);
+        }
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(&hs, ds, sizeof(hs), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(buf);
+    if (e != hipSuccess) return fail(PF_EDEVICE, std::string("moments: ") + hipGetErrorString(e));
+    if (hs.status != ST_OK) return fail((pf_status)hs.status, "every weight zero or covariance not factorable");
+    for (uint32_t i = 0; i < p; ++i) {
+        if (mean) mean[i] = hs.theta_bar[i];
+        for (uint32_t j = 0; j < p; ++j) {
+            if (cov) cov[i * p + j] = hs.C[i * p + j];
+            if (chol) chol[i * p + j] = hs.L[i * p + j];
+        }
+    }
+    if (ess) *ess = hs.ess;
+    return PF_OK;
+}
+
 // The filter-based test entry points run on the context's own stream, which
 // does not wait for the caller's streams: they first wait for the whole
 // device, so the caller's buffers are ready (e.g. still being cleared on

@@ -30,7 +30,7 @@ EXPORTS = [
     "pf_server_create", "pf_server_open", "pf_server_submit", "pf_server_poll", "pf_server_posterior",
     "pf_server_close", "pf_server_drain", "pf_server_stats", "pf_server_destroy",
     "pf_test_philox", "pf_test_normals", "pf_test_propagate", "pf_test_resample", "pf_test_resample_multinomial",
-    "pf_test_get_ensemble", "pf_test_set_ensemble", "pf_test_last_ancestors",
+    "pf_test_get_ensemble", "pf_test_set_ensemble", "pf_test_last_ancestors", "pf_test_moments",
 ]
 
 
@@ -114,6 +114,7 @@ def lib():
                                         vp, vp]
         L.pf_test_resample.argtypes = [u64, vp, u64, vp, vp]
         L.pf_test_resample_multinomial.argtypes = [u64, vp, u64, u64, vp, vp]
+        L.pf_test_moments.argtypes = [u64, C.c_uint32, vp, vp, dp, dp, dp, dp, vp]
         L.pf_test_get_ensemble.argtypes = [vp, vp, vp, vp]
         L.pf_test_set_ensemble.argtypes = [vp, vp, vp, vp, dp, dp, u64, C.c_double]
         L.pf_test_last_ancestors.argtypes = [vp, vp]

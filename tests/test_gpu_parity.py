@@ -226,6 +226,63 @@ def test_propagate_chain(pf, oracle, prec):
         assert err.max() < TOL[prec], (h, err.max())
 
 
+# ---------------------------------------------------------------- moments
+def _moments_gpu(pf, theta, logw):
+    n, p = theta.shape
+    th, lw = dev(theta.T), dev(logw)
+    mean, cov, L = np.zeros(p), np.zeros(p * p), np.zeros(p * p)
+    ess = np.zeros(1)
+    st = pf.lib().pf_test_moments(n, p, th.data_ptr(), lw.data_ptr(), pf._dp(mean), pf._dp(cov), pf._dp(L),
+                                  pf._dp(ess), None)
+    return st, mean, cov.reshape(p, p), L.reshape(p, p), ess[0]
+
+
+@pytest.mark.parametrize("p", [3, 5, 12])
+@pytest.mark.parametrize("n", [1, 300, 4097, 65536 + 7])
+def test_moments_match_oracle(pf, oracle, p, n):
+    rng = np.random.default_rng(p * 1000 + n)
+    theta = rng.standard_normal((n, p)) * rng.uniform(0.1, 3.0, p) + rng.uniform(-5, 5, p)
+    logw = 3.0 * rng.standard_normal(n)
+    logw[rng.uniform(size=n) < 0.1] = -np.inf
+    if n == 1:
+        logw[0] = 0.0
+    st, mean, cov, L, ess = _moments_gpu(pf, theta, logw)
+    w, _ = oracle.normalise(logw)
+    om, oc = oracle.moments(theta, w)
+    if n == 1:
+        # one particle: zero covariance, no jitter makes it factorable
+        assert st == pf.PF_EDEGENERATE
+        return
+    assert st == pf.PF_OK
+    ost, oL, _ = oracle.cholesky(oc)
+    assert ost == 0
+    assert np.allclose(mean, om, rtol=1e-12, atol=1e-12)
+    assert np.allclose(cov, oc, rtol=1e-10, atol=1e-13 * np.abs(oc).max())
+    assert np.allclose(L, oL, rtol=1e-9, atol=1e-12 * np.abs(oL).max())
+    assert ess == pytest.approx(1.0 / np.sum(w * w), rel=1e-10)
+
+
+def test_moments_jitter_and_degenerate(pf, oracle):
+    rng = np.random.default_rng(7)
+    n, p = 2000, 5
+    theta = rng.standard_normal((n, p))
+    theta[:, 3] = theta[:, 1]          # rank deficient: the jitter rule decides
+    logw = rng.standard_normal(n)
+    st, mean, cov, L, ess = _moments_gpu(pf, theta, logw)
+    w, _ = oracle.normalise(logw)
+    om, oc = oracle.moments(theta, w)
+    ost, oL, ojit = oracle.cholesky(oc)
+    assert st == (pf.PF_OK if ost == 0 else pf.PF_EDEGENERATE)
+    if ost == 0:
+        # the factor's column for the dependent direction is rounding noise
+        # over sqrt(delta) on both sides; the product L L^T = C + delta I is
+        # what the jitter rule fixes, and the columns before it are determined
+        assert np.allclose(L @ L.T, oL @ oL.T, rtol=0, atol=1e-8 * np.abs(oc).max())
+        assert np.allclose(L[:, :3], oL[:, :3], rtol=1e-9, atol=1e-12)
+    st, *_ = _moments_gpu(pf, theta, np.full(n, -np.inf))
+    assert st == pf.PF_EDEGENERATE
+
+
 # ---------------------------------------------------------------- resampling
 @pytest.mark.parametrize("N", [1, 7, 256, 257, 1000, 4097, 65536 + 13])
 def test_resample_bitexact(pf, oracle, N):
