@@ -3,6 +3,7 @@
 // Newton solve and local-error estimate (Algorithm 1, steps 2 and 4).
 // One particle per lane; everything here lives in registers.
 #pragma once
+#include <type_traits>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -335,8 +336,14 @@ __device__ inline void integrate(const Model& md, R x[Model::D], R gam[Model::D]
         for (int i = 0; i < D; ++i) gam[i] = R(0);
     }
     int avail = 0;           // history beyond x_{m-1}
-    for (int m = 1; m <= M; ++m) {
-        const int q = avail < 1 ? 1 : (avail < KORD ? avail : KORD);
+    // One step of the order-q formula.  QC > 0: q = QC = KORD is known at
+    // compile time (every step after the ramp: coefficients and predictor are
+    // constants); QC = 0: q from the history available (the ramp, and the
+    // SDIRK start-up when SD).
+    auto step = [&](auto qc) {
+        constexpr int QC = decltype(qc)::value;
+        const int q = QC > 0 ? QC : (avail < 1 ? 1 : (avail < KORD ? avail : KORD));
+        const bool first = QC > 0 ? false : avail == 0;   // m = 1: Euler comparison value
         const BdfCoef co = bdf_coef(q);
         const R c = h * (R)co.beta;
         R psi[D], xp[D], xn[D];
@@ -347,7 +354,7 @@ __device__ inline void integrate(const Model& md, R x[Model::D], R gam[Model::D]
             if (KORD >= 3 && q >= 3) s -= (R)co.a3 * h2[i];
             psi[i] = s;
             R p = x[i];
-            if (avail >= 1) {
+            if (!first) {
                 if (q == 1) p = R(2) * x[i] - h1[i];
                 else if (KORD >= 2 && q == 2) p = R(3) * x[i] - R(3) * h1[i] + h2[i];
                 else if (KORD >= 3) p = R(4) * x[i] - R(6) * h1[i] + R(4) * h2[i] - h3[i];
@@ -356,7 +363,7 @@ __device__ inline void integrate(const Model& md, R x[Model::D], R gam[Model::D]
             xn[i] = p;
         }
         typename Model::LU lu;
-        if constexpr (SD && KORD >= 2) {
+        if constexpr (SD && KORD >= 2 && QC == 0) {
             if (avail < KORD - 1) {
                 // start-up step: the SDIRK stages, x_m the last one
                 const Sdirk tb = sdirk_table<KORD>();
@@ -378,7 +385,7 @@ __device__ inline void integrate(const Model& md, R x[Model::D], R gam[Model::D]
                 if constexpr (LTE) {
                     // the ramp's estimator: comparison value as above (Euler
                     // at m = 1), the ramp order's matrix at x_m
-                    if (avail == 0) {
+                    if (first) {
                         R f0[D];
                         md.rhs(x, f0);
 #pragma unroll
@@ -386,12 +393,12 @@ __device__ inline void integrate(const Model& md, R x[Model::D], R gam[Model::D]
                     }
                     R fm[D];
                     md.eval(y, c, fm, lu);
-                    const R kap = avail == 0 ? R(0.5) : (R)co.kappa;
+                    const R kap = first ? R(0.5) : (R)co.kappa;
                     R e[D];
 #pragma unroll
                     for (int i = 0; i < D; ++i) e[i] = y[i] - xp[i];
                     md.solve(lu, e);
-                    if (avail == 0) md.solve(lu, e);
+                    if (first) md.solve(lu, e);
 #pragma unroll
                     for (int i = 0; i < D; ++i) {
                         const R v = kap * e[i];
@@ -406,7 +413,7 @@ __device__ inline void integrate(const Model& md, R x[Model::D], R gam[Model::D]
                     x[i] = y[i];
                 }
                 avail = avail < KORD ? avail + 1 : KORD;
-                continue;
+                return;
             }
         }
         // one exit (converged or kmax reached), so the loop is a plain
@@ -416,7 +423,7 @@ __device__ inline void integrate(const Model& md, R x[Model::D], R gam[Model::D]
         do {
             R f[D];
             md.eval(xn, c, f, lu);
-            if (LTE && avail == 0 && it == 0) {
+            if (LTE && first && it == 0) {
 #pragma unroll
                 for (int i = 0; i < D; ++i) xp[i] = x[i] + h * f[i];
             }
@@ -435,12 +442,12 @@ __device__ inline void integrate(const Model& md, R x[Model::D], R gam[Model::D]
         iters += (uint32_t)it;
         fails += ok ? 0u : 1u;
         if constexpr (LTE) {
-            const R kap = avail == 0 ? R(0.5) : (R)co.kappa;
+            const R kap = first ? R(0.5) : (R)co.kappa;
             R e[D];
 #pragma unroll
             for (int i = 0; i < D; ++i) e[i] = xn[i] - xp[i];
             md.solve(lu, e);
-            if (avail == 0) md.solve(lu, e);
+            if (first) md.solve(lu, e);
 #pragma unroll
             for (int i = 0; i < D; ++i) {
                 const R v = kap * e[i];
@@ -455,7 +462,10 @@ __device__ inline void integrate(const Model& md, R x[Model::D], R gam[Model::D]
             x[i] = xn[i];
         }
         avail = avail < KORD ? avail + 1 : KORD;
-    }
+    };
+    int m = 1;
+    for (; m <= M && avail < KORD; ++m) step(std::integral_constant<int, 0>{});
+    for (; m <= M; ++m) step(std::integral_constant<int, KORD>{});
 }
 
 // ---------------------------------------------------------------------------
