@@ -81,7 +81,7 @@ def algorithmic_bytes(prob):
 # sources: once they change, the figure no longer applies and bench reports
 # null until the counters are taken again.
 TRAFFIC = {
-    "d26da6bb72b1c3fd": {"fetch_kib": 3427.0, "write_kib": 5936.0, "fetch_scale": 2.0, "write_scale": 1.0},
+    "3964abf24f33e2f1": {"fetch_kib": 3428.0, "write_kib": 5936.0, "fetch_scale": 2.0, "write_scale": 1.0},
 }
 KERNEL_SOURCES = ("pf_kernels.hip", "pf_device.hpp", "pf_types.hpp")
 
@@ -98,7 +98,8 @@ def kernel_source_hash():
 def update_traffic_bytes(prob):
     """Counter-measured HBM bytes per k_update launch, or None when the
     counters were not taken on this workload and these kernel sources."""
-    if prob.model != inputs.MODEL_ROBERTSON or prob.n_particles != 1 << 17:
+    if (prob.model != inputs.MODEL_ROBERTSON or prob.n_particles != 1 << 17 or prob.lmm != 0
+            or prob.order != 2 or prob.substeps != 20 or prob.resampling != 0):
         return None
     t = TRAFFIC.get(kernel_source_hash())
     if t is None:

@@ -509,10 +509,18 @@ __device__ inline void integrate_am(const Model& md, R x[Model::D], R gam[Model:
     }
     md.rhs(x, f0);
     int avail = 0;               // x history beyond x_{m-1}
-    for (int m = 1; m <= M; ++m) {
-        const int q = m < KORD ? m : KORD;
-        const int r0 = q + 1 < avail ? q + 1 : avail;
-        const int r = r0 < 3 ? r0 : 3;
+    // the steady steps (q = KORD, extrapolation degree RS) run with both known
+    // at compile time; the first steps of the interval take them from m
+    constexpr int RS = KORD + 1 < 3 ? KORD + 1 : 3;
+    int m = 1;
+    auto step = [&](auto steady) {
+        constexpr bool ST = decltype(steady)::value;
+        int q = KORD, r = RS;
+        if constexpr (!ST) {
+            q = m < KORD ? m : KORD;
+            const int r0 = q + 1 < avail ? q + 1 : avail;
+            r = r0 < 3 ? r0 : 3;
+        }
         const AmCoef co = am_coef(q);
         const R c = h * (R)co.b0;
         R psi[D], xp[D], xn[D];
@@ -575,7 +583,9 @@ __device__ inline void integrate_am(const Model& md, R x[Model::D], R gam[Model:
         }
         md.rhs(x, f0);
         avail = avail < 3 ? avail + 1 : 3;
-    }
+    };
+    for (; m <= M && !(m >= KORD && avail >= RS); ++m) step(std::false_type{});
+    for (; m <= M; ++m) step(std::true_type{});
 }
 
 // Psi of either LMM family (LMM 0 BDF, 1 Adams-Moulton, 2 BDF with the SDIRK start-up)
