@@ -756,6 +756,21 @@ __device__ inline const FilterDesc& desc_of(const Batch& B, const FilterDesc* de
 // final kernel reports PF_EORDER).
 __device__ inline bool step_valid(const StepRec& r, const FilterState& st) { return r.t_next > st.t; }
 
+// Uniform values loaded together with the ones a branch tests: an empty asm
+// that takes them in scalar registers keeps the compiler from sinking their
+// loads below the branch (a second round trip to memory before the first use).
+template <class T>
+__device__ __forceinline__ void keep_loaded(const T v)
+{
+    asm volatile("" ::"s"(v));
+}
+template <class T, class... U>
+__device__ __forceinline__ void keep_loaded(const T v, const U... rest)
+{
+    keep_loaded(v);
+    keep_loaded(rest...);
+}
+
 // ---------------------------------------------------------------------------
 // step 1: prior draw and initial moment partials
 // ---------------------------------------------------------------------------
@@ -815,7 +830,7 @@ __global__ __launch_bounds__(TILE) void k_init_moments(int slot, const FilterDes
 // steps 2 and 3(a): shrink, predictor, first-stage log-weights
 // ---------------------------------------------------------------------------
 template <class Model, class R, int KORD, int LMM, bool INL>
-__global__ __launch_bounds__(TILE) void k_predict(Batch B, const FilterDesc* descs, FilterState* states)
+__global__ __launch_bounds__(TILE) void k_predict(Batch B, const FilterDesc* __restrict__ descs, FilterState* __restrict__ states)
 {
     constexpr int D = Model::D, P = Model::P;
     __shared__ double sh[TILE];
@@ -825,15 +840,20 @@ __global__ __launch_bounds__(TILE) void k_predict(Batch B, const FilterDesc* des
         const StepRec& rec = itm.rec;
         const FilterDesc& fd = desc_of<INL>(B, descs, itm.slot);
         const FilterState& st = states[itm.slot];
-        if (!step_valid(rec, st)) continue;
-        const double h = (rec.t_next - st.t) / fd.substeps;
+        // the state fields and buffer pointers, loaded before the test waits
+        const double t_cur = st.t;
+        const int cur = st.cur;
+        const R* const xb = (const R*)(cur ? fd.x[1] : fd.x[0]);
+        const double* const tb = cur ? fd.theta[1] : fd.theta[0];
+        const double* const lw = cur ? fd.logw[1] : fd.logw[0];
+        keep_loaded(xb, tb, lw);
+        if (!(rec.t_next > t_cur)) continue;
+        const double h = (rec.t_next - t_cur) / fd.substeps;
         const int n = itm.tile * TILE + threadIdx.x;
         const bool valid = n < fd.n;
-        const int cur = st.cur;
         double lg = -INFINITY;
         uint32_t iters = 0, fails = 0;
         if (valid) {
-            const R* xb = (const R*)fd.x[cur];
             R x[D];
 #pragma unroll
             for (int i = 0; i < D; ++i) x[i] = xb[(size_t)i * fd.npad + n];
@@ -841,14 +861,14 @@ __global__ __launch_bounds__(TILE) void k_predict(Batch B, const FilterDesc* des
             const double a = fd.a;
 #pragma unroll
             for (int i = 0; i < P; ++i)
-                m[i] = a * fd.theta[cur][(size_t)i * fd.npad + n] + (1.0 - a) * st.theta_bar[i];
+                m[i] = a * tb[(size_t)i * fd.npad + n] + (1.0 - a) * st.theta_bar[i];
             Model md;
             md.set_params(m, fd);
             const R* fl = sizeof(R) == 4 ? (const R*)fd.floor_f : (const R*)fd.floor_;
             integrate_lmm<Model, R, KORD, false, LMM>(md, x, nullptr, h, fd.substeps, (R)fd.rtol, fl, fd.kmax,
                                              iters, fails);
             const double lb = loglik<R>(x, fd.obs, rec.y, rec.sigma, fd.m);
-            lg = fd.logw[cur][n] + lb;
+            lg = lw[n] + lb;
             if (!(lg > -INFINITY)) lg = -INFINITY;   // NaN -> zero weight
             fd.lbar[n] = lb;
             fd.lg[n] = lg;
@@ -883,7 +903,7 @@ __global__ __launch_bounds__(TILE) void k_predict(Batch B, const FilterDesc* des
 // step 3(b): systematic resampling in integers
 // ---------------------------------------------------------------------------
 template <bool INL>
-__global__ __launch_bounds__(TILE) void k_count(Batch B, const FilterDesc* descs, FilterState* states)
+__global__ __launch_bounds__(TILE) void k_count(Batch B, const FilterDesc* __restrict__ descs, FilterState* __restrict__ states)
 {
     __shared__ double sh[TILE];
     __shared__ double tot[1];
@@ -1074,7 +1094,7 @@ __global__ __launch_bounds__(TILE) void k_scatter(Batch B, const FilterDesc* des
 // steps 3(c)-5 per output slot
 // ---------------------------------------------------------------------------
 template <class Model, class R, int KORD, int LMM, bool INL>
-__global__ __launch_bounds__(TILE) void k_update(Batch B, const FilterDesc* descs, FilterState* states)
+__global__ __launch_bounds__(TILE) void k_update(Batch B, const FilterDesc* __restrict__ descs, FilterState* __restrict__ states)
 {
     constexpr int D = Model::D, P = Model::P;
     __shared__ double sh[TILE];
@@ -1086,10 +1106,16 @@ __global__ __launch_bounds__(TILE) void k_update(Batch B, const FilterDesc* desc
         const int n = itm.tile * TILE + threadIdx.x;
         const bool valid = n < fd.n;
         const int k_anc = valid ? fd.anc[n] : 0;   // issued before the state checks wait
-        if (!step_valid(rec, st) || st.T == 0) continue;
-        const double h = (rec.t_next - st.t) / fd.substeps;
-        const uint64_t step = st.j + 1;
+        // every state field the step reads, loaded before any test waits on one
+        const double t_cur = st.t;
+        const uint64_t T_cur = st.T, j_cur = st.j;
         const int cur = st.cur, nxt = cur ^ 1;
+        const R* const xb = (const R*)(cur ? fd.x[1] : fd.x[0]);
+        const double* const tb = cur ? fd.theta[1] : fd.theta[0];
+        keep_loaded(j_cur, cur, xb, tb);
+        if (!(rec.t_next > t_cur) || T_cur == 0) continue;
+        const double h = (rec.t_next - t_cur) / fd.substeps;
+        const uint64_t step = j_cur + 1;
         double l = -INFINITY;
         double th[P];
         R x[D];
@@ -1106,18 +1132,22 @@ __global__ __launch_bounds__(TILE) void k_update(Batch B, const FilterDesc* desc
             if (bad) k = 0;
             // 3(c): the slot takes its ancestor's x_j, shrunk parameters and
             // predictor likelihood
-            const R* xb = (const R*)fd.x[cur];
 #pragma unroll
             for (int i = 0; i < D; ++i) x[i] = xb[(size_t)i * fd.npad + k];
-            const double a = fd.a;
-            double m[P];
+            double ta[P];
 #pragma unroll
-            for (int i = 0; i < P; ++i)
-                m[i] = a * fd.theta[cur][(size_t)i * fd.npad + k] + (1.0 - a) * st.theta_bar[i];
+            for (int i = 0; i < P; ++i) ta[i] = tb[(size_t)i * fd.npad + k];
             const double lb = fd.lbar[k];
+            // the ancestor's loads are in flight while the normals are drawn:
+            // keep the scheduler from sinking them below the generator
+            __builtin_amdgcn_sched_barrier(0);
             // 4(a): theta_{j+1} = m + s L z (normals in the propagation precision)
             R z[P];
             normals<P, R>(fd.seed, step, (uint64_t)n, PUR_PROLIF, z);
+            const double a = fd.a;
+            double m[P];
+#pragma unroll
+            for (int i = 0; i < P; ++i) m[i] = a * ta[i] + (1.0 - a) * st.theta_bar[i];
 #pragma unroll
             for (int i = 0; i < P; ++i) {
                 double v = 0.0;
