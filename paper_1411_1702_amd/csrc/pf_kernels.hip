@@ -1039,11 +1039,18 @@ __global__ __launch_bounds__(TILE) void k_scatter(Batch B, const FilterDesc* des
         // (the step's validity only gates the stores)
         const int n = itm.tile * TILE + threadIdx.x;
         const unsigned long long q = n < fd.n ? fd.q[n] : 0ull;
+        // exclusive offset of this tile and total T of the integer weights:
+        // the first two tile sums of each lane are loaded with the rest, so
+        // one round trip covers up to 2 TILE tiles (2 TILE^2 particles)
+        const int nt = fd.ntiles;
+        const int t0 = threadIdx.x, t1 = t0 + TILE;
+        const unsigned long long v0 = t0 < nt ? fd.tsum[t0] : 0ull;
+        const unsigned long long v1 = t1 < nt ? fd.tsum[t1] : 0ull;
         const double t_cur = st.t;
         const uint64_t j_cur = st.j, v_test = st.V;
-        // exclusive offset of this tile and total T of the integer weights
-        unsigned long long pre = 0, all = 0;
-        for (int t = threadIdx.x; t < fd.ntiles; t += TILE) {
+        unsigned long long all = v0 + v1;
+        unsigned long long pre = (t0 < itm.tile ? v0 : 0ull) + (t1 < itm.tile ? v1 : 0ull);
+        for (int t = t0 + 2 * TILE; t < nt; t += TILE) {
             const unsigned long long v = fd.tsum[t];
             all += v;
             if (t < itm.tile) pre += v;
