@@ -100,9 +100,12 @@ __device__ inline void normals(uint64_t seed, uint64_t step, uint64_t particle, 
     }
 }
 
-// rate constant from a log-parameter: exponential in FP64 (the parameters
-// are FP64), rounded once to the propagation precision
-template <class R> __device__ inline R exp_rate(double th, R) { return (R)exp(th); }
+// rate constant from a log-parameter, in the propagation precision: FP64
+// exp for FP64 propagation; for FP32 propagation expf of the parameter
+// rounded to FP32 (relative error of the rate about |theta| 2^-24, below the
+// Newton tolerance of that path, at a third of the FP64 exp's instructions)
+__device__ inline double exp_rate(double th, double) { return exp(th); }
+__device__ inline float exp_rate(double th, float) { return expf((float)th); }
 
 // reciprocal: single-instruction v_rcp_f32 in FP32 (about 1 ulp), correctly
 // rounded division in FP64
