@@ -81,7 +81,7 @@ def algorithmic_bytes(prob):
 # sources: once they change, the figure no longer applies and bench reports
 # null until the counters are taken again.
 TRAFFIC = {
-    "3964abf24f33e2f1": {"fetch_kib": 3428.0, "write_kib": 5936.0, "fetch_scale": 2.0, "write_scale": 1.0},
+    "d0704d6d933fc63a": {"fetch_kib": 3425.0, "write_kib": 5936.0, "fetch_scale": 2.0, "write_scale": 1.0},
 }
 KERNEL_SOURCES = ("pf_kernels.hip", "pf_device.hpp", "pf_types.hpp")
 
@@ -300,7 +300,7 @@ def cpu_baseline_particles(O, prob, target_s, threads):
                       f"(FP64 C oracle, OpenMP over particles, {el:.1f} s)"}
 
 
-def precision_error(pf, ctx, prob, steps, reps=8):
+def precision_error(pf, ctx, prob, steps, reps=24):
     """FP32-propagation against FP64 at the stated error: `reps` seeds, each
     run in both precisions on the same data; after every step, the paired
     difference of each log-parameter's posterior mean, t = mean(d) /
