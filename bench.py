@@ -307,7 +307,11 @@ def precision_error(pf, ctx, prob, steps, reps=24):
     (sd(d)/sqrt(reps)) over the seeds.  Runs are compared only in
     distribution (a last-bit difference flips a resampling decision sooner
     or later and the paired runs decorrelate); |t| stays O(1) when the two
-    precisions estimate the same posterior.  Also the difference in units of
+    precisions estimate the same posterior.  Paired runs share every random
+    number and stay coupled for many steps, so sd(d) can be far below the
+    Monte Carlo error of either run, and a tiny consistent offset then shows
+    as a large t: the offset is also given in units of that Monte Carlo
+    error (the spread over seeds of the FP64 run's posterior mean) and of
     the posterior standard deviation."""
     mu = {}
     for prec in (pf.PF_PREC_FP32_PROP, pf.PF_PREC_FP64):
@@ -322,7 +326,7 @@ def precision_error(pf, ctx, prob, steps, reps=24):
                 rows.append((post["mean"], np.sqrt(np.maximum(np.diag(post["cov"]), 0.0))))
             f.close()
             mu[(prec, r)] = rows
-    tt, eff = [], []
+    tt, eff, mce = [], [], []
     for j in range(steps):
         pairs = [(mu[(pf.PF_PREC_FP32_PROP, r)][j], mu[(pf.PF_PREC_FP64, r)][j]) for r in range(reps)]
         pairs = [(a, b) for a, b in pairs if a is not None and b is not None]
@@ -331,14 +335,18 @@ def precision_error(pf, ctx, prob, steps, reps=24):
         d = np.array([a[0] - b[0] for a, b in pairs])
         sd_post = np.mean([b[1] for _, b in pairs], axis=0)
         se = d.std(axis=0, ddof=1) / np.sqrt(len(pairs))
+        mc = np.array([b[0] for _, b in pairs]).std(axis=0, ddof=1)
         tt.append(np.abs(d.mean(axis=0)) / np.maximum(se, 1e-300))
         eff.append(np.abs(d.mean(axis=0)) / np.maximum(sd_post, 1e-300))
-    tt, eff = np.asarray(tt), np.asarray(eff)
+        mce.append(np.abs(d.mean(axis=0)) / np.maximum(mc, 1e-300))
+    tt, eff, mce = np.asarray(tt), np.asarray(eff), np.asarray(mce)
     if not tt.size:
         return None
     return {"seeds": reps, "steps": int(tt.shape[0]),
             "paired_t_median": float(np.median(tt)), "paired_t_p95": float(np.percentile(tt, 95)),
             "frac_abs_t_above_3": float(np.mean(tt > 3.0)),
+            "mean_diff_in_mc_error_median": float(np.median(mce)),
+            "mean_diff_in_mc_error_max": float(mce.max()),
             "mean_diff_in_posterior_sd_median": float(np.median(eff)),
             "mean_diff_in_posterior_sd_max": float(eff.max())}
 
