@@ -398,6 +398,80 @@ __device__ __noinline__ double combine_cols(const double* part, int cs, int ntil
     return M;
 }
 
+// The combination for at most 2 TILE tiles and a few columns (the
+// first-stage partials; the kinetic and advection-diffusion moments): lane l
+// loads tiles l and l + TILE, all their columns at once; the block max of
+// the tile maxima; two exponentials per lane; each lane adds its two scaled
+// rows; the columns are summed over the block (sixteen at a time with
+// row_sum16, or with wave_sum for one column) and across wavefronts in LDS.
+// Fixed lane assignment and order, so the result depends only on ntiles.
+template <int NS>
+__device__ __forceinline__ double combine_pair(const double* part, int cs, int ntiles, int sq, int nplain,
+                                               double* out, double* sh)
+{
+    constexpr int NA = NS + 1;
+    constexpr int NCH = (NS + 15) / 16;
+    __shared__ double csum[NWAVE][NS == 1 ? 1 : NCH][NS == 1 ? 1 : WAVE];
+    const int t0 = threadIdx.x, t1 = t0 + TILE;
+    double r0[NA], r1[NA];
+    if (t0 < ntiles) {
+#pragma unroll
+        for (int k = 0; k < NA; ++k) r0[k] = part[(size_t)k * cs + t0];
+    } else {
+        r0[0] = -INFINITY;
+#pragma unroll
+        for (int k = 1; k < NA; ++k) r0[k] = 0.0;
+    }
+    if (t1 < ntiles) {
+#pragma unroll
+        for (int k = 0; k < NA; ++k) r1[k] = part[(size_t)k * cs + t1];
+    } else {
+        r1[0] = -INFINITY;
+#pragma unroll
+        for (int k = 1; k < NA; ++k) r1[k] = 0.0;
+    }
+    const double M = block_max(fmax(r0[0], r1[0]), sh);
+    const double s0 = (r0[0] > -INFINITY && M > -INFINITY) ? exp(r0[0] - M) : 0.0;
+    const double s1 = (r1[0] > -INFINITY && M > -INFINITY) ? exp(r1[0] - M) : 0.0;
+    auto scale = [&](int a, double r) { return a >= NS - nplain ? 1.0 : a == sq ? r * r : r; };
+    const int w = threadIdx.x / WAVE, ln = threadIdx.x % WAVE;
+    if constexpr (NS == 1) {
+        const double v = wave_sum(scale(0, s0) * r0[1] + scale(0, s1) * r1[1]);
+        if (ln == 0) csum[w][0][0] = v;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = 0.0;
+#pragma unroll
+            for (int ww = 0; ww < NWAVE; ++ww) t += csum[ww][0][0];
+            out[0] = t;
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            double chunk[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const int a = 16 * c + k;
+                chunk[k] = a < NS ? scale(a, s0) * r0[1 + a] + scale(a, s1) * r1[1 + a] : 0.0;
+            }
+            csum[w][c][ln] = row_sum16(chunk);
+        }
+        __syncthreads();
+        const int t = threadIdx.x;
+        if (t < NS) {
+            const int c = t / 16, j = t % 16;
+            double acc = 0.0;
+#pragma unroll
+            for (int ww = 0; ww < NWAVE; ++ww)
+#pragma unroll
+                for (int r = 0; r < WAVE / 16; ++r) acc += csum[ww][c][16 * r + j];
+            out[t] = acc;
+        }
+    }
+    __syncthreads();
+    return M;
+}
+
 // ---------------------------------------------------------------------------
 // moments of the parameters for one tile: partial[0] = max l, then
 // s0 = sum e, s00 = sum e^2, S1 = sum e d, S2 = sum e d d^T (upper triangle,
@@ -586,7 +660,8 @@ __device__ __forceinline__ void moments_combine(const FilterDesc& fd, double* to
 {
     constexpr int NA = 1 + 2 + P + P * (P + 1) / 2 + D + NPLAIN;
     if constexpr (NA * 8 <= 256) {
-        combine_rows<NA - 1>(fd.part2, fd.ntiles, fd.ntiles, 1, NPLAIN, tot, sh);
+        if (fd.ntiles <= 2 * TILE) combine_pair<NA - 1>(fd.part2, fd.ntiles, fd.ntiles, 1, NPLAIN, tot, sh);
+        else combine_rows<NA - 1>(fd.part2, fd.ntiles, fd.ntiles, 1, NPLAIN, tot, sh);
     } else {
         if (fd.ntiles <= TILE) combine_wide<NA - 1>(fd.part2, fd.ntiles, fd.ntiles, 1, NPLAIN, tot, sh);
         else combine_cols<NA - 1>(fd.part2, fd.ntiles, fd.ntiles, 1, NPLAIN, tot, sh);
@@ -921,7 +996,8 @@ __global__ __launch_bounds__(TILE) void k_count(Batch B, const FilterDesc* __res
         double M = 0.0, S = 1.0;
         if (!fd.g_direct) {
             // the filter's first-stage log-sum-exp, from the tile partials
-            M = combine_rows<1>(fd.part1, fd.ntiles, fd.ntiles, -1, 0, tot, sh);
+            M = fd.ntiles <= 2 * TILE ? combine_pair<1>(fd.part1, fd.ntiles, fd.ntiles, -1, 0, tot, sh)
+                                      : combine_rows<1>(fd.part1, fd.ntiles, fd.ntiles, -1, 0, tot, sh);
             S = tot[0];
         }
         const bool ok = fd.g_direct || (M > -INFINITY && isfinite(M) && S > 0.0);

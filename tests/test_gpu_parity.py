@@ -238,7 +238,7 @@ def _moments_gpu(pf, theta, logw):
 
 
 @pytest.mark.parametrize("p", [3, 5, 12])
-@pytest.mark.parametrize("n", [1, 300, 4097, 65536 + 7])
+@pytest.mark.parametrize("n", [1, 300, 4097, 65536 + 7, 1 << 17, (1 << 18) + 5])
 def test_moments_match_oracle(pf, oracle, p, n):
     rng = np.random.default_rng(p * 1000 + n)
     theta = rng.standard_normal((n, p)) * rng.uniform(0.1, 3.0, p) + rng.uniform(-5, 5, p)
@@ -435,6 +435,35 @@ def test_step_parity_robertson(pf, ctx, oracle, prec, j0):
         assert np.allclose(post["cov"], cov, rtol=1e-7, atol=1e-12)
         assert post["ess"] == pytest.approx(out["ess"], rel=1e-8)
         assert np.allclose(post["state_mean"], out["state_mean"], rtol=1e-9, atol=1e-15)
+
+
+@pytest.mark.parametrize("N", [1 << 17, (1 << 17) + 300])
+def test_step_parity_robertson_large_n(pf, ctx, oracle, N):
+    """One FP64 step from the prior draw at the largest tile counts: at 2^17
+    particles (512 tiles) the filter-wide combines (first-stage log-sum-exp,
+    moments) take two tiles per lane; above that they loop over the tiles.
+    Ancestors bit-exact, states and posterior summaries to rounding."""
+    prob = inputs.robertson(N, 5, seed=3)
+    ora = oracle.Filter(prob)
+    f = pf.Filter(ctx, pf.Config(prob, pf.PF_PREC_FP64))
+    rc, _, anc_o = ora.stage1(prob.times[0], prob.y[0], prob.sigma[0])
+    assert rc == 0
+    assert f.assimilate(prob.times[0], prob.y[0], prob.sigma[0]) == pf.PF_OK
+    out = ora.step(prob.times[0], prob.y[0], prob.sigma[0])
+    assert out["status"] == 0
+    anc = torch.zeros(f.N, dtype=torch.int32, device="cuda")
+    pf.check(pf.lib().pf_test_last_ancestors(f.h, anc.data_ptr()), "anc")
+    assert (anc.cpu().numpy() == anc_o).all()
+    x, th, lw = _get(pf, f)
+    post = f.posterior()
+    f.close()
+    err = np.abs(x - ora.x) / np.maximum(np.abs(ora.x), prob.state_floor)
+    assert err.max() < 1e-10, err.max()
+    assert np.allclose(th, ora.theta, rtol=1e-12, atol=1e-12)
+    mean, cov = ora.moments()
+    assert np.allclose(post["mean"], mean, rtol=1e-10, atol=1e-12)
+    assert np.allclose(post["cov"], cov, rtol=1e-7, atol=1e-12)
+    assert post["ess"] == pytest.approx(out["ess"], rel=1e-8)
 
 
 @pytest.mark.parametrize("prec", [0, 1])
