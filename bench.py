@@ -388,6 +388,17 @@ def single_filter(pf, args, prob):
         "avg_launch_ms": upd_ms,
         "flop_per_launch": r32["flop_update_per_launch"],
     }
+    # the predictor kernel alone: propagation and first-stage weights, no
+    # random numbers and no local-error estimate
+    pred_ms = r32["kernel_ms"]["predict"]
+    pred_tf = r32["flop_predict_per_launch"] / (pred_ms * 1e-3) / 1e12
+    propagation = {
+        "kernel": (f"k_ad_predict<{model}, fp32, {lmm_label(prob)}>" if prob.model == inputs.MODEL_ADVDIFF else
+                   f"k_predict<{model}, fp32, {lmm_label(prob)}> (steps 2-3a)"),
+        "bound": "alu", "achieved": pred_tf, "peak": PEAK_VALU_NONPACKED, "unit": "TFLOP/s",
+        "frac": pred_tf / PEAK_VALU_NONPACKED, "avg_launch_ms": pred_ms,
+        "flop_per_launch": r32["flop_predict_per_launch"],
+    }
     out = {
         "metric": METRIC,
         "value": r32["particle_steps_per_s"],
@@ -410,6 +421,7 @@ def single_filter(pf, args, prob):
         "lmm_substeps_per_s": r32["particle_steps_per_s"] * 2 * prob.substeps,
         "latency": lat,
         "roofline": roofline,
+        "roofline_propagation": propagation,
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
