@@ -232,6 +232,29 @@ enum { PF_TIME_STEP = 0, PF_TIME_PREDICT = 1, PF_TIME_RESAMPLE = 2, PF_TIME_UPDA
 pf_status pf_context_profile(pf_context* ctx, int enable);
 pf_status pf_context_kernel_time(pf_context* ctx, int which, uint64_t* count, double* ms);
 
+/* Launch-shape autotuner of the batched step (an implementation choice: it
+ * changes how tiles map to workgroups, never what Algorithm 1 computes).  A
+ * multi-filter submission runs three groups of launches: 0 the predictor
+ * kernels, 1 the resampling kernels, 2 the update kernels.  For each group
+ * and power-of-two bucket of the group's tile count, the first submissions
+ * try every candidate grid (one workgroup per tile, or 16, 8, 4, 2
+ * workgroups per compute unit, each looping over the tiles) twice, timed
+ * with events on the context stream; the fastest is kept for the context's
+ * lifetime.  Submissions on trial launch directly; a batch shape is captured
+ * into a graph only once its groups are tuned.  Grids never change a
+ * filter's arithmetic (fixed tiles, fixed per-tile order), so results are
+ * bit-identical with tuning on or off.  Single-filter steps always run one
+ * workgroup per tile.  On by default; PF_AUTOTUNE=0 in the environment at
+ * context creation, or pf_context_autotune(ctx, 0), turns it off (the
+ * default grid, min(tiles, 8 x CUs), is used; choices are kept and apply
+ * again when it is turned back on).
+ * pf_context_launch_grid waits for the submissions whose trials are not yet
+ * counted, then reports the grid a multi-filter submission would launch for
+ * `items` tiles in `group` now, and whether it was tuned (*tuned = 1).
+ * PF_EINVAL: ctx NULL, group outside 0..2, items 0 or above 2^20. */
+pf_status pf_context_autotune(pf_context* ctx, int enable);
+pf_status pf_context_launch_grid(pf_context* ctx, int group, uint32_t items, uint32_t* grid, int* tuned);
+
 /* Releases the filter's pool memory after its pending steps complete. */
 void pf_destroy(pf_filter* f);
 

@@ -135,6 +135,26 @@ struct Stage {
     hipEvent_t ev = nullptr;           // completion of the last submission from this block
     hipEvent_t tev[5] = {};            // timing events of that submission (profiling)
     bool timed = false;                // tev holds an uncollected timing
+    hipEvent_t uev[4] = {};            // launch-shape trial: bounds of the three tuned groups
+    bool trial = false;                // uev holds an uncollected trial
+    int trial_key[3] = {-1, -1, -1};   // tuner key of each group (-1: not on trial)
+    int trial_cand[3] = {0, 0, 0};     // candidate grid cap tried for it
+};
+
+// Launch-shape autotuner for multi-filter submissions.  Three groups of
+// launches are tuned: the predictor kernels, the resampling pair and the
+// update kernels.  For each group and power-of-two bucket of its tile count
+// the tuner times every candidate grid cap (one workgroup per tile, or 16,
+// 8, 4, 2 workgroups per compute unit looping over the tiles) TUNE_REPS times
+// on real steps, then keeps the fastest (least time of its trials).  Grid
+// shapes never change a filter's arithmetic (fixed tiles, fixed per-tile
+// order), so tuning leaves every result bit for bit as it is.
+constexpr int TUNE_NCAND = 5;
+constexpr int TUNE_REPS = 2;
+struct Tune {
+    float best[TUNE_NCAND];
+    int samples[TUNE_NCAND];
+    int chosen = -1;
 };
 
 // A captured step graph for one (staging block, batch signature).
@@ -166,6 +186,9 @@ struct pf_context {
     Stage stage[NSTAGE];
     int stage_next = 0;
     int grid_cap = 2048;
+    int n_cu = 256;
+    bool autotune = true;
+    std::map<int, Tune> tune;    // (group, bucket) -> trials and choice
     pf_allocator alloc{};        // caller's allocator of the pool (alloc == NULL: hipMalloc)
     std::mutex mu;
 };
@@ -493,12 +516,17 @@ extern "C" pf_status pf_context_create(int device, uint64_t pool_bytes, const pf
         // an interval holds the kernels and their dispatch, not a flush
         for (int i = 0; i < 5; ++i)
             HIP_TRY(hipEventCreateWithFlags(&ctx->stage[s].tev[i], hipEventDisableSystemFence));
+        for (int i = 0; i < 4; ++i)
+            HIP_TRY(hipEventCreateWithFlags(&ctx->stage[s].uev[i], hipEventDisableSystemFence));
     }
     hipDeviceProp_t prop;
     HIP_TRY(hipGetDeviceProperties(&prop, device));
+    ctx->n_cu = std::max(1, prop.multiProcessorCount);
     ctx->grid_cap = std::max(256, prop.multiProcessorCount * 8);
     const char* env = std::getenv("PF_GRAPHS");
     if (env && env[0] == '0') ctx->use_graphs = false;
+    const char* envt = std::getenv("PF_AUTOTUNE");
+    if (envt && envt[0] == '0') ctx->autotune = false;
     *out = ctx.release();
     return PF_OK;
 }
@@ -511,6 +539,7 @@ extern "C" void pf_context_destroy(pf_context* ctx)
     for (auto& kv : ctx->graphs) (void)hipGraphExecDestroy(kv.second.exec);
     for (int s = 0; s < NSTAGE; ++s) {
         for (int i = 0; i < 5; ++i) (void)hipEventDestroy(ctx->stage[s].tev[i]);
+        for (int i = 0; i < 4; ++i) (void)hipEventDestroy(ctx->stage[s].uev[i]);
         (void)hipEventDestroy(ctx->stage[s].ev);
         (void)hipHostFree(ctx->stage[s].host);
         (void)hipFree(ctx->stage[s].dev);
@@ -548,6 +577,41 @@ static unsigned grid_for(const pf_context* ctx, int items)
 {
     return (unsigned)std::max(1, std::min(items, ctx->grid_cap));
 }
+
+// candidate grid caps of the tuner: uncapped, then 16, 8, 4, 2 per CU
+static int tune_cap(const pf_context* ctx, int cand)
+{
+    static const int per_cu[TUNE_NCAND] = {0, 16, 8, 4, 2};
+    return cand == 0 ? MAX_ITEMS : per_cu[cand] * ctx->n_cu;
+}
+static int tune_bucket(int items)
+{
+    int b = 0;
+    while ((1 << b) < items) ++b;
+    return b;
+}
+static int tune_key(int group, int items) { return items > 0 ? group * 64 + tune_bucket(items) : -1; }
+
+// the tuner's entry for a key, created on first use: candidates whose cap
+// can never bind in the bucket (cap >= its largest tile count) are the same
+// launch as one workgroup per tile, so they are not tried
+static Tune& tune_entry(pf_context* ctx, int key)
+{
+    auto it = ctx->tune.find(key);
+    if (it != ctx->tune.end()) return it->second;
+    Tune t;
+    const int top = 1 << (key % 64);
+    int open = 0;
+    for (int c = 0; c < TUNE_NCAND; ++c) {
+        const bool same = c > 0 && tune_cap(ctx, c) >= top;
+        t.best[c] = same ? INFINITY : 0.0f;
+        t.samples[c] = same ? TUNE_REPS : 0;
+        open += same ? 0 : 1;
+    }
+    if (open == 1) t.chosen = 0;
+    return ctx->tune.emplace(key, t).first->second;
+}
+
 
 // ---------------------------------------------------------------------------
 // filter creation
@@ -637,6 +701,29 @@ static hipEvent_t pooled_event(pf_context* ctx)
 // accumulate the timing of the last submission from one staging block
 static pf_status stage_collect(pf_context* ctx, Stage& sg)
 {
+    if (sg.trial) {
+        HIP_TRY(hipEventSynchronize(sg.uev[3]));
+        for (int g = 0; g < 3; ++g) {
+            const int key = sg.trial_key[g];
+            if (key < 0) continue;
+            float ms = 0.0f;
+            HIP_TRY(hipEventElapsedTime(&ms, sg.uev[g], sg.uev[g + 1]));
+            Tune& t = tune_entry(ctx, key);
+            if (t.chosen >= 0) continue;
+            const int c = sg.trial_cand[g];
+            t.best[c] = t.samples[c] == 0 ? ms : std::min(t.best[c], ms);
+            t.samples[c]++;
+            bool done = true;
+            for (int k = 0; k < TUNE_NCAND; ++k) done = done && t.samples[k] >= TUNE_REPS;
+            if (done) {
+                int b = 0;
+                for (int k = 1; k < TUNE_NCAND; ++k)
+                    if (t.best[k] < t.best[b]) b = k;
+                t.chosen = b;
+            }
+        }
+        sg.trial = false;
+    }
     if (!sg.timed) return PF_OK;
     HIP_TRY(hipEventSynchronize(sg.tev[4]));
     float ms[5];
@@ -670,6 +757,30 @@ extern "C" pf_status pf_context_profile(pf_context* ctx, int enable)
     ctx->profiling = enable != 0;
     ctx->prof_count = 0;
     for (double& v : ctx->prof_ms) v = 0.0;
+    return PF_OK;
+}
+
+extern "C" pf_status pf_context_autotune(pf_context* ctx, int enable)
+{
+    if (!ctx) return fail(PF_EINVAL, "ctx is NULL");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->autotune = enable != 0;
+    return PF_OK;
+}
+
+extern "C" pf_status pf_context_launch_grid(pf_context* ctx, int group, uint32_t items, uint32_t* grid, int* tuned)
+{
+    if (!ctx || group < 0 || group > 2 || items == 0 || items > (uint32_t)MAX_ITEMS)
+        return fail(PF_EINVAL, "bad argument");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    HIP_TRY(hipSetDevice(ctx->device));
+    pf_status s = prof_collect(ctx);   // trials of completed submissions count
+    if (s != PF_OK) return s;
+    const int key = tune_key(group, (int)items);
+    auto it = ctx->tune.find(key);
+    const bool ok = ctx->autotune && it != ctx->tune.end() && it->second.chosen >= 0;
+    if (grid) *grid = (uint32_t)std::max(1, std::min((int)items, ok ? tune_cap(ctx, it->second.chosen) : ctx->grid_cap));
+    if (tuned) *tuned = ok ? 1 : 0;
     return PF_OK;
 }
 
@@ -753,6 +864,34 @@ static pf_status submit(pf_context* ctx, uint32_t count, pf_filter* const* fs, c
     }
     const int n_all = off;
     const bool timed = ctx->profiling;
+    // launch shapes: the tuned grid cap of each group, or a candidate on trial
+    int n_kin = 0;
+    for (const Range& r : ranges) {
+        int model, lmm, prec, order;
+        class_decode(r.cls, model, lmm, prec, order);
+        if (model != MODEL_ADVDIFF) n_kin += r.cnt;
+    }
+    const int gkey[3] = {tune_key(0, n_kin), tune_key(1, n_all), tune_key(2, n_kin)};
+    int gcap[3], gcand[3] = {-1, -1, -1};
+    bool trial = false;
+    for (int g = 0; g < 3; ++g) {
+        // a single filter's step keeps one workgroup per tile (up to the cap)
+        gcap[g] = ctx->grid_cap;
+        if (!ctx->autotune || gkey[g] < 0 || count == 1) continue;
+        Tune& t = tune_entry(ctx, gkey[g]);
+        if (t.chosen >= 0) {
+            gcap[g] = tune_cap(ctx, t.chosen);
+            continue;
+        }
+        if (timed) continue;   // profiled submissions time the kernels, not trials
+        int c = 0;
+        for (int k = 1; k < TUNE_NCAND; ++k)
+            if (t.samples[k] < t.samples[c]) c = k;
+        gcand[g] = c;
+        gcap[g] = tune_cap(ctx, c);
+        trial = true;
+    }
+    auto grid_of = [](int cap, int items) { return (unsigned)std::max(1, std::min(items, cap)); };
     // one filter: its record travels in the kernel arguments and nothing is
     // copied ahead of the kernels; otherwise one copy of [recs | items]
     const bool inline_rec = count == 1;
@@ -811,23 +950,26 @@ static pf_status submit(pf_context* ctx, uint32_t count, pf_filter* const* fs, c
             if (e != hipSuccess) return e;
         }
         if (timed && (e = hipEventRecord(sg.tev[0], ctx->stream)) != hipSuccess) return e;
+        if (trial && (e = hipEventRecord(sg.uev[0], ctx->stream)) != hipSuccess) return e;
         for (const Range& r : ranges) {
             int model, lmm, prec, order;
             class_decode(r.cls, model, lmm, prec, order);
             if (model == MODEL_ADVDIFF) continue;
             hipLaunchKernelGGL(inline_rec ? predict_kernel<true>(model, lmm, prec, order)
                                           : predict_kernel<false>(model, lmm, prec, order),
-                               dim3(grid_for(ctx, r.cnt)), dim3(TILE), 0,
+                               dim3(grid_of(gcap[0], r.cnt)), dim3(TILE), 0,
                                ctx->stream, part(r), ctx->d_desc, ctx->d_state);
         }
+        if (trial && (e = hipEventRecord(sg.uev[1], ctx->stream)) != hipSuccess) return e;
         ad_launch(false);
         if (timed && (e = hipEventRecord(sg.tev[1], ctx->stream)) != hipSuccess) return e;
-        hipLaunchKernelGGL(inline_rec ? k_count<true> : k_count<false>, dim3(grid_for(ctx, n_all)), dim3(TILE), 0,
+        hipLaunchKernelGGL(inline_rec ? k_count<true> : k_count<false>, dim3(grid_of(gcap[1], n_all)), dim3(TILE), 0,
                            ctx->stream, all, ctx->d_desc,
                            ctx->d_state);
-        hipLaunchKernelGGL(inline_rec ? k_scatter<true> : k_scatter<false>, dim3(grid_for(ctx, n_all)), dim3(TILE),
-                           0, ctx->stream, all, ctx->d_desc,
+        hipLaunchKernelGGL(inline_rec ? k_scatter<true> : k_scatter<false>, dim3(grid_of(gcap[1], n_all)),
+                           dim3(TILE), 0, ctx->stream, all, ctx->d_desc,
                            ctx->d_state);
+        if (trial && (e = hipEventRecord(sg.uev[2], ctx->stream)) != hipSuccess) return e;
         if (timed && (e = hipEventRecord(sg.tev[2], ctx->stream)) != hipSuccess) return e;
         for (const Range& r : ranges) {
             int model, lmm, prec, order;
@@ -835,9 +977,10 @@ static pf_status submit(pf_context* ctx, uint32_t count, pf_filter* const* fs, c
             if (model == MODEL_ADVDIFF) continue;
             hipLaunchKernelGGL(inline_rec ? update_kernel<true>(model, lmm, prec, order)
                                           : update_kernel<false>(model, lmm, prec, order),
-                               dim3(grid_for(ctx, r.cnt)), dim3(TILE), 0,
+                               dim3(grid_of(gcap[2], r.cnt)), dim3(TILE), 0,
                                ctx->stream, part(r), ctx->d_desc, ctx->d_state);
         }
+        if (trial && (e = hipEventRecord(sg.uev[3], ctx->stream)) != hipSuccess) return e;
         ad_launch(true);
         if (timed && (e = hipEventRecord(sg.tev[3], ctx->stream)) != hipSuccess) return e;
         hipLaunchKernelGGL(moments_kernel,
@@ -852,7 +995,9 @@ static pf_status submit(pf_context* ctx, uint32_t count, pf_filter* const* fs, c
     // profiled submissions launch directly: their events then bracket the
     // kernels themselves.  A single filter's step launches directly too: its
     // record is in the kernel arguments, which a graph would freeze.
-    if (ctx->use_graphs && !timed && !inline_rec && ad_entries.empty()) {
+    // a batch shape whose launch shapes are still on trial is launched
+    // directly (its events time the trial) and captured once they are chosen
+    if (ctx->use_graphs && !timed && !trial && !inline_rec && ad_entries.empty()) {
         auto it = ctx->graphs.find(sig);
         if (it == ctx->graphs.end() && ++ctx->seen[sig] >= 2) {
             // a repeated batch shape: capture it once and replay it afterwards
@@ -889,6 +1034,11 @@ static pf_status submit(pf_context* ctx, uint32_t count, pf_filter* const* fs, c
     }
     if (!launched) HIP_TRY(enqueue());
     sg.timed = timed;
+    sg.trial = trial;
+    for (int g = 0; g < 3; ++g) {
+        sg.trial_key[g] = gcand[g] >= 0 ? gkey[g] : -1;
+        sg.trial_cand[g] = gcand[g] >= 0 ? gcand[g] : 0;
+    }
     HIP_TRY(hipEventRecord(sg.ev, ctx->stream));
     hipEvent_t raw = pooled_event(ctx);
     HIP_TRY(hipEventRecord(raw, ctx->stream));

@@ -26,7 +26,7 @@ EXPORTS = [
     "pf_context_create", "pf_context_destroy", "pf_filter_bytes", "pf_context_memory",
     "pf_create", "pf_assimilate", "pf_assimilate_async", "pf_wait", "pf_assimilate_batch",
     "pf_posterior", "pf_stats", "pf_destroy", "pf_status_str", "pf_last_error",
-    "pf_context_profile", "pf_context_kernel_time", "pf_query",
+    "pf_context_profile", "pf_context_kernel_time", "pf_context_autotune", "pf_context_launch_grid", "pf_query",
     "pf_server_create", "pf_server_open", "pf_server_submit", "pf_server_poll", "pf_server_posterior",
     "pf_server_close", "pf_server_drain", "pf_server_stats", "pf_server_destroy",
     "pf_test_philox", "pf_test_normals", "pf_test_propagate", "pf_test_resample", "pf_test_resample_multinomial",
@@ -103,6 +103,8 @@ def lib():
         L.pf_stats.argtypes = [vp, C.POINTER(u64), C.c_uint32]
         L.pf_context_profile.argtypes = [vp, C.c_int]
         L.pf_context_kernel_time.argtypes = [vp, C.c_int, C.POINTER(u64), C.POINTER(C.c_double)]
+        L.pf_context_autotune.argtypes = [vp, C.c_int]
+        L.pf_context_launch_grid.argtypes = [vp, C.c_int, C.c_uint32, C.POINTER(C.c_uint32), C.POINTER(C.c_int)]
         L.pf_destroy.argtypes = [vp]
         L.pf_destroy.restype = None
         L.pf_status_str.argtypes = [C.c_int]
@@ -230,6 +232,17 @@ class Context:
         n, ms = C.c_uint64(), C.c_double()
         check(lib().pf_context_kernel_time(self.h, int(which), C.byref(n), C.byref(ms)), "kernel_time")
         return n.value, ms.value
+
+    def autotune(self, enable=True):
+        check(lib().pf_context_autotune(self.h, int(enable)), "pf_context_autotune")
+
+    def launch_grid(self, group, items):
+        """(grid, tuned) of a multi-filter submission's launch group (0 predictor,
+        1 resampling, 2 update) over `items` tiles."""
+        g, t = C.c_uint32(), C.c_int()
+        check(lib().pf_context_launch_grid(self.h, int(group), int(items), C.byref(g), C.byref(t)),
+              "pf_context_launch_grid")
+        return g.value, bool(t.value)
 
     def close(self):
         if self.h:

@@ -107,6 +107,44 @@ def test_batched_bit_identical_to_alone(pf, graphs):
             f.close()
 
 
+def test_autotuned_launch_shapes(pf):
+    """The launch-shape tuner tries every candidate grid on the first
+    submissions of a batch, keeps one per launch group, and changes no
+    result: a tuned context and one with the tuner off give the same
+    ensembles bit for bit, and each tuned grid is a candidate."""
+    probs = [(inputs.robertson(65536 - 300 * i, 40, seed=20 + i), 1) for i in range(6)]
+    probs.append((inputs.chain16(16384, 40, seed=30, model_seed=0), 1))
+    tiles = sum((p.n_particles + 255) // 256 for p, _ in probs)
+    cu = torch.cuda.get_device_properties(0).multi_processor_count
+    steps = 24
+    runs = []
+    for tuned in (True, False):
+        with _ctx(pf, True) as ctx:
+            ctx.autotune(tuned)
+            fs = [pf.Filter(ctx, pf.Config(prob, prec)) for prob, prec in probs]
+            for j in range(steps):
+                tk = ctx.assimilate_batch(fs, [p.times[j] for p, _ in probs], [p.y[j] for p, _ in probs],
+                                          [p.sigma[j] for p, _ in probs])
+                for f, t in zip(fs, tk):
+                    assert f.wait(t) == pf.PF_OK
+            for group in (0, 1, 2):
+                grid, ok = ctx.launch_grid(group, tiles)
+                assert ok == tuned, group
+                if tuned:
+                    assert grid in {min(tiles, c) for c in (tiles, 16 * cu, 8 * cu, 4 * cu, 2 * cu)}, grid
+                else:
+                    assert grid == min(tiles, 8 * cu)
+            assert pf.lib().pf_context_launch_grid(ctx.h, 3, tiles, None, None) == pf.PF_EINVAL
+            assert pf.lib().pf_context_launch_grid(ctx.h, 0, 0, None, None) == pf.PF_EINVAL
+            runs.append([(f.posterior(), _ensemble(pf, f)) for f in fs])
+            for f in fs:
+                f.close()
+    for i, ((pa, ea), (pb, eb)) in enumerate(zip(*runs)):
+        assert np.array_equal(pa["mean"], pb["mean"]) and np.array_equal(pa["cov"], pb["cov"]), i
+        for u, v in zip(ea, eb):
+            assert np.array_equal(u, v), i
+
+
 def test_batch_with_uneven_schedules(pf):
     # filters join and leave the batch: each one's trajectory still matches
     # running it alone
