@@ -244,7 +244,9 @@ pf_status pf_context_kernel_time(pf_context* ctx, int which, uint64_t* count, do
  * into a graph only once its groups are tuned.  Grids never change a
  * filter's arithmetic (fixed tiles, fixed per-tile order), so results are
  * bit-identical with tuning on or off.  Single-filter steps always run one
- * workgroup per tile.  On by default; PF_AUTOTUNE=0 in the environment at
+ * workgroup per tile; batches holding advection-diffusion filters use the
+ * grids already chosen but run no trials (their own launches sit between
+ * the groups).  On by default; PF_AUTOTUNE=0 in the environment at
  * context creation, or pf_context_autotune(ctx, 0), turns it off (the
  * default grid, min(tiles, 8 x CUs), is used; choices are kept and apply
  * again when it is turned back on).

@@ -871,6 +871,8 @@ static pf_status submit(pf_context* ctx, uint32_t count, pf_filter* const* fs, c
         class_decode(r.cls, model, lmm, prec, order);
         if (model != MODEL_ADVDIFF) n_kin += r.cnt;
     }
+    bool has_ad = false;   // advection-diffusion launches sit between the groups' events
+    for (uint32_t b = 0; b < count; ++b) has_ad = has_ad || fs[b]->desc.model == MODEL_ADVDIFF;
     const int gkey[3] = {tune_key(0, n_kin), tune_key(1, n_all), tune_key(2, n_kin)};
     int gcap[3], gcand[3] = {-1, -1, -1};
     bool trial = false;
@@ -883,7 +885,7 @@ static pf_status submit(pf_context* ctx, uint32_t count, pf_filter* const* fs, c
             gcap[g] = tune_cap(ctx, t.chosen);
             continue;
         }
-        if (timed) continue;   // profiled submissions time the kernels, not trials
+        if (timed || has_ad) continue;   // trials only where the events bracket the group alone
         int c = 0;
         for (int k = 1; k < TUNE_NCAND; ++k)
             if (t.samples[k] < t.samples[c]) c = k;
