@@ -70,6 +70,16 @@ __device__ inline double lane63(double v)
     return __longlong_as_double((long long)lane63_u64((uint64_t)__double_as_longlong(v)));
 }
 
+// orders one wavefront's LDS writes before its lanes' later reads (a
+// wavefront's LDS operations complete in order; the fences keep the
+// compiler from moving them across this point)
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ inline double wave_sum(double v)
 {
     v += dppd<DPP_QUAD_1032, 0xF>(v);
@@ -693,44 +703,52 @@ __device__ __forceinline__ int32_t moments_tail_wg(const double* tot, const MomP
         cv[i][j] = tot[2 + P + r * P - r * (r - 1) / 2 + (c - r)] * inv - dms[i] * dms[j];
     }
     __syncthreads();
-    double tr = 0.0;
+    // the factorisation runs in wavefront 0 alone: its rounds order their LDS
+    // traffic with wavefront-scope fences instead of workgroup barriers
+    __shared__ int jit_sh;
+    if (t < WAVE) {
+        double tr = 0.0;
 #pragma unroll
-    for (int i = 0; i < P; ++i) tr += cv[i][i];
-    double delta = 0.0;
-    int jit = -1;
-    for (int attempt = 0; attempt <= 5 && jit < 0; ++attempt) {
-        if (attempt == 1) delta = 1e-10 * tr / P;
-        else if (attempt > 1) delta *= 10.0;
-        for (int e = t; e < P * P; e += TILE) {
-            const int i = e / P, j = e % P;
-            A[i][j] = i == j ? cv[i][j] + delta : cv[i][j];
-        }
-        __syncthreads();
-        bool ok = true;
-        for (int j = 0; j < P && ok; ++j) {
-            const double sdiag = A[j][j];
-            ok = sdiag > 0.0 && isfinite(sdiag);
-            if (ok) {
-                const double ljj = sqrt(sdiag);
-                const double rl = 1.0 / ljj;
-                __syncthreads();
-                if (t == j) A[j][j] = ljj;
-                if (t > j && t < P) A[t][j] = A[t][j] * rl;
-                __syncthreads();
-                // trailing triangle: rows i > j, columns j < k <= i
-                const int m = P - j - 1;
-                for (int e = t; e < m * (m + 1) / 2; e += TILE) {
-                    int i = 0;
-                    while ((i + 1) * (i + 2) / 2 <= e) ++i;
-                    const int k = e - i * (i + 1) / 2;
-                    const int ii = j + 1 + i, kk = j + 1 + k;
-                    A[ii][kk] -= A[ii][j] * A[kk][j];
-                }
-                __syncthreads();
+        for (int i = 0; i < P; ++i) tr += cv[i][i];
+        double delta = 0.0;
+        int jit = -1;
+        for (int attempt = 0; attempt <= 5 && jit < 0; ++attempt) {
+            if (attempt == 1) delta = 1e-10 * tr / P;
+            else if (attempt > 1) delta *= 10.0;
+            for (int e = t; e < P * P; e += WAVE) {
+                const int i = e / P, j = e % P;
+                A[i][j] = i == j ? cv[i][j] + delta : cv[i][j];
             }
+            wave_sync();
+            bool ok = true;
+            for (int j = 0; j < P && ok; ++j) {
+                const double sdiag = A[j][j];
+                ok = sdiag > 0.0 && isfinite(sdiag);
+                if (ok) {
+                    const double ljj = sqrt(sdiag);
+                    const double rl = 1.0 / ljj;
+                    wave_sync();
+                    if (t == j) A[j][j] = ljj;
+                    if (t > j && t < P) A[t][j] = A[t][j] * rl;
+                    wave_sync();
+                    // trailing triangle: rows i > j, columns j < k <= i
+                    const int m = P - j - 1;
+                    for (int e = t; e < m * (m + 1) / 2; e += WAVE) {
+                        int i = 0;
+                        while ((i + 1) * (i + 2) / 2 <= e) ++i;
+                        const int k = e - i * (i + 1) / 2;
+                        const int ii = j + 1 + i, kk = j + 1 + k;
+                        A[ii][kk] -= A[ii][j] * A[kk][j];
+                    }
+                    wave_sync();
+                }
+            }
+            if (ok) jit = attempt;
         }
-        if (ok) jit = attempt;
+        if (t == 0) jit_sh = jit;
     }
+    __syncthreads();
+    const int jit = jit_sh;
     if (jit < 0) return ST_EDEGENERATE;
     for (int e = t; e < P * P; e += TILE) {
         const int i = e / P, j = e % P;
