@@ -1004,13 +1004,14 @@ __global__ __launch_bounds__(TILE) void k_count(Batch B, const FilterDesc* __res
     for (int itx = blockIdx.x; itx < B.n_items; itx += gridDim.x) {
         const Item itm = fetch<INL>(B, itx);
         const FilterDesc& fd = desc_of<INL>(B, descs, itm.slot);
-        const FilterState& st = states[itm.slot];
+        FilterState& st = states[itm.slot];
         // every load is issued before anything waits: the lane's log-weight,
-        // the filter time (the step's validity only gates the stores), and
+        // the filter state (the step's validity only gates the stores), and
         // the tile partials of the combine
         const int n = itm.tile * TILE + threadIdx.x;
         const double l = n < fd.n ? fd.lg[n] : -INFINITY;
         const double t_cur = st.t;
+        const uint64_t j_cur = st.j, v_test = st.V;
         double M = 0.0, S = 1.0;
         if (!fd.g_direct) {
             // the filter's first-stage log-sum-exp, from the tile partials
@@ -1029,6 +1030,17 @@ __global__ __launch_bounds__(TILE) void k_count(Batch B, const FilterDesc* __res
             if (!fd.g_direct && !(itm.rec.t_next > t_cur)) continue;   // the step does not run
             if (n < fd.n) fd.q[n] = q;
             if (threadIdx.x == 0) fd.tsum[itm.tile] = ts;
+            // the systematic draw's one uniform word of the filter and step,
+            // drawn once here for the scatter pass (test mode: the host's)
+            if (itm.tile == 0 && threadIdx.x == 0) {
+                uint64_t r = v_test;
+                if (!fd.g_direct) {
+                    uint64_t w[4];
+                    Philox::block(j_cur + 1, 0, PUR_RESAMPLE, 0, fd.seed, 0, w);
+                    r = w[0];
+                }
+                st.R = r;
+            }
         } else {
             // multinomial draw: the inclusive prefix of q within the tile
             // (every lane of the tile, so the prefix is monotone up to 255)
@@ -1141,21 +1153,13 @@ __global__ __launch_bounds__(TILE) void k_scatter(Batch B, const FilterDesc* des
         const unsigned long long v0 = t0 < nt ? fd.tsum[t0] : 0ull;
         const unsigned long long v1 = t1 < nt ? fd.tsum[t1] : 0ull;
         const double t_cur = st.t;
-        const uint64_t j_cur = st.j, v_test = st.V;
+        const uint64_t r = st.R;   // the step's uniform word, from the count pass
         unsigned long long all = v0 + v1;
         unsigned long long pre = (t0 < itm.tile ? v0 : 0ull) + (t1 < itm.tile ? v1 : 0ull);
         for (int t = t0 + 2 * TILE; t < nt; t += TILE) {
             const unsigned long long v = fd.tsum[t];
             all += v;
             if (t < itm.tile) pre += v;
-        }
-        uint64_t r;
-        if (fd.g_direct) {
-            r = v_test;   // test mode: the uniform word was stored by the host
-        } else {
-            uint64_t w[4];
-            Philox::block(j_cur + 1, 0, PUR_RESAMPLE, 0, fd.seed, 0, w);
-            r = w[0];
         }
         unsigned long long T;
         block_sum2_u64(pre, all, shu, pre, T);

@@ -94,6 +94,7 @@ struct FilterState {
     double t_next;
     uint64_t step;                      // j + 1
     uint64_t T, V;                      // resampling total and offset
+    uint64_t R;                         // the step's resampling word (drawn by the count pass)
     unsigned long long newton_pred, newton_upd, newton_fails, nonfinite, jitters;
     int32_t ring[RING];                 // status by ticket % RING
 };
