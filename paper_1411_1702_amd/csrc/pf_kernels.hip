@@ -175,17 +175,27 @@ __device__ inline void block_sum2_u64(unsigned long long a, unsigned long long b
     }
 }
 
+// inclusive prefix sum over the wavefront (uint64, exact) with DPP lane
+// moves: shifts by 1, 2, 4, 8 within each row of 16 (lanes without a source
+// add 0), then the row broadcasts of lane 15 and lane 31 into the rows above
+constexpr int DPP_ROW_SR1 = 0x111, DPP_ROW_SR2 = 0x112, DPP_ROW_SR4 = 0x114, DPP_ROW_SR8 = 0x118;
+__device__ inline unsigned long long wave_incl_scan_u64(unsigned long long v)
+{
+    v += dpp64<DPP_ROW_SR1, 0xF>(v);
+    v += dpp64<DPP_ROW_SR2, 0xF>(v);
+    v += dpp64<DPP_ROW_SR4, 0xF>(v);
+    v += dpp64<DPP_ROW_SR8, 0xF>(v);
+    v += dpp64<DPP_ROW_BCAST15, 0xA>(v);
+    v += dpp64<DPP_ROW_BCAST31, 0xC>(v);
+    return v;
+}
+
 // exclusive prefix sum over the block (uint64, exact); returns the total
 __device__ inline unsigned long long block_exscan_u64(unsigned long long v, unsigned long long& excl,
                                                       unsigned long long* sh)
 {
     const int w = threadIdx.x / WAVE, l = threadIdx.x % WAVE;
-    unsigned long long incl = v;
-#pragma unroll
-    for (int o = 1; o < WAVE; o <<= 1) {
-        const unsigned long long t = __shfl_up(incl, o);
-        if (l >= o) incl += t;
-    }
+    const unsigned long long incl = wave_incl_scan_u64(v);
     __syncthreads();
     if (l == WAVE - 1) sh[w] = incl;
     __syncthreads();
