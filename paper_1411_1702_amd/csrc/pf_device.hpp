@@ -107,6 +107,10 @@ __device__ inline void normals(uint64_t seed, uint64_t step, uint64_t particle, 
 __device__ inline double exp_rate(double th, double) { return exp(th); }
 __device__ inline float exp_rate(double th, float) { return expf((float)th); }
 
+// fused multiply-add a b + c, one rounding
+__device__ inline float rfma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ inline double rfma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 // reciprocal: single-instruction v_rcp_f32 in FP32 (about 1 ulp), correctly
 // rounded division in FP64
 __device__ inline float recip(float v) { return __builtin_amdgcn_rcpf(v); }
@@ -352,6 +356,15 @@ __device__ inline void integrate(const Model& md, R x[Model::D], R gam[Model::D]
         R psi[D], xp[D], xn[D];
 #pragma unroll
         for (int i = 0; i < D; ++i) {
+            if constexpr (QC == 2) {
+                // the steady BDF2 step with its fused multiply-adds written
+                // out, so that unrolled copies round exactly as one step does
+                psi[i] = rfma(x[i], -(R)co.a1, -((R)co.a2 * h1[i]));
+                const R p = h2[i] + rfma(x[i], R(3), -(R(3) * h1[i]));
+                xp[i] = p;
+                xn[i] = p;
+                continue;
+            }
             R s = -(R)co.a1 * x[i];
             if (KORD >= 2 && q >= 2) s -= (R)co.a2 * h1[i];
             if (KORD >= 3 && q >= 3) s -= (R)co.a3 * h2[i];
@@ -468,7 +481,14 @@ __device__ inline void integrate(const Model& md, R x[Model::D], R gam[Model::D]
     };
     int m = 1;
     for (; m <= M && avail < KORD; ++m) step(std::integral_constant<int, 0>{});
-    for (; m <= M; ++m) step(std::integral_constant<int, KORD>{});
+    if constexpr (KORD == 2) {
+        // unrolled by the history's rotation period (x_m, x_{m-1}, x_{m-2}):
+        // the copies rename the history registers instead of moving them
+#pragma unroll(3)
+        for (; m <= M; ++m) step(std::integral_constant<int, KORD>{});
+    } else {
+        for (; m <= M; ++m) step(std::integral_constant<int, KORD>{});
+    }
 }
 
 // ---------------------------------------------------------------------------
