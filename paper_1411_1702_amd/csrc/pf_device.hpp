@@ -356,11 +356,19 @@ __device__ inline void integrate(const Model& md, R x[Model::D], R gam[Model::D]
         R psi[D], xp[D], xn[D];
 #pragma unroll
         for (int i = 0; i < D; ++i) {
+            // the steady BDF2 and BDF3 steps with their fused multiply-adds
+            // written out, so that unrolled copies round exactly as one step
+            // does
             if constexpr (QC == 2) {
-                // the steady BDF2 step with its fused multiply-adds written
-                // out, so that unrolled copies round exactly as one step does
                 psi[i] = rfma(x[i], -(R)co.a1, -((R)co.a2 * h1[i]));
                 const R p = h2[i] + rfma(x[i], R(3), -(R(3) * h1[i]));
+                xp[i] = p;
+                xn[i] = p;
+                continue;
+            }
+            if constexpr (QC == 3) {
+                psi[i] = rfma(h2[i], -(R)co.a3, rfma(x[i], -(R)co.a1, -((R)co.a2 * h1[i])));
+                const R p = rfma(h2[i], R(4), rfma(x[i], R(4), -(R(6) * h1[i]))) - h3[i];
                 xp[i] = p;
                 xn[i] = p;
                 continue;
@@ -481,10 +489,11 @@ __device__ inline void integrate(const Model& md, R x[Model::D], R gam[Model::D]
     };
     int m = 1;
     for (; m <= M && avail < KORD; ++m) step(std::integral_constant<int, 0>{});
-    if constexpr (KORD == 2) {
-        // unrolled by the history's rotation period (x_m, x_{m-1}, x_{m-2}):
-        // the copies rename the history registers instead of moving them
-#pragma unroll(3)
+    if constexpr ((KORD == 2 || KORD == 3) && (sizeof(R) == 4 || D <= 4)) {
+        // unrolled by the history's rotation period (x_m and KORD older
+        // states): the copies rename the history registers instead of moving
+        // them (not for the large models in FP64, whose copies would spill)
+#pragma unroll(KORD + 1)
         for (; m <= M; ++m) step(std::integral_constant<int, KORD>{});
     } else {
         for (; m <= M; ++m) step(std::integral_constant<int, KORD>{});
