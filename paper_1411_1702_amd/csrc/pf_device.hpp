@@ -558,6 +558,16 @@ __device__ inline void integrate_am(const Model& md, R x[Model::D], R gam[Model:
         R psi[D], xp[D], xn[D];
 #pragma unroll
         for (int i = 0; i < D; ++i) {
+            if constexpr (ST && KORD == 1) {
+                // the steady trapezoidal step with its fused multiply-adds
+                // written out, so that unrolled copies round exactly as one
+                // step does
+                psi[i] = rfma((R)co.b1 * f0[i], h, x[i]);
+                const R p = h2[i] + rfma(x[i], R(3), -(R(3) * h1[i]));
+                xp[i] = p;
+                xn[i] = p;
+                continue;
+            }
             R s = (R)co.b1 * f0[i];
             if (KORD >= 2 && q >= 2) s += (R)co.b2 * f1[i];
             if (KORD >= 3 && q >= 3) s += (R)co.b3 * f2[i];
@@ -617,7 +627,14 @@ __device__ inline void integrate_am(const Model& md, R x[Model::D], R gam[Model:
         avail = avail < 3 ? avail + 1 : 3;
     };
     for (; m <= M && !(m >= KORD && avail >= RS); ++m) step(std::false_type{});
-    for (; m <= M; ++m) step(std::true_type{});
+    // AM1 unrolled by its history's rotation period (x_m, x_{m-1}, x_{m-2}):
+    // the copies rename the history registers instead of moving them
+    if constexpr (KORD == 1 && (sizeof(R) == 4 || D <= 4)) {
+#pragma unroll(3)
+        for (; m <= M; ++m) step(std::true_type{});
+    } else {
+        for (; m <= M; ++m) step(std::true_type{});
+    }
 }
 
 // Psi of either LMM family (LMM 0 BDF, 1 Adams-Moulton, 2 BDF with the SDIRK start-up)
