@@ -489,10 +489,12 @@ __device__ inline void integrate(const Model& md, R x[Model::D], R gam[Model::D]
     };
     int m = 1;
     for (; m <= M && avail < KORD; ++m) step(std::integral_constant<int, 0>{});
-    if constexpr ((KORD == 2 || KORD == 3) && (sizeof(R) == 4 || D <= 4)) {
+    if constexpr (sizeof(R) == 4 || D <= 4) {
         // unrolled by the history's rotation period (x_m and KORD older
         // states): the copies rename the history registers instead of moving
-        // them (not for the large models in FP64, whose copies would spill)
+        // them (not for the large models in FP64, whose copies would spill).
+        // The BDF1 step needs no written-out form: its products (x by 1 and
+        // by 2) are exact, so any fusion rounds the same.
 #pragma unroll(KORD + 1)
         for (; m <= M; ++m) step(std::integral_constant<int, KORD>{});
     } else {
