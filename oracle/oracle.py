@@ -15,6 +15,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "pf_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
+# another build of the same source (e.g. with sanitizers) can be loaded instead
+LIB_OVERRIDE = os.environ.get("PF_ORACLE_LIB")
 
 OK, EINVAL, EDEGENERATE = 0, 1, 4
 PUR_PRIOR, PUR_RESAMPLE, PUR_PROLIF, PUR_INNOV = 1, 2, 3, 4
@@ -22,13 +24,21 @@ MODEL_DECAY, MODEL_ROBERTSON, MODEL_CHAIN, MODEL_ADVDIFF = 0, 1, 2, 3
 DMAX, PMAX, MMAX = 1521, 12, 32
 
 
+CFLAGS = ["-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-Wall"]
+
+
+def compile_to(src: str, out: str, extra=()) -> str:
+    """gcc one oracle source into a shared library at `out`."""
+    tmp = out + ".tmp"
+    subprocess.check_call(["gcc"] + CFLAGS + list(extra) + ["-o", tmp, src, "-lm"])
+    os.replace(tmp, out)
+    return out
+
+
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (OpenMP over particles)."""
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-        tmp = LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
-                               "-Wall", "-o", tmp, SRC, "-lm"])
-        os.replace(tmp, LIB)
+        compile_to(SRC, LIB)
     return LIB
 
 
@@ -68,9 +78,12 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-            build(force=True)
-        L = C.CDLL(LIB)
+        if LIB_OVERRIDE:
+            L = C.CDLL(LIB_OVERRIDE)
+        else:
+            if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+                build(force=True)
+            L = C.CDLL(LIB)
         dp = C.POINTER(C.c_double)
         up = C.POINTER(C.c_uint64)
         L.or_philox4x64.argtypes = [up, up, up]
