@@ -65,14 +65,21 @@ typedef enum {
  * field is the BDF order k (k steps, order k), or for AM the number of steps
  * k of the Adams-Moulton formula (order k + 1; AM1 is the trapezoidal rule;
  * AM2 and AM3 are not A-stable, so stiff models need AM1 or small steps).
- *   BDF:       each interval restarts the history, so its first k-1 steps
- *              use BDF1 .. BDF(k-1) (the interval is then first order).
+ *   BDF:       each interval restarts the history (the filter carries only
+ *              x_j), and step m of the interval uses order
+ *              q = max(1, min(k, m - 1)): steps 1 and 2 are BDF1, BDFk is
+ *              reached at step k + 1 (the interval is of order 1, 2, 2 for
+ *              k = 1, 2, 3).
  *   BDF_SDIRK: the first k-1 steps of each interval instead take one step
  *              each of an L-stable, stiffly accurate SDIRK method of order k
- *              (k stages; Alexander's order-2 and order-3 methods), then
- *              BDFk; the interval keeps order k.  The Sec. 2.2 estimate at
- *              those steps is the ramp's (same comparison value and
- *              constant).  With order 1 it is plain BDF1. */
+ *              (k stages; Alexander's order-2 and order-3 methods), step k
+ *              uses BDF(k-1) on the k values then available, and BDFk
+ *              follows; the one lower-order step has a local error of order
+ *              h^k, so the interval keeps order k.  The local-error estimate
+ *              of step 4(b) of Algorithm 1 (Sec. 2; its formula is the
+ *              library's own reading, the paper defers it to a companion
+ *              paper) takes at those steps the ramp's comparison value and
+ *              constant.  With order 1 it is plain BDF1. */
 typedef enum { PF_LMM_BDF = 0, PF_LMM_AM = 1, PF_LMM_BDF_SDIRK = 2 } pf_lmm;
 
 typedef enum {
@@ -204,15 +211,20 @@ pf_status pf_posterior(pf_filter* f, double* mean, double* cov, double* state_me
 /* Counters since creation, written to counters[0..n) (n <= PF_STAT_COUNT):
  * Newton iterations of the predictor pass (step 2), Newton iterations of
  * the repropagation pass (step 4), integration steps that hit the Newton
- * iteration cap, particles given weight zero for a non-finite state, and
- * Cholesky jitter retries.  Waits for pending steps. */
+ * iteration cap, particles given weight zero for a non-finite state,
+ * Cholesky jitter retries, and new states x_{j+1} (after the innovation of
+ * step 4(d)) with a negative component.  The kinetic models solve the Newton
+ * system I - c J without pivoting, which is shown safe (every pivot >= 1)
+ * for states x >= 0; the last counter tells how often a step started from
+ * outside that region.  Waits for pending steps. */
 enum {
     PF_STAT_NEWTON_PREDICT = 0,
     PF_STAT_NEWTON_UPDATE = 1,
     PF_STAT_NEWTON_FAILS = 2,
     PF_STAT_NONFINITE = 3,
     PF_STAT_JITTERS = 4,
-    PF_STAT_COUNT = 5
+    PF_STAT_NEGATIVE_STATES = 5,
+    PF_STAT_COUNT = 6
 };
 pf_status pf_stats(pf_filter* f, uint64_t* counters, uint32_t n);
 

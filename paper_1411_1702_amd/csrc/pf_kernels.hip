@@ -497,18 +497,20 @@ __device__ __forceinline__ double combine_pair(const double* part, int cs, int n
 // s0 = sum e, s00 = sum e^2, S1 = sum e d, S2 = sum e d d^T (upper triangle,
 // row by row), Sx = sum e x, with e = exp(l - max) and d = theta - c; then
 // the NPLAIN counters: the lanes' packed counts, plus the predictor's
-// (iterations, fails) of the tile when pred is given (pred[0], pred[cs]).
+// (iterations, fails) of the tile when pred is given (pred[0], pred[cs]),
+// and the number of lanes with `neg` set.
 // Column c of the tile's partials goes to out_part[c * cs].  P and D are the
 // model's, so every register index is static.
 // ---------------------------------------------------------------------------
 template <class R, int P, int D>
 __device__ void tile_moments(double l, bool valid, const double* th, const R* x, const double* cshift,
-                             uint64_t counts, const double* pred, double* out_part, int cs, double* sh)
+                             uint64_t counts, const double* pred, double* out_part, int cs, double* sh,
+                             bool neg = false)
 {
     constexpr int NV = 2 + P + P * (P + 1) / 2 + D;   // weighted sums
     constexpr int NCH = (NV + 15) / 16;
     __shared__ double part[NWAVE][NCH][WAVE];
-    __shared__ double cw[NWAVE][3];
+    __shared__ double cw[NWAVE][4];
     const double lv = valid ? l : -INFINITY;
     const double Mt = block_max(lv, sh);
     const double e = (valid && lv > -INFINITY) ? exp(lv - Mt) : 0.0;
@@ -537,10 +539,12 @@ __device__ void tile_moments(double l, bool valid, const double* th, const R* x,
         part[w][c][ln] = row_sum16(chunk);
     }
     const uint64_t wc = wave_sum_u64(counts);
+    const uint64_t wneg = __ballot(neg);
     if (ln == 0) {
         cw[w][0] = count_iters(wc);
         cw[w][1] = count_fails(wc);
         cw[w][2] = count_nonf(wc);
+        cw[w][3] = (double)__popcll(wneg);
     }
     __syncthreads();
     const int t = threadIdx.x;
@@ -554,9 +558,10 @@ __device__ void tile_moments(double l, bool valid, const double* th, const R* x,
                 for (int r = 0; r < WAVE / 16; ++r) s += part[ww][c][16 * r + j];
         } else {
             const int k = t - NV;
-            if (k < 3) {
+            if (k < 3 || k == 4) {
+                const int kc = k < 3 ? k : 3;
 #pragma unroll
-                for (int ww = 0; ww < NWAVE; ++ww) s += cw[ww][k];
+                for (int ww = 0; ww < NWAVE; ++ww) s += cw[ww][kc];
             }
             if (pred && k == 1) s += pred[cs];
             if (pred && k == 3) s += pred[0];
@@ -581,7 +586,7 @@ struct MomPre {
     double tb[PMAX];
     double t;
     uint64_t j, T;
-    unsigned long long jit, n_pred, n_upd, n_fail, n_nonf;
+    unsigned long long jit, n_pred, n_upd, n_fail, n_nonf, n_neg;
     int32_t cur;
 };
 template <int P>
@@ -598,6 +603,7 @@ __device__ inline MomPre mom_prefetch(const FilterState& st)
     r.n_upd = st.newton_upd;
     r.n_fail = st.newton_fails;
     r.n_nonf = st.nonfinite;
+    r.n_neg = st.negative;
     r.cur = st.cur;
     return r;
 }
@@ -790,6 +796,7 @@ __device__ __forceinline__ void moments_counters(const FilterDesc& fd, const dou
     st.newton_fails = pre.n_fail + (unsigned long long)c[1];
     st.nonfinite = pre.n_nonf + (unsigned long long)c[2];
     st.newton_pred = pre.n_pred + (unsigned long long)c[3];
+    st.negative = pre.n_neg + (unsigned long long)c[4];
 }
 
 // counters and tail, called by the whole workgroup; returns the status to
@@ -1239,6 +1246,7 @@ __global__ __launch_bounds__(TILE) void k_update(Batch B, const FilterDesc* __re
 #pragma unroll
         for (int i = 0; i < D; ++i) x[i] = R(0);
         uint32_t iters = 0, fails = 0, nonf = 0;
+        bool neg = false;
         if (valid) {
             int k = k_anc;
             // the scatter covers every slot exactly once; an out-of-range
@@ -1287,6 +1295,7 @@ __global__ __launch_bounds__(TILE) void k_update(Batch B, const FilterDesc* __re
             for (int i = 0; i < D; ++i) {
                 x[i] = xw[i] + sqrt(gam[i]) * zi[i];
                 xo[(size_t)i * fd.npad + n] = x[i];
+                neg |= x[i] < R(0);
             }
 #pragma unroll
             for (int i = 0; i < P; ++i) fd.theta[nxt][(size_t)i * fd.npad + n] = th[i];
@@ -1297,7 +1306,7 @@ __global__ __launch_bounds__(TILE) void k_update(Batch B, const FilterDesc* __re
         }
         // 6 (partials): tile moments with shift theta_bar_j
         tile_moments<R, P, D>(l, valid, th, x, st.theta_bar, pack_counts(iters, fails, nonf),
-                              fd.part1 + (size_t)2 * fd.ntiles + itm.tile, fd.part2 + itm.tile, fd.ntiles, sh);
+                              fd.part1 + (size_t)2 * fd.ntiles + itm.tile, fd.part2 + itm.tile, fd.ntiles, sh, neg);
     }
 }
 

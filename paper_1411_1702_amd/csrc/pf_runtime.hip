@@ -1176,7 +1176,8 @@ extern "C" pf_status pf_stats(pf_filter* f, uint64_t* counters, uint32_t n)
     FilterState st;
     pf_status s = read_state(f, &st);
     if (s != PF_OK) return s;
-    const uint64_t v[PF_STAT_COUNT] = {st.newton_pred, st.newton_upd, st.newton_fails, st.nonfinite, st.jitters};
+    const uint64_t v[PF_STAT_COUNT] = {st.newton_pred, st.newton_upd, st.newton_fails, st.nonfinite, st.jitters,
+                                       st.negative};
     for (uint32_t i = 0; i < n; ++i) counters[i] = v[i];
     return PF_OK;
 }

@@ -88,6 +88,7 @@ struct Stream {
     OwnedConfig conf;
     SState state = SState::Queued;
     bool close_requested = false;
+    int readers = 0;                  // pf_server_posterior calls reading f outside the lock
     pf_filter* f = nullptr;
     uint64_t bytes = 0;
     uint64_t next_ticket = 1;
@@ -179,6 +180,7 @@ bool pf_server::admit_locked()
         admitted++;
         admit_waits.push_back(ms_between(s->opened, Clock::now()));
         if (!s->waiting.empty() || s->close_requested) live[s->id] = s;
+        done_cv.notify_all();   // a posterior call may wait for the admission
     }
     return progress;
 }
@@ -209,6 +211,10 @@ bool pf_server::collect_locked()
             progress = true;
         }
         if (s->waiting.empty() && s->inflight.empty()) {
+            if (s->close_requested && s->readers > 0) {
+                ++it;   // released once the posterior read ends
+                continue;
+            }
             if (s->close_requested) release_locked(s);
             it = live.erase(it);
             progress = true;
@@ -236,7 +242,8 @@ bool pf_server::launch_locked()
     std::vector<Stream*> members;
     for (auto& kv : live) {
         Stream* s = kv.second;
-        if (!s->waiting.empty() && s->inflight.size() < 60) members.push_back(s);
+        // a stream whose posterior is being read is not touched until the read ends
+        if (!s->waiting.empty() && s->inflight.size() < 60 && s->readers == 0) members.push_back(s);
         if (members.size() >= max_batch) break;
     }
     if (members.empty()) return false;
@@ -262,7 +269,9 @@ bool pf_server::launch_locked()
             const Obs o = s->waiting.front();
             s->waiting.pop_front();
             s->done[o.ticket] = Result{st, 0.0};
-            s->completed_upto = o.ticket;
+            // with earlier steps still in flight, completed_upto advances when
+            // they complete (the failed step belongs to no tick)
+            if (s->inflight.empty()) s->completed_upto = o.ticket;
             skipped++;
         }
         done_cv.notify_all();
@@ -388,6 +397,7 @@ extern "C" pf_status pf_server_posterior(pf_server* s, uint64_t stream, double* 
     auto it = s->streams.find(stream);
     if (it == s->streams.end()) return PF_EINVAL;
     Stream* st = it->second;
+    s->cv.notify_one();
     s->done_cv.wait(lk, [&] {
         return st->state == SState::Closed || (st->state != SState::Queued && st->waiting.empty() && st->inflight.empty());
     });
@@ -401,7 +411,17 @@ extern "C" pf_status pf_server_posterior(pf_server* s, uint64_t stream, double* 
         if (step) *step = st->fstep;
         return PF_OK;
     }
-    return pf_posterior(st->f, mean, cov, nullptr, ess, step);
+    // read outside the lock (pf_posterior waits for the device): while
+    // readers > 0 the scheduler launches nothing for this stream and does not
+    // release it, so the filter has one user at a time
+    st->readers++;
+    pf_filter* f = st->f;
+    lk.unlock();
+    const pf_status r = pf_posterior(f, mean, cov, nullptr, ess, step);
+    lk.lock();
+    st->readers--;
+    s->cv.notify_one();
+    return r;
 }
 
 extern "C" pf_status pf_server_close(pf_server* s, uint64_t stream)

@@ -22,8 +22,8 @@ constexpr int RING = 64;       // per-filter status ring (steps in flight)
 constexpr int PART1_STRIDE = 4;
 // counter columns at the end of each moment-partial row (summed unscaled):
 // update iterations, failed solves (both kernels), non-finite weights,
-// predictor iterations
-constexpr int NPLAIN = 4;
+// predictor iterations, states with a negative component
+constexpr int NPLAIN = 5;
 constexpr int SUBSTEPS_MAX = 65536;
 constexpr int KMAX_MAX = 64;
 constexpr int MULTI_MAX_TILES = 4096;   // multinomial draw: N <= 2^20 (tile offsets in LDS)
@@ -96,6 +96,9 @@ struct FilterState {
     uint64_t T, V;                      // resampling total and offset
     uint64_t R;                         // the step's resampling word (drawn by the count pass)
     unsigned long long newton_pred, newton_upd, newton_fails, nonfinite, jitters;
+    // new states with a negative component: the kinetic models' unpivoted
+    // elimination of I - c J is shown safe (every pivot >= 1) for x >= 0 only
+    unsigned long long negative;
     int32_t ring[RING];                 // status by ticket % RING
 };
 

@@ -298,9 +298,10 @@ class Filter:
                 "step": step.value}
 
     def stats(self):
-        v = (C.c_uint64 * 5)()
-        check(lib().pf_stats(self.h, v, 5), "pf_stats")
-        return dict(zip(["newton_predict", "newton_update", "newton_fails", "nonfinite", "jitters"], list(v)))
+        names = ["newton_predict", "newton_update", "newton_fails", "nonfinite", "jitters", "negative_states"]
+        v = (C.c_uint64 * len(names))()
+        check(lib().pf_stats(self.h, v, len(names)), "pf_stats")
+        return dict(zip(names, list(v)))
 
     def close(self):
         if self.h:

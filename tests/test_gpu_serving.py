@@ -124,3 +124,31 @@ def test_admission_by_memory(pf):
         assert _same(a, b), i
     assert report["streams_admitted"] == len(streams)
     assert report["admit_wait_p99_ms"] > 0.0
+
+
+def test_posterior_of_a_fresh_stream_returns(pf):
+    """pf_server_posterior on a stream with no submissions waits only for its
+    admission and returns the prior's summary (the same as pf_create's)."""
+    import threading
+    prob = inputs.robertson(2000, 5, seed=7)
+    with pf.Context(0, 1 << 30) as ctx:
+        f = pf.Filter(ctx, pf.Config(prob, pf.PF_PREC_FP64))
+        ref = f.posterior()
+        f.close()
+        srv = pf.Server(ctx)
+        sid = srv.open(pf.Config(prob, pf.PF_PREC_FP64))
+        box = {}
+        th = threading.Thread(target=lambda: box.update(post=srv.posterior(sid, prob.p)), daemon=True)
+        th.start()
+        th.join(timeout=30)
+        assert not th.is_alive(), "pf_server_posterior did not return"
+        post = box["post"]
+        assert post["step"] == 0
+        assert np.array_equal(post["mean"], ref["mean"]) and np.array_equal(post["cov"], ref["cov"])
+        # the stream still serves afterwards
+        tk = srv.submit(sid, prob.times[0], prob.y[0], prob.sigma[0])
+        srv.drain()
+        assert srv.poll(sid, tk)[0] == pf.PF_OK
+        assert srv.posterior(sid, prob.p)["step"] == 1
+        srv.close(sid)
+        srv.destroy()

@@ -7,17 +7,17 @@ be compared element by element: their propagation differs from the FP64
 oracle by more than rounding and the runs decorrelate (FP64 runs with shared
 seeds are compared step by step in test_gpu_wholerun.py).
 
-Calibration: the per-step z-scores of one comparison are strongly correlated
-over steps (the posterior at step j carries into step j+1), so an excursion
-of one replicate set spans many steps.  Independent oracle seed sets compared
-with each other exceed |z| = 3 on up to 6% of the steps (small AM1 problem,
-R = 16) and, with R = 8 over 200 steps, one oracle set ran ~7% high in its
-posterior sd against three others.  Hence R >= 12 where the oracle is cheap,
-at most 10% of steps beyond 3 MCSE, and no step beyond 5.
+The rule (tests/stat_rule.py): at most 10% of the (step, parameter)
+z-scores beyond 3 and none beyond 5.  Its calibration on the oracle alone
+(test_stat_rule_calibration.py): pairs of independent oracle seed sets
+stayed at or below 1.3% beyond 3 with |z| <= 3.4, so a comparison that
+shows more than that is seeing a difference between the two sides (for the
+FP32 path, its rounding offset); each test prints its margins.
 """
 import numpy as np
 import pytest
 
+import stat_rule as S
 from paper_1411_1702_amd import inputs
 
 torch = pytest.importorskip("torch")
@@ -33,31 +33,17 @@ def pf():
     return _pf
 
 
-def _replicates(run, R, seed0):
-    ms, ss = [], []
-    for r in range(R):
-        m, s, _ = run(seed0 + r)
-        ms.append(m)
-        ss.append(s)
-    return np.array(ms), np.array(ss)
-
-
-def _zscores(a, b):
-    R = a.shape[0]
-    se = np.sqrt(a.var(axis=0, ddof=1) / R + b.var(axis=0, ddof=1) / R)
-    return (a.mean(axis=0) - b.mean(axis=0)) / np.maximum(se, 1e-300)
-
-
 def _check(pf, oracle, prob, precs, R, T):
-    ora_m, ora_s = _replicates(lambda sd: oracle.Filter(prob, seed=sd).run(T), R, 0)
+    ora_m, ora_s = S.replicates(lambda sd: oracle.Filter(prob, seed=sd).run(T), R, 0)
     with pf.Context(0, 2 << 30) as ctx:
         for prec in precs:
-            gm, gs = _replicates(lambda sd: pf.run_filter(ctx, prob, prec, T=T, seed=sd), R, 100)
-            for name, z in (("mean", _zscores(gm, ora_m)), ("sd", _zscores(gs, ora_s))):
-                z = z[np.isfinite(z)]
-                frac = np.mean(np.abs(z) > 3.0)
-                assert frac <= 0.10, (prec, name, frac, np.abs(z).max())
-                assert np.abs(z).max() < 5.0, (prec, name, np.abs(z).max())
+            gm, gs = S.replicates(lambda sd: pf.run_filter(ctx, prob, prec, T=T, seed=sd), R, 100)
+            m = S.margins(gm, gs, ora_m, ora_s)
+            print(prob.name, "precision", prec, "R", R, "T", T,
+                  {q: ("%.3f beyond 3" % f, "max |z| %.2f" % z) for q, (f, z) in m.items()})
+            for name, (frac, zmax) in m.items():
+                assert frac <= S.FRAC_BEYOND_3, (prec, name, frac, zmax)
+                assert zmax < S.MAX_Z, (prec, name, zmax)
 
 
 def test_small_robertson_within_3_mcse(pf, oracle):
@@ -99,8 +85,10 @@ def test_robertson_200_steps_within_3_mcse(pf, oracle):
     _check(pf, oracle, prob, (pf.PF_PREC_FP32_PROP,), R=16, T=200)
 
 
+@pytest.mark.timeout(900)
 def test_chain_within_3_mcse(pf, oracle):
-    """The 16-compartment chain (BDF3, M=40) at N=2048, first 20 observations,
-    R=6 (the oracle's dense 16x16 LU makes longer runs slow)."""
+    """The 16-compartment chain (BDF3, M=40) at N=2048 over all 100
+    observations, R=12 (the oracle's dense 16x16 LU makes it the slowest
+    comparison: about 10 s per oracle run on 16 cores)."""
     prob = inputs.chain16(2048, 100, seed=0)
-    _check(pf, oracle, prob, (pf.PF_PREC_FP32_PROP,), R=6, T=20)
+    _check(pf, oracle, prob, (pf.PF_PREC_FP32_PROP,), R=12, T=100)

@@ -44,6 +44,7 @@ def _cases():
         ("robertson_multinomial_50", mult, 50, 2, 1e-9),
         ("advdiff_7x7_n512", inputs.advdiff(512, 5, seed=0, n=8), 5, 2, 1e-9),
         ("advdiff_19x19_n64", inputs.advdiff(64, 2, seed=0, n=20), 2, 1, 1e-9),
+        ("chain16_bdf3_n1024_30", inputs.chain16(1024, 100, seed=0), 30, 2, 1e-9),
     ]
 
 
