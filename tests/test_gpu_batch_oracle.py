@@ -2,23 +2,35 @@
 (Algorithm 1 for many filters at once).
 
 Several filters with different particle counts, integrators and resampling
-draws run through one pf_assimilate_batch per observation step (step graphs
-on), and through the continuous-batching server; every filter's posterior is
-compared with an oracle filter of the same seed.  As in the single-filter
-whole runs, both sides draw the same random numbers and resample on the same
-integer weights, so the runs follow one trajectory and the posterior
-summaries agree to rounding at every step."""
+draws, and both kinetic models, run through one pf_assimilate_batch per
+observation step (step graphs on), and through the continuous-batching
+server.  The Robertson filters' posteriors are compared with oracle filters
+of the same seed over whole runs: both sides draw the same random numbers and
+resample on the same integer weights, so the runs follow one trajectory and
+the summaries agree to rounding at every step (within the flat floor, or a
+fixed multiple of the oracle's own spread under fused multiply-adds;
+tests/rounding_yardstick.py).
+
+The 16-state chain runs in the same batches, but its whole runs are not a
+well-posed comparison: its first observation leaves 1-5 particles with
+weight (ESS 1.0-4.6 of 1024-2048 across seeds), so the parameter covariance
+has rank at most 5 of 12, its null space is rounding noise, and the jittered
+Cholesky factor -- and every proliferation drawn from it -- differs between
+any two evaluation orders by far more than rounding (the CPU test
+test_rounding_yardstick.py shows the collapse).  The chain is compared step by
+step instead: every filter of the batch starts from the oracle's ensemble and
+one batched step must give the oracle's ancestors, states, parameters and
+weights."""
 import os
 
 import numpy as np
 import pytest
 
 from paper_1411_1702_amd import inputs
+import rounding_yardstick as Y
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
-
-TOL = 1e-9
 
 
 @pytest.fixture(scope="module")
@@ -32,7 +44,7 @@ def pf():
 
 def _filters():
     """(problem, observations assimilated): BDF2, BDF3 with the SDIRK
-    start-up, AM1, multinomial draw, and the chain with BDF3."""
+    start-up, AM1, multinomial draw, and the chain with BDF3 (last)."""
     bdf2 = inputs.robertson(1000, 50, seed=0)
     sd3 = inputs.robertson(1500, 50, seed=1)
     sd3.lmm, sd3.order = 2, 3
@@ -45,17 +57,17 @@ def _filters():
 
 
 def _oracle_runs(oracle, fs):
+    """Per filter: the oracle's (means, sds, ess) and the per-step tolerances."""
     out = []
     for prob, T in fs:
-        m, s, e = oracle.Filter(prob).run(T)
-        out.append((m, s, e))
+        ref, sp = Y.spread(oracle, prob, T)
+        out.append((ref, Y.tolerances(sp)))
     return out
 
 
 def _err(gm, gs, om, osd):
-    """Mean error relative to max(|mean|, sd); sd error relative to the sd."""
-    scale = np.maximum(np.abs(om), osd)
-    return (np.abs(gm - om) / scale).max(), (np.abs(gs - osd) / osd).max()
+    em, es = Y.summary_errors(gm, gs, om, osd)
+    return em[0], es[0]
 
 
 def _ctx(pf, pool=1 << 30):
@@ -85,17 +97,19 @@ def test_batched_fp64_follows_the_oracle(pf, oracle):
                 st = hs[i].wait(t)
                 assert st in (pf.PF_OK, pf.PF_EDEGENERATE), (i, j, st)
             for i in members:
+                if fs[i][0].model == inputs.MODEL_CHAIN:
+                    continue   # ill-posed over whole runs: compared step by step below
                 post = hs[i].posterior()
-                om, osd, oess = ref[i][0][j], ref[i][1][j], ref[i][2][j]
+                (om, osd, oess), (tm, ts, te) = ref[i]
                 gs = np.sqrt(np.diag(post["cov"]))
-                em, es = _err(post["mean"], gs, om, osd)
-                worst = [max(worst[0], em), max(worst[1], es)]
-                assert em < TOL and es < TOL, (fs[i][0].name, j, em, es)
-                if np.isfinite(oess):
-                    assert post["ess"] == pytest.approx(oess, rel=TOL), (i, j)
+                em, es = _err(post["mean"], gs, om[j], osd[j])
+                worst = [max(worst[0], em / tm[j]), max(worst[1], es / ts[j])]
+                assert em < tm[j] and es < ts[j], (fs[i][0].name, j, em, es, tm[j], ts[j])
+                if np.isfinite(oess[j]):
+                    assert post["ess"] == pytest.approx(oess[j], rel=te[j]), (i, j)
                 # a degenerate step is skipped on both sides
-                assert post["step"] == np.isfinite(ref[i][2][: j + 1]).sum(), (i, j, post["step"])
-        print("batched FP64 vs oracle: worst mean err %.2e, sd err %.2e" % tuple(worst))
+                assert post["step"] == np.isfinite(oess[: j + 1]).sum(), (i, j, post["step"])
+        print("batched FP64 vs oracle: worst mean err %.2f, sd err %.2f of the tolerance" % tuple(worst))
         for h in hs:
             h.close()
 
@@ -131,7 +145,61 @@ def test_served_fp64_follows_the_oracle(pf, oracle):
     assert report["mean_batch"] > 1.0
     assert len(checked) == 2 * len(fs)
     for i, j, post in checked:
-        om, osd = ref[i][0][j], ref[i][1][j]
-        em, es = _err(post["mean"], np.sqrt(np.diag(post["cov"])), om, osd)
-        print("served", fs[i][0].name, "step", j + 1, "mean err %.2e sd err %.2e" % (em, es))
-        assert em < TOL and es < TOL, (fs[i][0].name, j, em, es)
+        if fs[i][0].model == inputs.MODEL_CHAIN:
+            continue   # ill-posed over whole runs (module docstring)
+        (om, osd, _), (tm, ts, _) = ref[i]
+        em, es = _err(post["mean"], np.sqrt(np.diag(post["cov"])), om[j], osd[j])
+        print("served", fs[i][0].name, "step", j + 1, "mean err %.2e sd err %.2e (tol %.1e, %.1e)"
+              % (em, es, tm[j], ts[j]))
+        assert em < tm[j] and es < ts[j], (fs[i][0].name, j, em, es)
+
+
+def test_batched_step_matches_oracle(pf, oracle):
+    """One batched step (graphs on) of all five filters, each started from
+    the oracle's ensemble after three observations: per filter, the oracle's
+    ancestors exactly, states within 1e-10 of the scale of their terms,
+    parameters within 1e-12, log-weights within 1e-8 and the posterior mean
+    within 1e-10 (the single-filter step parity bars)."""
+    import test_gpu_parity as TP
+    fs = _filters()
+    j0 = 3
+    oras = []
+    for prob, _ in fs:
+        ora = oracle.Filter(prob)
+        for j in range(j0):
+            assert ora.step(prob.times[j], prob.y[j], prob.sigma[j])["status"] == 0
+        oras.append(ora)
+    with _ctx(pf) as ctx:
+        hs = [pf.Filter(ctx, pf.Config(prob, pf.PF_PREC_FP64)) for prob, _ in fs]
+        x_in = [(o.x.copy(), o.t) for o in oras]
+        for h, o in zip(hs, oras):
+            TP._set(pf, h, o)
+        anc_o = []
+        for (prob, _), o in zip(fs, oras):
+            rc, _, a = o.stage1(prob.times[j0], prob.y[j0], prob.sigma[j0])
+            assert rc == 0
+            anc_o.append(a)
+        tk = ctx.assimilate_batch(hs, [p.times[j0] for p, _ in fs], [p.y[j0] for p, _ in fs],
+                                  [p.sigma[j0] for p, _ in fs])
+        for h, t in zip(hs, tk):
+            assert h.wait(t) == pf.PF_OK
+        for i, ((prob, _), h, o) in enumerate(zip(fs, hs, oras)):
+            assert o.step(prob.times[j0], prob.y[j0], prob.sigma[j0])["status"] == 0
+            anc = torch.zeros(h.N, dtype=torch.int32, device="cuda")
+            pf.check(pf.lib().pf_test_last_ancestors(h.h, anc.data_ptr()), "anc")
+            assert np.array_equal(anc.cpu().numpy(), anc_o[i]), prob.name
+            x, th, lw = TP._get(pf, h)
+            scale = np.maximum(TP._innovation_scale(oracle, prob, x_in[i][0], x_in[i][1], anc_o[i], o.theta,
+                                                    j0 + 1), prob.state_floor)
+            err = (np.abs(x - o.x) / scale).max()
+            fin = np.isfinite(o.logw)
+            print("batched step", prob.name, "state err %.2e" % err,
+                  "logw err %.2e" % np.abs(lw[fin] - o.logw[fin]).max())
+            assert err < 1e-10, (prob.name, err)
+            assert np.allclose(th, o.theta, rtol=1e-12, atol=1e-12), prob.name
+            assert np.array_equal(np.isfinite(lw), fin), prob.name
+            assert np.allclose(lw[fin], o.logw[fin], rtol=0, atol=1e-8), prob.name
+            mean, _ = o.moments()
+            assert np.allclose(h.posterior()["mean"], mean, rtol=1e-10, atol=1e-12), prob.name
+        for h in hs:
+            h.close()
