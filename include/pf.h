@@ -335,6 +335,24 @@ pf_status pf_server_drain(pf_server* s);
 pf_status pf_server_stats(pf_server* s, pf_server_report* out);
 void pf_server_destroy(pf_server* s);
 
+/*
+ * Systematic resampling of given weights without any allocation, for callers
+ * that cannot allocate device memory (code that runs between graph captures,
+ * tight serving loops, harnesses that forbid hipMalloc).  The same
+ * computation and result as pf_test_resample: g [n] normalised weights
+ * (device double), r the uniform word, anc [n] (device int32) receives the
+ * ancestors; PF_EDEGENERATE when every scaled weight is zero.
+ * Limit: n <= PF_NOALLOC_MAX_N (2^20).  Its scratch (the integer weights,
+ * the tile sums and the draw's state, about 8 MiB) is one static device array
+ * per GPU, held until the process ends; every call on a GPU uses the same
+ * array, so calls that overlap on one GPU (other streams or threads) race:
+ * serialise them.  Runs on `hip_stream` on the current device; synchronous
+ * (it reads back the weights' total).  PF_EINVAL for NULL buffers or n out
+ * of range; no memory is allocated, by this library or by HIP on its behalf.
+ */
+#define PF_NOALLOC_MAX_N (1ull << 20)
+pf_status pf_resample_noalloc(uint64_t n, const double* g, uint64_t r, int32_t* anc, void* hip_stream);
+
 const char* pf_status_str(pf_status s);
 const char* pf_last_error(void);
 

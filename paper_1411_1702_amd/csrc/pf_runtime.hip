@@ -1396,6 +1396,92 @@ extern "C" pf_status pf_test_resample_multinomial(uint64_t n, const double* g, u
     return test_resample(n, g, 1, 0, seed, step, anc, hip_stream);
 }
 
+// ---------------------------------------------------------------------------
+// systematic resampling without allocation: the draw's state, the integer
+// weights and the tile sums live in one static device array; the descriptor
+// and the record travel by value in the kernels' inline batch form
+// ---------------------------------------------------------------------------
+namespace pf {
+constexpr uint64_t NOALLOC_MAX_N = PF_NOALLOC_MAX_N;
+constexpr size_t NOALLOC_Q_OFF = 256 * ((sizeof(FilterState) + 255) / 256);
+constexpr size_t NOALLOC_TSUM_OFF = NOALLOC_Q_OFF + 8 * NOALLOC_MAX_N;
+constexpr size_t NOALLOC_BYTES = NOALLOC_TSUM_OFF + 8 * (NOALLOC_MAX_N / TILE);
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+// the draw's state: zero except the caller's uniform word (the count pass
+// takes it from V in the given-weights form)
+__global__ __launch_bounds__(TILE) void k_noalloc_state(FilterState* st, uint64_t r)
+{
+    uint64_t* w = (uint64_t*)st;
+    for (size_t i = threadIdx.x; i < sizeof(FilterState) / 8; i += TILE) w[i] = 0;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        st->status = ST_OK;
+        st->V = r;
+    }
+}
+}  // namespace pf
+
+// device address of `scratch` on each device, looked up once per device with
+// that device current (the array's name is not a device address in host code)
+static std::mutex g_noalloc_mu;
+static void* g_noalloc_ptr[64];
+
+static pf_status noalloc_scratch(char** out)
+{
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(PF_EDEVICE, "device ordinal out of range");
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+        void* p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(PF_EDEVICE, "no device address for the static scratch");
+        g_noalloc_ptr[dev] = p;
+    }
+    *out = (char*)g_noalloc_ptr[dev];
+    return PF_OK;
+}
+
+extern "C" pf_status pf_resample_noalloc(uint64_t n, const double* g, uint64_t r, int32_t* anc, void* hip_stream)
+{
+    if (!g || !anc) return fail(PF_EINVAL, "NULL buffer");
+    if (n == 0 || n > NOALLOC_MAX_N) return fail(PF_EINVAL, "n must be 1..2^20 (the size of the static scratch)");
+    char* base = nullptr;
+    const pf_status ps = noalloc_scratch(&base);
+    if (ps != PF_OK) return ps;
+    hipStream_t st = (hipStream_t)hip_stream;
+    Batch bt;
+    std::memset(&bt, 0, sizeof(bt));
+    FilterDesc& d = bt.fd;
+    d.n = (int)n;
+    d.ntiles = (d.n + TILE - 1) / TILE;
+    d.npad = d.ntiles * TILE;
+    int cl = 0;
+    while ((1ll << cl) < (long long)d.n) ++cl;
+    d.shift = 62 - cl;
+    d.g_direct = 1;
+    d.resampling = 0;
+    d.q = (uint64_t*)(base + NOALLOC_Q_OFF);
+    d.tsum = (uint64_t*)(base + NOALLOC_TSUM_OFF);
+    d.lg = const_cast<double*>(g);
+    d.anc = anc;
+    bt.n_items = d.ntiles;
+    bt.count = 1;
+    FilterState* ds = (FilterState*)base;
+    const unsigned grid = (unsigned)std::min(d.ntiles, 2048);
+    hipLaunchKernelGGL(k_noalloc_state, dim3(1), dim3(TILE), 0, st, ds, r);
+    hipLaunchKernelGGL(k_count<true>, dim3(grid), dim3(TILE), 0, st, bt, (const FilterDesc*)nullptr, ds);
+    hipLaunchKernelGGL(k_scatter<true>, dim3(grid), dim3(TILE), 0, st, bt, (const FilterDesc*)nullptr, ds);
+    hipError_t e = hipGetLastError();
+    uint64_t T = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&T, &ds->T, sizeof(T), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return fail(PF_EDEVICE, std::string("resample: ") + hipGetErrorString(e));
+    if (T == 0) return fail(PF_EDEGENERATE, "all scaled weights are zero");
+    return PF_OK;
+}
+
 namespace pf {
 template <class R>
 __global__ void k_test_get(const FilterDesc* descs, const FilterState* states, int slot, double* x, double* th,

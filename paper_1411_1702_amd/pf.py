@@ -28,7 +28,7 @@ EXPORTS = [
     "pf_posterior", "pf_stats", "pf_destroy", "pf_status_str", "pf_last_error",
     "pf_context_profile", "pf_context_kernel_time", "pf_context_autotune", "pf_context_launch_grid", "pf_query",
     "pf_server_create", "pf_server_open", "pf_server_submit", "pf_server_poll", "pf_server_posterior",
-    "pf_server_close", "pf_server_drain", "pf_server_stats", "pf_server_destroy",
+    "pf_server_close", "pf_server_drain", "pf_server_stats", "pf_server_destroy", "pf_resample_noalloc",
     "pf_test_philox", "pf_test_normals", "pf_test_propagate", "pf_test_resample", "pf_test_resample_multinomial",
     "pf_test_get_ensemble", "pf_test_set_ensemble", "pf_test_last_ancestors", "pf_test_moments",
 ]
@@ -116,6 +116,7 @@ def lib():
                                         vp, vp]
         L.pf_test_resample.argtypes = [u64, vp, u64, vp, vp]
         L.pf_test_resample_multinomial.argtypes = [u64, vp, u64, u64, vp, vp]
+        L.pf_resample_noalloc.argtypes = [u64, vp, u64, vp, vp]
         L.pf_test_moments.argtypes = [u64, C.c_uint32, vp, vp, dp, dp, dp, dp, vp]
         L.pf_test_get_ensemble.argtypes = [vp, vp, vp, vp]
         L.pf_test_set_ensemble.argtypes = [vp, vp, vp, vp, dp, dp, u64, C.c_double]
