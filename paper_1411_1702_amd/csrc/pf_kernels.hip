@@ -882,6 +882,43 @@ __device__ __forceinline__ void keep_loaded(const T v, const U... rest)
 }
 
 // ---------------------------------------------------------------------------
+// the step-4 normals of one output slot (Algorithm 1 steps 4(a) and 4(d)):
+// they depend only on (seed, step, slot), so they are drawn ahead of the
+// update kernel, where workgroups are idle, into the filter's z buffer; the
+// update kernel takes them from there when the tile's tag names its step and
+// draws them itself otherwise
+// ---------------------------------------------------------------------------
+template <class R, int P, int D>
+__device__ inline void draw_slot_normals(const FilterDesc& fd, uint64_t step, int n)
+{
+    R z[P], zi[D];
+    normals<P, R>(fd.seed, step, (uint64_t)n, PUR_PROLIF, z);
+    normals<D, R>(fd.seed, step, (uint64_t)n, PUR_INNOV, zi);
+    R* zb = (R*)fd.z;
+#pragma unroll
+    for (int i = 0; i < P; ++i) zb[(size_t)i * fd.npad + n] = z[i];
+#pragma unroll
+    for (int i = 0; i < D; ++i) zb[(size_t)(P + i) * fd.npad + n] = zi[i];
+}
+
+// every valid slot of tiles blockIdx.x - first, stepping by gridDim.x - first,
+// for `step`; the tile's tag follows its normals (both are read by a later
+// kernel, after this one has completed)
+template <class Model>
+__device__ inline void draw_ahead(const FilterDesc& fd, uint64_t step, int first)
+{
+    constexpr int P = Model::P, D = Model::D;
+    for (int tile = blockIdx.x - first; tile < fd.ntiles; tile += gridDim.x - first) {
+        const int n = tile * TILE + threadIdx.x;
+        if (n < fd.n) {
+            if (fd.prec == PREC_FP32) draw_slot_normals<float, P, D>(fd, step, n);
+            else draw_slot_normals<double, P, D>(fd, step, n);
+        }
+        if (threadIdx.x == 0) fd.ztag[tile] = step;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // step 1: prior draw and initial moment partials
 // ---------------------------------------------------------------------------
 template <class Model, class R>
@@ -917,6 +954,11 @@ __global__ __launch_bounds__(TILE) void k_init(int slot, const FilterDesc* descs
         }
         tile_moments<R, P, D>(-log((double)fd.n), valid, th, xs, fd.prior_mean, 0, nullptr, fd.part2 + tile,
                               fd.ntiles, sh);
+        // the first observation step's normals
+        if (fd.z) {
+            if (valid) draw_slot_normals<R, P, D>(fd, 1, n);
+            if (threadIdx.x == 0) fd.ztag[tile] = 1;
+        }
     }
 }
 
@@ -1042,14 +1084,17 @@ __global__ __launch_bounds__(TILE) void k_count(Batch B, const FilterDesc* __res
             const double g = fd.g_direct ? l : (ok && l > -INFINITY ? exp(l - M) / S : 0.0);
             if (g > 0.0) q = (unsigned long long)floor(ldexp(g, fd.shift));
         }
-        if (fd.resampling == 0) {
-            const unsigned long long ts = block_sum_u64(q, shu);
-            if (!fd.g_direct && !(itm.rec.t_next > t_cur)) continue;   // the step does not run
-            if (n < fd.n) fd.q[n] = q;
-            if (threadIdx.x == 0) fd.tsum[itm.tile] = ts;
+        // the inclusive prefix of q within the tile (every lane of the tile,
+        // so the prefix is monotone up to lane 255) and the tile's sum
+        unsigned long long ex;
+        const unsigned long long ts = block_exscan_u64(q, ex, shu);
+        if (!fd.g_direct && !(itm.rec.t_next > t_cur)) continue;   // the step does not run
+        fd.q[n] = ex + q;
+        if (threadIdx.x == 0) fd.tsum[itm.tile] = ts;
+        if (itm.tile == 0 && threadIdx.x == 0) {
             // the systematic draw's one uniform word of the filter and step,
-            // drawn once here for the scatter pass (test mode: the host's)
-            if (itm.tile == 0 && threadIdx.x == 0) {
+            // drawn once here for the scatter (test mode: the host's)
+            if (fd.resampling == 0) {
                 uint64_t r = v_test;
                 if (!fd.g_direct) {
                     uint64_t w[4];
@@ -1058,14 +1103,7 @@ __global__ __launch_bounds__(TILE) void k_count(Batch B, const FilterDesc* __res
                 }
                 st.R = r;
             }
-        } else {
-            // multinomial draw: the inclusive prefix of q within the tile
-            // (every lane of the tile, so the prefix is monotone up to 255)
-            unsigned long long ex;
-            const unsigned long long ts = block_exscan_u64(q, ex, shu);
-            if (!fd.g_direct && !(itm.rec.t_next > t_cur)) continue;
-            fd.q[n] = ex + q;
-            if (threadIdx.x == 0) fd.tsum[itm.tile] = ts;
+            st.j_run = j_cur + 1;
         }
     }
 }
@@ -1091,11 +1129,15 @@ constexpr uint64_t LONG_RUN = 16;
 // i draws tau_i = floor(r_i T / 2^64) from its own RESAMPLE word, finds the
 // tile s with P[s] <= tau_i < P[s+1] by bisection in LDS, then the particle by
 // bisection over that tile's inclusive prefix (written by k_count).
-__device__ inline void multinomial_tile(const FilterDesc& fd, FilterState& st, int tile, uint64_t step, bool run,
-                                        unsigned long long* P, unsigned long long* shu)
+// The filter's tile offsets in LDS: P[s] = the exclusive prefix of the tile
+// sums, P[ntiles] = T, built by every workgroup in the same order (exact
+// integers, so any order gives the same values).  MAXT tile sums at most.
+template <int MAXT>
+__device__ inline unsigned long long tile_offsets(const FilterDesc& fd, unsigned long long* P,
+                                                  unsigned long long* shu)
 {
     const int nt = fd.ntiles;
-    constexpr int PER = MULTI_MAX_TILES / TILE;   // tile sums per lane
+    constexpr int PER = MAXT / TILE;   // tile sums per lane
     unsigned long long v[PER], loc = 0;
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
@@ -1113,6 +1155,14 @@ __device__ inline void multinomial_tile(const FilterDesc& fd, FilterState& st, i
     }
     if (threadIdx.x == 0) P[nt] = T;
     __syncthreads();
+    return T;
+}
+
+__device__ inline void multinomial_tile(const FilterDesc& fd, FilterState& st, int tile, uint64_t step, bool run,
+                                        unsigned long long* P, unsigned long long* shu)
+{
+    const int nt = fd.ntiles;
+    const unsigned long long T = tile_offsets<MULTI_MAX_TILES>(fd, P, shu);
     if (!run) return;
     if (tile == 0 && threadIdx.x == 0) {
         st.T = T;
@@ -1158,10 +1208,12 @@ __global__ __launch_bounds__(TILE) void k_scatter(Batch B, const FilterDesc* des
             __syncthreads();
             continue;
         }
-        // loads first: this lane's weight, the filter state, the tile sums
-        // (the step's validity only gates the stores)
+        // loads first: this lane's weight and exclusive offset within the
+        // tile (from the count pass's inclusive prefix), the filter state, the
+        // tile sums (the step's validity only gates the stores)
         const int n = itm.tile * TILE + threadIdx.x;
-        const unsigned long long q = n < fd.n ? fd.q[n] : 0ull;
+        const unsigned long long ex = threadIdx.x > 0 ? fd.q[n - 1] : 0ull;
+        const unsigned long long q = n < fd.n ? fd.q[n] - ex : 0ull;
         // exclusive offset of this tile and total T of the integer weights:
         // the first two tile sums of each lane are loaded with the rest, so
         // one round trip covers up to 2 TILE tiles (2 TILE^2 particles)
@@ -1187,8 +1239,6 @@ __global__ __launch_bounds__(TILE) void k_scatter(Batch B, const FilterDesc* des
             if (!fd.g_direct) st.V = V;
         }
         if (T == 0) continue;
-        unsigned long long ex;
-        block_exscan_u64(q, ex, shu);
         if (threadIdx.x == 0) n_long = 0;
         __syncthreads();
         if (q > 0) {
@@ -1212,6 +1262,50 @@ __global__ __launch_bounds__(TILE) void k_scatter(Batch B, const FilterDesc* des
     }
 }
 
+// A single kinetic filter's systematic draw is folded into its update
+// kernel (no scatter pass) when its tile offsets fit in LDS.  Host and device
+// decide it the same way.
+constexpr int FOLD_MAX_TILES = 2048;   // N <= 2^19
+__host__ __device__ inline bool fold_scatter(const FilterDesc& fd)
+{
+    return fd.model != MODEL_ADVDIFF && fd.resampling == 0 && !fd.g_direct && fd.ntiles <= FOLD_MAX_TILES;
+}
+
+// The ancestor of output slot i in the systematic draw: the first particle k
+// with C_k N > i T + V, C the cumulative integer weights -- the same slot
+// assignment as the scatter pass's F(C_{k-1}) <= i < F(C_k).  The tile by
+// bisection over the LDS offsets P, then the particle by two rounds of
+// sixteen loads of the tile's inclusive prefix (the ends of its sixteen
+// blocks, then the block's entries).  Every product is below 2^63 (i T < N
+// 2^shift <= 2^62).
+__device__ inline int systematic_ancestor(const FilterDesc& fd, const unsigned long long* P, uint64_t T, uint64_t V,
+                                          uint64_t i)
+{
+    const uint64_t N = (uint64_t)fd.n;
+    const uint64_t u = i * T + V;
+    int lo = 0, hi = fd.ntiles;   // P[lo] N <= u < P[hi] N
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (P[mid] * N <= u) lo = mid;
+        else hi = mid;
+    }
+    const uint64_t base = P[lo];
+    const uint64_t* cq = fd.q + (size_t)lo * TILE;
+    uint64_t ends[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) ends[j] = cq[16 * j + 15];
+    int b = 0;   // blocks that end at or below u (the last one ends above: P[lo + 1] N > u)
+#pragma unroll
+    for (int j = 0; j < 15; ++j) b += (base + ends[j]) * N <= u ? 1 : 0;
+    uint64_t c[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) c[j] = cq[16 * b + j];
+    int k = 0;
+#pragma unroll
+    for (int j = 0; j < 15; ++j) k += (base + c[j]) * N <= u ? 1 : 0;
+    return lo * TILE + 16 * b + k;
+}
+
 // ---------------------------------------------------------------------------
 // steps 3(c)-5 per output slot
 // ---------------------------------------------------------------------------
@@ -1220,24 +1314,49 @@ __global__ __launch_bounds__(TILE) void k_update(Batch B, const FilterDesc* __re
 {
     constexpr int D = Model::D, P = Model::P;
     __shared__ double sh[TILE];
+    // the folded systematic draw's tile offsets (single-filter form only)
+    __shared__ unsigned long long Poff[INL ? FOLD_MAX_TILES + 1 : 1];
+    __shared__ unsigned long long shu[NWAVE];
     for (int itx = blockIdx.x; itx < B.n_items; itx += gridDim.x) {
         const Item itm = fetch<INL>(B, itx);
         const StepRec& rec = itm.rec;
         const FilterDesc& fd = desc_of<INL>(B, descs, itm.slot);
-        const FilterState& st = states[itm.slot];
+        FilterState& st = states[itm.slot];
         const int n = itm.tile * TILE + threadIdx.x;
         const bool valid = n < fd.n;
-        const int k_anc = valid ? fd.anc[n] : 0;   // issued before the state checks wait
+        const bool fold = INL && fold_scatter(fd);
+        int k_anc = valid && !fold ? fd.anc[n] : 0;   // issued before the state checks wait
+        const uint64_t ztag = fd.ztag ? fd.ztag[itm.tile] : 0;
         // every state field the step reads, loaded before any test waits on one
         const double t_cur = st.t;
-        const uint64_t T_cur = st.T, j_cur = st.j;
+        uint64_t T_cur = st.T;
+        const uint64_t j_cur = st.j, r_word = st.R;
         const int cur = st.cur, nxt = cur ^ 1;
         const R* const xb = (const R*)(cur ? fd.x[1] : fd.x[0]);
         const double* const tb = cur ? fd.theta[1] : fd.theta[0];
-        keep_loaded(j_cur, cur, xb, tb);
+        keep_loaded(j_cur, cur, xb, tb, ztag);
+        if constexpr (INL) {
+            if (fold) {
+                // 3(b) here: the draw's total and offset, then this slot's ancestor
+                T_cur = tile_offsets<FOLD_MAX_TILES>(fd, Poff, shu);
+                if (!(rec.t_next > t_cur)) continue;   // the step does not run
+                const uint64_t V = T_cur ? __umul64hi(r_word, T_cur) : 0;
+                if (itm.tile == 0 && threadIdx.x == 0) {
+                    st.T = T_cur;
+                    st.V = V;
+                }
+                if (T_cur == 0) continue;
+                if (valid) {
+                    k_anc = systematic_ancestor(fd, Poff, T_cur, V, (uint64_t)n);
+                    fd.anc[n] = k_anc;
+                }
+            }
+        }
         if (!(rec.t_next > t_cur) || T_cur == 0) continue;
         const double h = (rec.t_next - t_cur) / fd.substeps;
         const uint64_t step = j_cur + 1;
+        const bool ahead = ztag == step;   // this step's normals were drawn ahead
+        const R* const zb = (const R*)fd.z;
         double l = -INFINITY;
         double th[P];
         R x[D];
@@ -1261,12 +1380,22 @@ __global__ __launch_bounds__(TILE) void k_update(Batch B, const FilterDesc* __re
 #pragma unroll
             for (int i = 0; i < P; ++i) ta[i] = tb[(size_t)i * fd.npad + k];
             const double lb = fd.lbar[k];
-            // the ancestor's loads are in flight while the normals are drawn:
-            // keep the scheduler from sinking them below the generator
-            __builtin_amdgcn_sched_barrier(0);
             // 4(a): theta_{j+1} = m + s L z (normals in the propagation precision)
             R z[P];
-            normals<P, R>(fd.seed, step, (uint64_t)n, PUR_PROLIF, z);
+            R zi[D];
+            if (ahead) {
+#pragma unroll
+                for (int i = 0; i < P; ++i) z[i] = zb[(size_t)i * fd.npad + n];
+                if constexpr (D <= 4) {
+#pragma unroll
+                    for (int i = 0; i < D; ++i) zi[i] = zb[(size_t)(P + i) * fd.npad + n];
+                }
+            } else {
+                // the ancestor's loads are in flight while the normals are
+                // drawn: keep the scheduler from sinking them below the generator
+                __builtin_amdgcn_sched_barrier(0);
+                normals<P, R>(fd.seed, step, (uint64_t)n, PUR_PROLIF, z);
+            }
             const double a = fd.a;
             double m[P];
 #pragma unroll
@@ -1288,8 +1417,12 @@ __global__ __launch_bounds__(TILE) void k_update(Batch B, const FilterDesc* __re
             const R* fl = sizeof(R) == 4 ? (const R*)fd.floor_f : (const R*)fd.floor_;
             integrate_lmm<Model, R, KORD, true, LMM>(md, xw, gam, h, fd.substeps, (R)fd.rtol, fl, fd.kmax, iters,
                                                      fails);
-            R zi[D];
-            normals<D, R>(fd.seed, step, (uint64_t)n, PUR_INNOV, zi);
+            if (!ahead) {
+                normals<D, R>(fd.seed, step, (uint64_t)n, PUR_INNOV, zi);
+            } else if constexpr (D > 4) {
+#pragma unroll
+                for (int i = 0; i < D; ++i) zi[i] = zb[(size_t)(P + i) * fd.npad + n];
+            }
             R* xo = (R*)fd.x[nxt];
 #pragma unroll
             for (int i = 0; i < D; ++i) {
@@ -1377,10 +1510,23 @@ __global__ __launch_bounds__(TILE) void k_moments(Batch B, const FilterDesc* des
 {
     __shared__ double sh[TILE];
     __shared__ double tot[NACC_MAX];
-    // the inline form has one entry (and a grid of one): no loop, so nothing
-    // per-filter is hoisted and kept live across iterations
+    // the inline form has one entry: workgroup 0 does its moments, without a
+    // loop (nothing per-filter is hoisted and kept live across iterations);
+    // for a kinetic model the other workgroups draw the normals of the step
+    // after this one (this step's index is recorded by the count pass; if
+    // this step does not commit, the tags do not match the next step and
+    // its update kernel draws them itself)
+    if constexpr (INL && (MDL == MODEL_ROBERTSON || MDL == MODEL_CHAIN16)) {
+        if (blockIdx.x > 0) {
+            const FilterDesc& fd = B.fd;
+            const uint64_t next = states[uniform(B.one.slot)].j_run + 1;
+            if constexpr (MDL == MODEL_ROBERTSON) draw_ahead<Robertson<double>>(fd, next, 1);
+            else draw_ahead<Chain16<double>>(fd, next, 1);
+            return;
+        }
+    }
     const int b_end = INL ? 1 : B.count;
-    for (int b = blockIdx.x; b < b_end; b += INL ? b_end : gridDim.x) {
+    for (int b = blockIdx.x; b < b_end; b += INL ? b_end : gridDim.x) {   // inline: b = 0 only
         const StepRec rec = record<INL>(B, b);
         const int slot = uniform(rec.slot);
         const FilterDesc& fd = desc_of<INL>(B, descs, slot);

@@ -405,7 +405,7 @@ static void fill_static(FilterDesc& d, const pf_config* c)
 
 // bytes and offsets of one filter's buffers inside its pool block
 struct Layout {
-    uint64_t x[2], th[2], lw[2], lbar, lg, q, anc, part1, tsum, part2, x0b, smb, partx, total;
+    uint64_t x[2], th[2], lw[2], lbar, lg, q, anc, part1, tsum, part2, z, ztag, x0b, smb, partx, total;
 };
 static Layout layout_of(const FilterDesc& d)
 {
@@ -426,6 +426,10 @@ static Layout layout_of(const FilterDesc& d)
     L.part1 = take((uint64_t)d.ntiles * PART1_STRIDE * 8);
     L.tsum = take((uint64_t)d.ntiles * 8);
     L.part2 = take((uint64_t)d.ntiles * d.nacc * 8);
+    if (d.model != MODEL_ADVDIFF) {
+        L.z = take((uint64_t)(d.p + d.d) * np * rs);
+        L.ztag = take((uint64_t)d.ntiles * 8);
+    }
     if (d.model == MODEL_ADVDIFF) {
         L.x0b = take((uint64_t)d.d * 8);
         L.smb = take((uint64_t)d.d * 8);
@@ -450,6 +454,12 @@ static void bind_buffers(FilterDesc& d, char* base, const Layout& L)
     d.part1 = (double*)(base + L.part1);
     d.tsum = (uint64_t*)(base + L.tsum);
     d.part2 = (double*)(base + L.part2);
+    d.z = nullptr;
+    d.ztag = nullptr;
+    if (d.model != MODEL_ADVDIFF) {
+        d.z = base + L.z;
+        d.ztag = (uint64_t*)(base + L.ztag);
+    }
     if (d.model == MODEL_ADVDIFF) {
         d.x0b = (const double*)(base + L.x0b);
         d.smb = (double*)(base + L.smb);
@@ -968,9 +978,11 @@ static pf_status submit(pf_context* ctx, uint32_t count, pf_filter* const* fs, c
         hipLaunchKernelGGL(inline_rec ? k_count<true> : k_count<false>, dim3(grid_of(gcap[1], n_all)), dim3(TILE), 0,
                            ctx->stream, all, ctx->d_desc,
                            ctx->d_state);
-        hipLaunchKernelGGL(inline_rec ? k_scatter<true> : k_scatter<false>, dim3(grid_of(gcap[1], n_all)),
-                           dim3(TILE), 0, ctx->stream, all, ctx->d_desc,
-                           ctx->d_state);
+        // a single kinetic filter's update kernel does the systematic scatter itself
+        if (!(inline_rec && fold_scatter(fs[0]->desc)))
+            hipLaunchKernelGGL(inline_rec ? k_scatter<true> : k_scatter<false>, dim3(grid_of(gcap[1], n_all)),
+                               dim3(TILE), 0, ctx->stream, all, ctx->d_desc,
+                               ctx->d_state);
         if (trial && (e = hipEventRecord(sg.uev[2], ctx->stream)) != hipSuccess) return e;
         if (timed && (e = hipEventRecord(sg.tev[2], ctx->stream)) != hipSuccess) return e;
         for (const Range& r : ranges) {
@@ -985,8 +997,12 @@ static pf_status submit(pf_context* ctx, uint32_t count, pf_filter* const* fs, c
         if (trial && (e = hipEventRecord(sg.uev[3], ctx->stream)) != hipSuccess) return e;
         ad_launch(true);
         if (timed && (e = hipEventRecord(sg.tev[3], ctx->stream)) != hipSuccess) return e;
-        hipLaunchKernelGGL(moments_kernel,
-                           dim3(std::min<uint32_t>(count, (uint32_t)ctx->grid_cap)), dim3(TILE), 0,
+        // a single kinetic filter's moment pass also draws the next step's
+        // normals, in workgroups beside the one that does the moments
+        const uint32_t mom_grid =
+            inline_rec && fs[0]->desc.z ? 1u + (uint32_t)std::min(fs[0]->desc.ntiles, ctx->grid_cap)
+                                        : std::min<uint32_t>(count, (uint32_t)ctx->grid_cap);
+        hipLaunchKernelGGL(moments_kernel, dim3(mom_grid), dim3(TILE), 0,
                            ctx->stream, all, ctx->d_desc, ctx->d_state, ctx->d_ring);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if (timed && (e = hipEventRecord(sg.tev[4], ctx->stream)) != hipSuccess) return e;

@@ -72,6 +72,11 @@ struct FilterDesc {
     double* part1;                      // [PART1_STRIDE][ntiles] (max, sum exp, iterations, fails), by column
     uint64_t* tsum;                     // [ntiles] integer weight per tile (then offsets)
     double* part2;                      // [nacc][ntiles] moment partials and counters, by column
+    // kinetic models: the step-4 normals of every output slot (P proliferation
+    // rows, then D innovation rows, in the propagation precision), drawn ahead
+    // of the update kernel, and per tile the step they were drawn for
+    void* z;                            // [P + D][npad]
+    uint64_t* ztag;                     // [ntiles]
     // advection-diffusion only (the state is too large for the inline arrays;
     // x is stored particle-major, [npad][d])
     const double* x0b;                  // [d] initial field
@@ -95,6 +100,7 @@ struct FilterState {
     uint64_t step;                      // j + 1
     uint64_t T, V;                      // resampling total and offset
     uint64_t R;                         // the step's resampling word (drawn by the count pass)
+    uint64_t j_run;                     // index of the last step the count pass ran
     unsigned long long newton_pred, newton_upd, newton_fails, nonfinite, jitters;
     // new states with a negative component: the kinetic models' unpivoted
     // elimination of I - c J is shown safe (every pivot >= 1) for x >= 0 only
