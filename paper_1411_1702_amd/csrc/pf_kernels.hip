@@ -901,20 +901,47 @@ __device__ inline void draw_slot_normals(const FilterDesc& fd, uint64_t step, in
     for (int i = 0; i < D; ++i) zb[(size_t)(P + i) * fd.npad + n] = zi[i];
 }
 
-// every valid slot of tiles blockIdx.x - first, stepping by gridDim.x - first,
-// for `step`; the tile's tag follows its normals (both are read by a later
-// kernel, after this one has completed)
+// the slots of tile pairs (2 (blockIdx.x - first), + 1), stepping by
+// gridDim.x - first pairs, for `step`: each lane draws for one slot in each
+// tile of the pair, two independent generators the compiler interleaves
+// (half the wavefronts of one per slot, at the same arithmetic).  A tile's
+// tag follows its normals; both are read by a later kernel, after this one
+// has completed.
+template <class R, int P, int D>
+__device__ inline void draw_pair(const FilterDesc& fd, uint64_t step, int n0, int n1)
+{
+    R z0[P], z1[P], i0[D], i1[D];
+    normals<P, R>(fd.seed, step, (uint64_t)n0, PUR_PROLIF, z0);
+    normals<P, R>(fd.seed, step, (uint64_t)n1, PUR_PROLIF, z1);
+    normals<D, R>(fd.seed, step, (uint64_t)n0, PUR_INNOV, i0);
+    normals<D, R>(fd.seed, step, (uint64_t)n1, PUR_INNOV, i1);
+    R* zb = (R*)fd.z;
+    if (n0 < fd.n) {
+#pragma unroll
+        for (int i = 0; i < P; ++i) zb[(size_t)i * fd.npad + n0] = z0[i];
+#pragma unroll
+        for (int i = 0; i < D; ++i) zb[(size_t)(P + i) * fd.npad + n0] = i0[i];
+    }
+    if (n1 < fd.n) {
+#pragma unroll
+        for (int i = 0; i < P; ++i) zb[(size_t)i * fd.npad + n1] = z1[i];
+#pragma unroll
+        for (int i = 0; i < D; ++i) zb[(size_t)(P + i) * fd.npad + n1] = i1[i];
+    }
+}
+
 template <class Model>
 __device__ inline void draw_ahead(const FilterDesc& fd, uint64_t step, int first)
 {
     constexpr int P = Model::P, D = Model::D;
-    for (int tile = blockIdx.x - first; tile < fd.ntiles; tile += gridDim.x - first) {
-        const int n = tile * TILE + threadIdx.x;
-        if (n < fd.n) {
-            if (fd.prec == PREC_FP32) draw_slot_normals<float, P, D>(fd, step, n);
-            else draw_slot_normals<double, P, D>(fd, step, n);
+    for (int t0 = 2 * (blockIdx.x - first); t0 < fd.ntiles; t0 += 2 * (gridDim.x - first)) {
+        const int n0 = t0 * TILE + threadIdx.x, n1 = n0 + TILE;
+        if (fd.prec == PREC_FP32) draw_pair<float, P, D>(fd, step, n0, n1);
+        else draw_pair<double, P, D>(fd, step, n0, n1);
+        if (threadIdx.x == 0) {
+            fd.ztag[t0] = step;
+            if (t0 + 1 < fd.ntiles) fd.ztag[t0 + 1] = step;
         }
-        if (threadIdx.x == 0) fd.ztag[tile] = step;
     }
 }
 
@@ -1271,30 +1298,44 @@ __host__ __device__ inline bool fold_scatter(const FilterDesc& fd)
     return fd.model != MODEL_ADVDIFF && fd.resampling == 0 && !fd.g_direct && fd.ntiles <= FOLD_MAX_TILES;
 }
 
-// The ancestor of output slot i in the systematic draw: the first particle k
-// with C_k N > i T + V, C the cumulative integer weights -- the same slot
-// assignment as the scatter pass's F(C_{k-1}) <= i < F(C_k).  The tile by
-// bisection over the LDS offsets P, then the particle by two rounds of
-// sixteen loads of the tile's inclusive prefix (the ends of its sixteen
-// blocks, then the block's entries).  Every product is below 2^63 (i T < N
-// 2^shift <= 2^62).
-__device__ inline int systematic_ancestor(const FilterDesc& fd, const unsigned long long* P, uint64_t T, uint64_t V,
-                                          uint64_t i)
+// The systematic draw's slot assignment from the slot side: output slot i
+// takes the first particle k with C_k N > u_i = i T + V, C the cumulative
+// integer weights -- the same assignment as the scatter pass's
+// F(C_{k-1}) <= i < F(C_k).  Every product is below 2^63 (i T < N 2^shift
+// <= 2^62, C_k N <= T N).  First the tile: the last s with P[s] N <= u
+// (bisection over the LDS offsets; P[ntiles] N > u).
+__device__ inline int offset_tile(const unsigned long long* P, int ntiles, uint64_t N, uint64_t u)
 {
-    const uint64_t N = (uint64_t)fd.n;
-    const uint64_t u = i * T + V;
-    int lo = 0, hi = fd.ntiles;   // P[lo] N <= u < P[hi] N
+    int lo = 0, hi = ntiles;   // P[lo] N <= u < P[hi] N
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
         if (P[mid] * N <= u) lo = mid;
         else hi = mid;
     }
-    const uint64_t base = P[lo];
-    const uint64_t* cq = fd.q + (size_t)lo * TILE;
+    return lo;
+}
+
+// then the particle within tile s, from the tile's inclusive prefix cq
+// (base = P[s]; its last entry ends above u): from LDS by bisection ...
+__device__ inline int intile_lds(const unsigned long long* cq, uint64_t base, uint64_t N, uint64_t u)
+{
+    int a = 0, b = TILE - 1;   // first k with (base + cq[k]) N > u
+    while (a < b) {
+        const int mid = (a + b) >> 1;
+        if ((base + cq[mid]) * N > u) b = mid;
+        else a = mid + 1;
+    }
+    return a;
+}
+
+// ... or from global memory in two rounds of sixteen independent loads (the
+// ends of the tile's sixteen blocks, then the chosen block's entries)
+__device__ inline int intile_global(const uint64_t* cq, uint64_t base, uint64_t N, uint64_t u)
+{
     uint64_t ends[16];
 #pragma unroll
     for (int j = 0; j < 16; ++j) ends[j] = cq[16 * j + 15];
-    int b = 0;   // blocks that end at or below u (the last one ends above: P[lo + 1] N > u)
+    int b = 0;   // blocks that end at or below u (the last one ends above)
 #pragma unroll
     for (int j = 0; j < 15; ++j) b += (base + ends[j]) * N <= u ? 1 : 0;
     uint64_t c[16];
@@ -1303,8 +1344,12 @@ __device__ inline int systematic_ancestor(const FilterDesc& fd, const unsigned l
     int k = 0;
 #pragma unroll
     for (int j = 0; j < 15; ++j) k += (base + c[j]) * N <= u ? 1 : 0;
-    return lo * TILE + 16 * b + k;
+    return 16 * b + k;
 }
+
+// tiles of prefixes a workgroup stages in LDS when its slots' ancestors lie
+// in that few (else each lane searches global memory)
+constexpr int FOLD_STAGE = 4;
 
 // ---------------------------------------------------------------------------
 // steps 3(c)-5 per output slot
@@ -1316,7 +1361,9 @@ __global__ __launch_bounds__(TILE) void k_update(Batch B, const FilterDesc* __re
     __shared__ double sh[TILE];
     // the folded systematic draw's tile offsets (single-filter form only)
     __shared__ unsigned long long Poff[INL ? FOLD_MAX_TILES + 1 : 1];
+    __shared__ unsigned long long cqs[INL ? FOLD_STAGE * TILE : 1];
     __shared__ unsigned long long shu[NWAVE];
+    __shared__ int lo_sh[2];
     for (int itx = blockIdx.x; itx < B.n_items; itx += gridDim.x) {
         const Item itm = fetch<INL>(B, itx);
         const StepRec& rec = itm.rec;
@@ -1335,6 +1382,22 @@ __global__ __launch_bounds__(TILE) void k_update(Batch B, const FilterDesc* __re
         const R* const xb = (const R*)(cur ? fd.x[1] : fd.x[0]);
         const double* const tb = cur ? fd.theta[1] : fd.theta[0];
         keep_loaded(j_cur, cur, xb, tb, ztag);
+        const uint64_t step = j_cur + 1;
+        const bool ahead = ztag == step;   // this step's normals were drawn ahead
+        const R* const zb = (const R*)fd.z;
+        // the slot's normals, when drawn ahead: loaded first, as they depend
+        // on nothing the search below finds (the innovation's only where they
+        // are few enough to hold through the integration)
+        R z[P];
+        R zi[D];
+        if (ahead && valid) {
+#pragma unroll
+            for (int i = 0; i < P; ++i) z[i] = zb[(size_t)i * fd.npad + n];
+            if constexpr (D <= 4) {
+#pragma unroll
+                for (int i = 0; i < D; ++i) zi[i] = zb[(size_t)(P + i) * fd.npad + n];
+            }
+        }
         if constexpr (INL) {
             if (fold) {
                 // 3(b) here: the draw's total and offset, then this slot's ancestor
@@ -1346,17 +1409,29 @@ __global__ __launch_bounds__(TILE) void k_update(Batch B, const FilterDesc* __re
                     st.V = V;
                 }
                 if (T_cur == 0) continue;
-                if (valid) {
-                    k_anc = systematic_ancestor(fd, Poff, T_cur, V, (uint64_t)n);
-                    fd.anc[n] = k_anc;
+                const uint64_t N = (uint64_t)fd.n;
+                const uint64_t u = (uint64_t)n * T_cur + V;
+                const int s_t = valid ? offset_tile(Poff, fd.ntiles, N, u) : 0;
+                // the tiles of the first and the last valid slot bound every
+                // slot's (ancestors are nondecreasing in the slot)
+                const int last = (fd.n - itm.tile * TILE < TILE ? fd.n - itm.tile * TILE : TILE) - 1;
+                if (threadIdx.x == 0) lo_sh[0] = s_t;
+                if (threadIdx.x == last) lo_sh[1] = s_t;
+                __syncthreads();
+                const int s_a = lo_sh[0], s_b = lo_sh[1];
+                if (s_b - s_a < FOLD_STAGE) {
+                    for (int k = threadIdx.x; k < (s_b - s_a + 1) * TILE; k += TILE)
+                        cqs[k] = fd.q[(size_t)s_a * TILE + k];
+                    __syncthreads();
+                    if (valid) k_anc = s_t * TILE + intile_lds(cqs + (s_t - s_a) * TILE, Poff[s_t], N, u);
+                } else if (valid) {
+                    k_anc = s_t * TILE + intile_global(fd.q + (size_t)s_t * TILE, Poff[s_t], N, u);
                 }
+                if (valid) fd.anc[n] = k_anc;
             }
         }
         if (!(rec.t_next > t_cur) || T_cur == 0) continue;
         const double h = (rec.t_next - t_cur) / fd.substeps;
-        const uint64_t step = j_cur + 1;
-        const bool ahead = ztag == step;   // this step's normals were drawn ahead
-        const R* const zb = (const R*)fd.z;
         double l = -INFINITY;
         double th[P];
         R x[D];
@@ -1381,16 +1456,7 @@ __global__ __launch_bounds__(TILE) void k_update(Batch B, const FilterDesc* __re
             for (int i = 0; i < P; ++i) ta[i] = tb[(size_t)i * fd.npad + k];
             const double lb = fd.lbar[k];
             // 4(a): theta_{j+1} = m + s L z (normals in the propagation precision)
-            R z[P];
-            R zi[D];
-            if (ahead) {
-#pragma unroll
-                for (int i = 0; i < P; ++i) z[i] = zb[(size_t)i * fd.npad + n];
-                if constexpr (D <= 4) {
-#pragma unroll
-                    for (int i = 0; i < D; ++i) zi[i] = zb[(size_t)(P + i) * fd.npad + n];
-                }
-            } else {
+            if (!ahead) {
                 // the ancestor's loads are in flight while the normals are
                 // drawn: keep the scheduler from sinking them below the generator
                 __builtin_amdgcn_sched_barrier(0);

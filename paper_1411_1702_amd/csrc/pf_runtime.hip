@@ -1000,7 +1000,7 @@ static pf_status submit(pf_context* ctx, uint32_t count, pf_filter* const* fs, c
         // a single kinetic filter's moment pass also draws the next step's
         // normals, in workgroups beside the one that does the moments
         const uint32_t mom_grid =
-            inline_rec && fs[0]->desc.z ? 1u + (uint32_t)std::min(fs[0]->desc.ntiles, ctx->grid_cap)
+            inline_rec && fs[0]->desc.z ? 1u + (uint32_t)std::min((fs[0]->desc.ntiles + 1) / 2, ctx->grid_cap)
                                         : std::min<uint32_t>(count, (uint32_t)ctx->grid_cap);
         hipLaunchKernelGGL(moments_kernel, dim3(mom_grid), dim3(TILE), 0,
                            ctx->stream, all, ctx->d_desc, ctx->d_state, ctx->d_ring);
