@@ -150,12 +150,22 @@ def test_propagate_robertson_am(pf, oracle, prec, lte, k):
             assert abs(itg - ito) <= 0.01 * ito + 5
 
 
+# FP32 rounding of trapezoidal (AM1) steps, the error model of the bound
+# below: each step adds rounding of a few units in the last place of the
+# state's largest component (its sums run over all components through the
+# chain's coupling), and the trapezoidal rule is A- but not L-stable -- it
+# multiplies a stiff mode's error by |(1 + z/2)/(1 - z/2)| (0.67 at h k = 10,
+# 0.85 at 25) per step instead of BDF's |1/(1 - z)| -- so a step's rounding in
+# a stiff component is not forgotten within the next steps and can dominate
+# a component that is small at the end (x_i of 1e-8 beside |x| of 600).
+# Bound per component: the relative contract plus M steps of 10 units of
+# 2^-24 of the state's largest component.  Measured on these inputs (h k up
+# to 12): at most 9.4e-7 of the largest component, against 2.4e-5 allowed.
+AM1_ULPS_PER_STEP = 10
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 def test_propagate_chain_am1(pf, oracle, prec):
-    # The trapezoidal rule is A- but not L-stable: with k h up to ~25 a stiff
-    # component's error is multiplied by |(1 - z/2)/(1 + z/2)| ~ 0.85 per step
-    # instead of ~1/z (BDF), so FP32 rounding in those components persists
-    # over the 40 steps; the FP32 bound is set for that (5e-3), FP64 as BDF.
     prob, sets = _chain_inputs()
     prob.lmm, prob.order = 1, 1
     rtol = prob.newton_rtol_fp64 if prec == 0 else prob.newton_rtol_fp32
@@ -163,9 +173,17 @@ def test_propagate_chain_am1(pf, oracle, prec):
         xg, gg, _ = _propagate_gpu(pf, prob, prec, x, th, h, True)
         xo, go, _ = _propagate_oracle(oracle, prob, x, th, h, True, rtol)
         err = relerr(xg, xo, prob.state_floor)
-        assert err.max() < (TOL[0] if prec == 0 else 5e-3), (h, err.max())
-        if prec == 1:
-            assert np.median(err) < 1e-5
+        if prec == 0:
+            assert err.max() < TOL[0], (h, err.max())
+            continue
+        big = np.abs(xo).max(axis=1, keepdims=True)
+        allow = TOL[1] * np.maximum(np.abs(xo), prob.state_floor) + \
+            prob.substeps * AM1_ULPS_PER_STEP * 2.0**-24 * big
+        dev_ = np.abs(xg - xo)
+        print("chain AM1 FP32: worst error / allowance %.3f, largest error / |x|_max %.2e"
+              % ((dev_ / allow).max(), (dev_ / big).max()))
+        assert np.all(dev_ <= allow), (h, (dev_ / allow).max())
+        assert np.median(err) < 1e-5
 
 
 @pytest.mark.parametrize("prec", [0, 1])
