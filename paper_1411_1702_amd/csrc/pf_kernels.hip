@@ -1400,17 +1400,7 @@ __global__ __launch_bounds__(TILE) void k_update(Batch B, const FilterDesc* __re
         }
         if constexpr (INL) {
             if (fold) {
-                // 3(b) here: the draw's total and offset, then this slot's
-                // ancestor.  The prefixes of the tiles around this one are
-                // loaded first, on speculation: with even weights a slot's
-                // ancestor is near the slot, and these loads then overlap
-                // the tile offsets' instead of following them.
-                const int w0 = itm.tile > 0 ? itm.tile - 1 : 0;
-                const int wn = fd.ntiles - w0 < FOLD_STAGE ? fd.ntiles - w0 : FOLD_STAGE;
-                unsigned long long spec[FOLD_STAGE];
-#pragma unroll
-                for (int j = 0; j < FOLD_STAGE; ++j)
-                    spec[j] = j < wn ? fd.q[(size_t)(w0 + j) * TILE + threadIdx.x] : 0ull;
+                // 3(b) here: the draw's total and offset, then this slot's ancestor
                 T_cur = tile_offsets<FOLD_MAX_TILES>(fd, Poff, shu);
                 if (!(rec.t_next > t_cur)) continue;   // the step does not run
                 const uint64_t V = T_cur ? __umul64hi(r_word, T_cur) : 0;
@@ -1429,13 +1419,7 @@ __global__ __launch_bounds__(TILE) void k_update(Batch B, const FilterDesc* __re
                 if (threadIdx.x == last) lo_sh[1] = s_t;
                 __syncthreads();
                 const int s_a = lo_sh[0], s_b = lo_sh[1];
-                if (s_a >= w0 && s_b < w0 + wn) {
-                    // every ancestor tile was loaded on speculation
-#pragma unroll
-                    for (int j = 0; j < FOLD_STAGE; ++j) cqs[j * TILE + threadIdx.x] = spec[j];
-                    __syncthreads();
-                    if (valid) k_anc = s_t * TILE + intile_lds(cqs + (s_t - w0) * TILE, Poff[s_t], N, u);
-                } else if (s_b - s_a < FOLD_STAGE) {
+                if (s_b - s_a < FOLD_STAGE) {
                     for (int k = threadIdx.x; k < (s_b - s_a + 1) * TILE; k += TILE)
                         cqs[k] = fd.q[(size_t)s_a * TILE + k];
                     __syncthreads();
