@@ -68,13 +68,18 @@ def advdiff_flops(prob, update):
 
 
 def algorithmic_bytes(prob):
-    """HBM bytes one update launch must move per particle: Robertson 92 (the
-    gathered state, parameters and weights, the new state, parameters and
-    weight, the ancestor); advection-diffusion: the ancestor's field and the
-    new field (4 d bytes each in FP32) plus the same parameter traffic."""
+    """HBM bytes one FP32 update launch must move: kinetic models per
+    particle the ancestor's state, parameters and predictor likelihood
+    (4 d + 8 p + 8), the new state, parameters and weight (the same), the
+    slot's drawn-ahead normals (4 (p + d)), the ancestor's integer-weight
+    prefix that locates it (8) and the ancestor written out (4): Robertson
+    124 bytes; advection-diffusion: the ancestor's field and the new field
+    (4 d bytes each) plus the parameter and weight traffic and the ancestor
+    read (its draw stays in the scatter pass)."""
     if prob.model == inputs.MODEL_ADVDIFF:
         return (8 * prob.d + 2 * 8 * prob.p + 3 * 8 + 4) * prob.n_particles
-    return 92 * prob.n_particles
+    d, p = prob.d, prob.p
+    return (2 * (4 * d + 8 * p + 8) + 4 * (p + d) + 8 + 4) * prob.n_particles
 
 
 # HBM bytes of one k_update launch (Robertson, N = 2^17, FP32 propagation)
@@ -85,7 +90,7 @@ def algorithmic_bytes(prob):
 # sources: once they change, the figure no longer applies and bench reports
 # null until the counters are taken again.
 TRAFFIC = {
-    "b640076980ecf52e": {"fetch_kib": 3438.8, "write_kib": 5936.0, "fetch_scale": 2.0, "write_scale": 1.0},
+    "155b6aeb8e78993c": {"fetch_kib": 5768.2, "write_kib": 6464.0, "fetch_scale": 2.0, "write_scale": 1.0},
 }
 KERNEL_SOURCES = ("pf_kernels.hip", "pf_device.hpp", "pf_types.hpp")
 

@@ -84,7 +84,8 @@ typedef enum { PF_LMM_BDF = 0, PF_LMM_AM = 1, PF_LMM_BDF_SDIRK = 2 } pf_lmm;
 
 typedef enum {
     PF_PREC_FP64 = 0,      /* propagation (BDF + Newton + LU) in double */
-    PF_PREC_FP32_PROP = 1  /* propagation in float; weights, moments, Cholesky in double */
+    PF_PREC_FP32_PROP = 1  /* propagation and the step's normals in float; parameters, weights,
+                              moments, Cholesky in double */
 } pf_precision;
 
 /* Step 3(b) index draw.  Both act on the integer weights q_k = floor(g_k 2^S),

@@ -60,15 +60,15 @@ struct Philox {
 // (0,1) uniform from the top 53 bits of a word
 __device__ inline double unit_open(uint64_t w) { return ((double)(w >> 11) + 0.5) * 0x1p-53; }
 
-// Box-Muller pair from two uniforms, in the precision of the caller's
-// propagation (FP32 inputs are the FP64 uniforms rounded to float; the angle
-// goes through sincospi, whose argument 2u needs no range reduction).
+// Box-Muller pair from two uniforms, FP64 or FP32 (the innovation normals
+// of FP32 propagation: the FP64 uniforms rounded to float).  The angle 2 pi u
+// goes through sincospi of 2u, which is exact in binary, so the argument
+// needs neither the rounded product by 2 pi nor a range reduction.
 __device__ inline void box_muller(double u0, double u1, double& z0, double& z1)
 {
-    constexpr double kTwoPi = 6.283185307179586476925286766559;
     const double rad = sqrt(-2.0 * log(u0));
     double sn, cs;
-    sincos(kTwoPi * u1, &sn, &cs);
+    sincospi(2.0 * u1, &sn, &cs);
     z0 = rad * cs;
     z1 = rad * sn;
 }

@@ -23,9 +23,12 @@ def test_more_than_one_gpu_is_refused():
 
 
 def test_algorithmic_bytes_of_the_update_launch():
-    # Robertson: 92 bytes per particle (ancestor 4, gathered x 12, theta 24,
-    # weight 8; written x 12, theta 24, weight 8)
-    assert bench.algorithmic_bytes(inputs.robertson(1 << 17, 5)) == 92 << 17
+    # Robertson: 124 bytes per particle (gathered x 12, theta 24, predictor
+    # likelihood 8; written x 12, theta 24, weight 8; the drawn-ahead normals
+    # 24; the ancestor's prefix 8; the ancestor written 4)
+    assert bench.algorithmic_bytes(inputs.robertson(1 << 17, 5)) == 124 << 17
+    # chain: 2 (64 + 96 + 8) + 4 (12 + 16) + 8 + 4
+    assert bench.algorithmic_bytes(inputs.chain16(1024, 5)) == 460 * 1024
     ad = inputs.advdiff(64, 2, seed=0, n=20)
     assert bench.algorithmic_bytes(ad) == (8 * 361 + 2 * 8 * 5 + 3 * 8 + 4) * 64
 
