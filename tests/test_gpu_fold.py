@@ -71,3 +71,24 @@ def pf():
         pytest.skip("no GPU")
     _pf.lib()
     return _pf
+
+
+def test_filter_above_the_fold_limit_uses_the_scatter_pass(pf, oracle):
+    """A single filter of more than 2^19 particles keeps the separate scatter
+    pass (its tile offsets would not fit the update kernel's LDS): its first
+    step's ancestors must equal the oracle's, bit for bit (FP64, so that both
+    sides resample on the same integer weights)."""
+    n = (1 << 19) + 777
+    prob = inputs.robertson(n, 50, seed=11)
+    ora = oracle.Filter(prob)
+    rc, g, anc_o = ora.stage1(prob.times[0], prob.y[0], prob.sigma[0])
+    assert rc == 0
+    with pf.Context(0, 1 << 30) as ctx:
+        f = pf.Filter(ctx, pf.Config(prob, pf.PF_PREC_FP64))
+        assert f.assimilate(prob.times[0], prob.y[0], prob.sigma[0]) == pf.PF_OK
+        anc = torch.zeros(n, dtype=torch.int32, device="cuda")
+        pf.check(pf.lib().pf_test_last_ancestors(f.h, anc.data_ptr()), "anc")
+        anc_g = anc.cpu().numpy()
+        f.close()
+    print("N", n, "distinct ancestors", len(np.unique(anc_o)), "mismatches", int((anc_g != anc_o).sum()))
+    assert np.array_equal(anc_g, anc_o)
