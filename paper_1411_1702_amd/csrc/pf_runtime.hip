@@ -185,6 +185,11 @@ struct pf_context {
     std::vector<char> slot_used;
     Stage stage[NSTAGE];
     int stage_next = 0;
+    // a single filter's untimed step takes no staging block; its record is
+    // built here (host memory, read only by the launch that copies it into
+    // the kernel arguments)
+    Stage light;
+    StepRec light_rec[1];
     int grid_cap = 2048;
     int n_cu = 256;
     bool autotune = true;
@@ -835,13 +840,21 @@ static pf_status submit(pf_context* ctx, uint32_t count, pf_filter* const* fs, c
     if (total_tiles > (uint64_t)MAX_ITEMS) return fail(PF_EINVAL, "batch has too many tiles");
 
     std::lock_guard<std::mutex> lk(ctx->mu);
-    const int si = ctx->stage_next;
-    Stage& sg = ctx->stage[si];
-    ctx->stage_next = (ctx->stage_next + 1) % NSTAGE;
-    HIP_TRY(hipEventSynchronize(sg.ev));   // previous use of this staging block is done
-    {
+    // A single filter's untimed step travels whole in the kernel arguments
+    // (nothing is copied, no item list, no events of a staging block), so it
+    // takes no staging block and does not wait for the submission that last
+    // used one: the host can run ahead of the GPU up to the filter's ring of
+    // pending steps.  Other submissions cycle through the staging blocks.
+    const bool light = count == 1 && !ctx->profiling;
+    const int si = light ? -1 : ctx->stage_next;
+    Stage& sg = light ? ctx->light : ctx->stage[si];
+    if (!light) {
+        ctx->stage_next = (ctx->stage_next + 1) % NSTAGE;
+        HIP_TRY(hipEventSynchronize(sg.ev));   // previous use of this staging block is done
         pf_status ps = stage_collect(ctx, sg);
         if (ps != PF_OK) return ps;
+    } else {
+        sg.host = (char*)ctx->light_rec;
     }
     // group tiles by kernel class so each class is one contiguous list
     const size_t rec_bytes = (sizeof(StepRec) * count + 255) & ~size_t(255);
@@ -860,6 +873,7 @@ static pf_status submit(pf_context* ctx, uint32_t count, pf_filter* const* fs, c
             r.y[i] = y[(size_t)b * ystride + i];
             r.sigma[i] = sigma[(size_t)b * ystride + i];
         }
+        if (light) continue;   // the inline form takes tile i as item i
         auto& v = by_class[f->cls];
         for (int t = 0; t < f->desc.ntiles; ++t) v.push_back((b << 16) | (uint32_t)t);
         sig += "," + std::to_string(f->slot) + ":" + std::to_string(f->cls) + ":" + std::to_string(f->desc.ntiles);
@@ -867,6 +881,10 @@ static pf_status submit(pf_context* ctx, uint32_t count, pf_filter* const* fs, c
     struct Range { int cls, off, cnt; };
     std::vector<Range> ranges;
     int off = 0;
+    if (light) {
+        ranges.push_back({fs[0]->cls, 0, fs[0]->desc.ntiles});
+        off = fs[0]->desc.ntiles;
+    }
     for (auto& kv : by_class) {
         std::memcpy(items + off, kv.second.data(), kv.second.size() * sizeof(uint32_t));
         ranges.push_back({kv.first, off, (int)kv.second.size()});
@@ -1051,13 +1069,15 @@ static pf_status submit(pf_context* ctx, uint32_t count, pf_filter* const* fs, c
         }
     }
     if (!launched) HIP_TRY(enqueue());
-    sg.timed = timed;
-    sg.trial = trial;
-    for (int g = 0; g < 3; ++g) {
-        sg.trial_key[g] = gcand[g] >= 0 ? gkey[g] : -1;
-        sg.trial_cand[g] = gcand[g] >= 0 ? gcand[g] : 0;
+    if (!light) {
+        sg.timed = timed;
+        sg.trial = trial;
+        for (int g = 0; g < 3; ++g) {
+            sg.trial_key[g] = gcand[g] >= 0 ? gkey[g] : -1;
+            sg.trial_cand[g] = gcand[g] >= 0 ? gcand[g] : 0;
+        }
+        HIP_TRY(hipEventRecord(sg.ev, ctx->stream));
     }
-    HIP_TRY(hipEventRecord(sg.ev, ctx->stream));
     hipEvent_t raw = pooled_event(ctx);
     HIP_TRY(hipEventRecord(raw, ctx->stream));
     auto ev = std::shared_ptr<hipEvent_t>(new hipEvent_t(raw), [ctx](hipEvent_t* e) {

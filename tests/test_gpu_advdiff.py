@@ -193,7 +193,11 @@ def test_step_matches_oracle(pf, ctx, oracle, prec, n, N, j0):
         assert np.allclose(lw[fin], ora.logw[fin], rtol=0, atol=1e-8)
         mean, cov = ora.moments()
         assert np.allclose(post["mean"], mean, rtol=1e-10, atol=1e-12)
-        assert np.allclose(post["cov"], cov, rtol=1e-7, atol=1e-12)
+        # the covariance against its largest entry (entries near zero are formed
+        # by cancellation in both sums): measured at most 1.7e-14
+        cerr = np.abs(post["cov"] - cov).max() / np.abs(cov).max()
+        print("FP64 step: covariance error %.2e of its largest entry" % cerr)
+        assert cerr < 1e-12, cerr
         assert post["ess"] == pytest.approx(out["ess"], rel=1e-8)
         assert np.allclose(post["state_mean"], out["state_mean"], rtol=1e-9, atol=1e-12)
     else:
@@ -266,5 +270,9 @@ def test_step_ragged_max_sites_startup(pf, ctx, oracle, N, sites, lmm, order):
     assert np.allclose(lw[fin], ora.logw[fin], rtol=0, atol=1e-8)
     mean, cov = ora.moments()
     assert np.allclose(post["mean"], mean, rtol=1e-10, atol=1e-12)
-    assert np.allclose(post["cov"], cov, rtol=1e-7, atol=1e-12)
+    # the covariance against its largest entry (entries near zero are formed
+    # by cancellation in both sums): measured at most 1.7e-14
+    cerr = np.abs(post["cov"] - cov).max() / np.abs(cov).max()
+    print("FP64 step: covariance error %.2e of its largest entry" % cerr)
+    assert cerr < 1e-12, cerr
     assert np.allclose(post["state_mean"], out["state_mean"], rtol=1e-9, atol=1e-12)

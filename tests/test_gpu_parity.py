@@ -461,7 +461,11 @@ def test_step_parity_robertson(pf, ctx, oracle, prec, j0):
         assert np.allclose(lw[fin], ora.logw[fin], rtol=0, atol=1e-8)
         mean, cov = ora.moments()
         assert np.allclose(post["mean"], mean, rtol=1e-10, atol=1e-12)
-        assert np.allclose(post["cov"], cov, rtol=1e-7, atol=1e-12)
+        # the covariance against its largest entry (entries near zero are formed
+        # by cancellation in both sums): measured at most 1.7e-14
+        cerr = np.abs(post["cov"] - cov).max() / np.abs(cov).max()
+        print("FP64 step: covariance error %.2e of its largest entry" % cerr)
+        assert cerr < 1e-12, cerr
         assert post["ess"] == pytest.approx(out["ess"], rel=1e-8)
         assert np.allclose(post["state_mean"], out["state_mean"], rtol=1e-9, atol=1e-15)
 
@@ -491,7 +495,11 @@ def test_step_parity_robertson_large_n(pf, ctx, oracle, N):
     assert np.allclose(th, ora.theta, rtol=1e-12, atol=1e-12)
     mean, cov = ora.moments()
     assert np.allclose(post["mean"], mean, rtol=1e-10, atol=1e-12)
-    assert np.allclose(post["cov"], cov, rtol=1e-7, atol=1e-12)
+    # the covariance against its largest entry (entries near zero are formed
+    # by cancellation in both sums): measured at most 1.7e-14
+    cerr = np.abs(post["cov"] - cov).max() / np.abs(cov).max()
+    print("FP64 step: covariance error %.2e of its largest entry" % cerr)
+    assert cerr < 1e-12, cerr
     assert post["ess"] == pytest.approx(out["ess"], rel=1e-8)
 
 
@@ -511,7 +519,11 @@ def test_step_parity_robertson_multinomial(pf, ctx, oracle, prec):
     if prec == 0:
         mean, cov = ora.moments()
         assert np.allclose(post["mean"], mean, rtol=1e-10, atol=1e-12)
-        assert np.allclose(post["cov"], cov, rtol=1e-7, atol=1e-12)
+        # the covariance against its largest entry (entries near zero are formed
+        # by cancellation in both sums): measured at most 1.7e-14
+        cerr = np.abs(post["cov"] - cov).max() / np.abs(cov).max()
+        print("FP64 step: covariance error %.2e of its largest entry" % cerr)
+        assert cerr < 1e-12, cerr
 
 
 @pytest.mark.parametrize("prec", [0, 1])
@@ -529,7 +541,11 @@ def test_step_parity_robertson_am1(pf, ctx, oracle, prec):
     if prec == 0:
         mean, cov = ora.moments()
         assert np.allclose(post["mean"], mean, rtol=1e-10, atol=1e-12)
-        assert np.allclose(post["cov"], cov, rtol=1e-7, atol=1e-12)
+        # the covariance against its largest entry (entries near zero are formed
+        # by cancellation in both sums): measured at most 1.7e-14
+        cerr = np.abs(post["cov"] - cov).max() / np.abs(cov).max()
+        print("FP64 step: covariance error %.2e of its largest entry" % cerr)
+        assert cerr < 1e-12, cerr
 
 
 @pytest.mark.parametrize("prec", [0, 1])
@@ -561,7 +577,11 @@ def test_step_parity_robertson_sdirk(pf, ctx, oracle, prec):
         assert np.allclose(lw[fin], ora.logw[fin], rtol=0, atol=1e-8)
         mean, cov = ora.moments()
         assert np.allclose(post["mean"], mean, rtol=1e-10, atol=1e-12)
-        assert np.allclose(post["cov"], cov, rtol=1e-7, atol=1e-12)
+        # the covariance against its largest entry (entries near zero are formed
+        # by cancellation in both sums): measured at most 1.7e-14
+        cerr = np.abs(post["cov"] - cov).max() / np.abs(cov).max()
+        print("FP64 step: covariance error %.2e of its largest entry" % cerr)
+        assert cerr < 1e-12, cerr
 
 
 @pytest.mark.parametrize("prec", [0, 1])
