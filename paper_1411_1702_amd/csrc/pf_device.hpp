@@ -127,16 +127,22 @@ __device__ inline double rmax(double a, double b) { return fmax(a, b); }
 // A = I - c J(x); `solve` overwrites b with A^{-1} b.
 // ---------------------------------------------------------------------------
 
-// Robertson kinetics.  A = I - cJ has A31 = 0, and for x >= 0 every pivot of
-// the unpivoted elimination is >= 1 (the columns of J sum to zero), so the
-// elimination runs in the natural order: two multipliers and three pivots.
+// Robertson kinetics.  The three rates move mass between the species, so
+// f sums to zero, the columns of J sum to zero, and 1^T A = 1^T for
+// A = I - cJ: the solution of A d = b has d1 + d2 + d3 = b1 + b2 + b3 = s
+// for every b.  `solve` takes rows 2 and 3 of A with d1 = s - d2 - d3
+// substituted,
+//   (1 + c(k1 + 2 k2 x2 + k3 x3)) d2 + c(k1 + k3 x2) d3 = b2 + c k1 s
+//   -2 c k2 x2 d2 + d3 = b3,
+// and eliminates d3: the exact solution of the 3x3 system, with one
+// reciprocal per factorisation.  For x >= 0 the pivot is >= 1.
 template <class R>
 struct Robertson {
     static constexpr int D = 3;
     static constexpr int P = 3;
     R k1, k2, k3;
 
-    struct LU { R inv11, l21, a12, a13, u23, inv22, l32, inv33, c; };
+    struct LU { R ck1, a12, t, inv; };
 
     __device__ inline void set_params(const double th[P], const FilterDesc&)
     {
@@ -158,37 +164,23 @@ struct Robertson {
 
     __device__ inline void eval(const R x[D], R c, R f[D], LU& lu) const
     {
-        const R r1 = k1 * x[0];
-        const R r2 = k2 * x[1] * x[1];
-        const R r3 = k3 * x[1] * x[2];
-        f[0] = r3 - r1;
-        f[1] = r1 - r2 - r3;
-        f[2] = r2;
-        const R ck1 = c * k1, ck3 = c * k3, c2k2x2 = R(2) * c * k2 * x[1];
-        const R a11 = R(1) + ck1;
-        lu.inv11 = recip(a11);
-        lu.l21 = -ck1 * lu.inv11;
-        lu.a12 = -ck3 * x[2];
-        lu.a13 = -ck3 * x[1];
-        const R a22 = R(1) + c2k2x2 + ck3 * x[2];
-        const R a23 = ck3 * x[1];
-        const R u22 = a22 - lu.l21 * lu.a12;
-        lu.u23 = a23 - lu.l21 * lu.a13;
-        lu.inv22 = recip(u22);
-        lu.l32 = -c2k2x2 * lu.inv22;
-        lu.inv33 = recip(R(1) - lu.l32 * lu.u23);
-        lu.c = c;
+        rhs(x, f);
+        const R ck3 = c * k3;
+        lu.ck1 = c * k1;
+        lu.t = R(2) * c * k2 * x[1];                  // -A32
+        const R a22 = (R(1) + lu.ck1) + lu.t + ck3 * x[2];
+        lu.a12 = lu.ck1 + ck3 * x[1];
+        lu.inv = recip(a22 + lu.a12 * lu.t);
     }
 
     __device__ inline void solve(const LU& lu, R b[D]) const
     {
-        const R b2 = b[1] - lu.l21 * b[0];
-        const R b3 = b[2] - lu.l32 * b2;
-        const R x3 = b3 * lu.inv33;
-        const R x2 = (b2 - lu.u23 * x3) * lu.inv22;
-        b[0] = (b[0] - lu.a12 * x2 - lu.a13 * x3) * lu.inv11;
-        b[1] = x2;
-        b[2] = x3;
+        const R s = b[0] + b[1] + b[2];
+        const R d2 = ((b[1] + lu.ck1 * s) - lu.a12 * b[2]) * lu.inv;
+        const R d3 = b[2] + lu.t * d2;
+        b[0] = s - d2 - d3;
+        b[1] = d2;
+        b[2] = d3;
     }
 };
 
