@@ -111,10 +111,18 @@ __device__ inline float exp_rate(double th, float) { return expf((float)th); }
 __device__ inline float rfma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ inline double rfma(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
-// reciprocal: single-instruction v_rcp_f32 in FP32 (about 1 ulp), correctly
-// rounded division in FP64
+// reciprocal: single-instruction v_rcp_f32 in FP32 (about 1 ulp); in FP64
+// v_rcp_f64's estimate refined by two Newton-Raphson steps r += r (1 - v r),
+// each of which squares the relative error (within about 1 ulp; the
+// correctly rounded division takes twice the instructions).  Used where
+// v is finite and nonzero (Newton pivots, K + x, |a|^2).
 __device__ inline float recip(float v) { return __builtin_amdgcn_rcpf(v); }
-__device__ inline double recip(double v) { return 1.0 / v; }
+__device__ inline double recip(double v)
+{
+    double r = __builtin_amdgcn_rcp(v);
+    r = __builtin_fma(r, __builtin_fma(-v, r, 1.0), r);
+    return __builtin_fma(r, __builtin_fma(-v, r, 1.0), r);
+}
 
 // |v| and max(a, b) as single instructions (max returns the non-NaN operand)
 __device__ inline float rabs(float v) { return fabsf(v); }
