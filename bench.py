@@ -126,6 +126,7 @@ def update_traffic_bytes(prob):
 # MI355X vector ALU peak: 256 CU x 4 SIMD x 16 lanes x 2 flop (fma) x 2.4 GHz
 PEAK_VALU_NONPACKED = 256 * 4 * 16 * 2 * 2.4e9 / 1e12      # 78.6 TFLOP/s (fp32 and fp64)
 PEAK_FP32_PUBLISHED = 157.3                                   # TFLOP/s, packed fp32
+PEAK_HBM_GBS = 8000.0                                         # GB/s, HBM3E
 
 
 def progress(msg):
@@ -429,6 +430,7 @@ def single_filter(pf, args, prob):
         progress(f"served leg done: p50 {served['latency_p50_ms']:.3f} ms, p99 {served['latency_p99_ms']:.3f} ms")
     upd_ms = r32["kernel_ms"]["update"]
     achieved = r32["flop_update_per_launch"] / (upd_ms * 1e-3) / 1e12
+    traffic = update_traffic_bytes(prob)
     model = {inputs.MODEL_ROBERTSON: "robertson", inputs.MODEL_CHAIN: "chain16"}.get(prob.model)
     if prob.model == inputs.MODEL_ADVDIFF:
         nt = int(prob.model_consts[0])
@@ -450,9 +452,14 @@ def single_filter(pf, args, prob):
         # iteration than the count above for Robertson)
         "frac_executed": r32["flop_update_executed_per_launch"] / (upd_ms * 1e-3) / 1e12 / PEAK_FP32_PUBLISHED,
         "local_error_filter_flop_per_launch": r32["flop_update_local_error_filter_per_launch"],
-        "traffic": update_traffic_bytes(prob),
+        "traffic": traffic,
         "traffic_unit": "bytes per launch (HBM, counter-measured)",
         "algorithmic_bytes": algorithmic_bytes(prob),
+        # the same launch against the HBM roofline: algorithmic bytes (and the
+        # counter-measured ones) over the launch's duration, against 8 TB/s
+        "hbm_gbs_algorithmic": algorithmic_bytes(prob) / (upd_ms * 1e-3) / 1e9,
+        "hbm_frac_algorithmic": algorithmic_bytes(prob) / (upd_ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+        "hbm_frac_measured": (traffic / (upd_ms * 1e-3) / 1e9 / PEAK_HBM_GBS) if traffic else None,
         "avg_launch_ms": upd_ms,
         "flop_per_launch": r32["flop_update_per_launch"],
     }
