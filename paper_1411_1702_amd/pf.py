@@ -265,24 +265,32 @@ class Filter:
         h = C.c_void_p()
         check(lib().pf_create(ctx.h, cfg.ptr(), C.byref(h)), "pf_create")
         self.h = h
+        # y and sigma of a step go through two small ctypes buffers of this
+        # filter (the library copies them during the call): converting numpy
+        # arrays to pointers costs a few microseconds per call, per array
+        n = max(4, self.m)
+        self._y = (C.c_double * n)()
+        self._s = (C.c_double * n)(*([1.0] * n))
+        self._tk = C.c_uint64()
+
+    def _load(self, y, sigma):
+        for i in range(self.m):
+            self._y[i] = y[i]
+            self._s[i] = sigma[i]
 
     def assimilate(self, t, y, sigma):
         """Returns the step's status (PF_OK or PF_EDEGENERATE); raises on other errors."""
-        yy = np.ascontiguousarray(y, dtype=np.float64)
-        ss = np.ascontiguousarray(sigma, dtype=np.float64)
-        st = lib().pf_assimilate(self.h, float(t), _dp(yy), _dp(ss))
+        self._load(y, sigma)
+        st = lib().pf_assimilate(self.h, float(t), self._y, self._s)
         if st not in (PF_OK, PF_EDEGENERATE):
             check(st, "pf_assimilate")
         return st
 
     def assimilate_async(self, t, y, sigma):
-        yy = np.zeros(max(4, self.m))
-        ss = np.ones(max(4, self.m))
-        yy[: self.m] = y[: self.m]
-        ss[: self.m] = sigma[: self.m]
-        tk = C.c_uint64()
-        check(lib().pf_assimilate_async(self.h, float(t), _dp(yy), _dp(ss), C.byref(tk)), "pf_assimilate_async")
-        return tk.value
+        self._load(y, sigma)
+        check(lib().pf_assimilate_async(self.h, float(t), self._y, self._s, C.byref(self._tk)),
+              "pf_assimilate_async")
+        return self._tk.value
 
     def wait(self, ticket):
         return lib().pf_wait(self.h, int(ticket))
