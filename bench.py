@@ -556,11 +556,13 @@ def batched(pf, args):
     }
 
 
-def serve_trace(pf, trace, pool):
+def serve_trace(pf, trace, pool, prec=None):
     """Replay a serving trace (stream arrivals and their observations) in real
     time through the continuous-batching server; the server's report plus the
-    wall time, the replay's largest lag behind the trace, and throughput."""
-    cfgs = [pf.Config(r.problem, pf.PF_PREC_FP32_PROP) for r in trace]
+    wall time, the replay's largest lag behind the trace, and throughput.
+    FP32 propagation unless `prec` says otherwise."""
+    prec = pf.PF_PREC_FP32_PROP if prec is None else prec
+    cfgs = [pf.Config(r.problem, prec) for r in trace]
     events = []
     for k, r in enumerate(trace):
         events.append((r.arrival, 0, k, -1))
@@ -619,6 +621,8 @@ def serving(pf, args):
     runs = {}
     for label, pool in (("uncapped", 48 << 30), ("pool_256MiB", 256 << 20)):
         runs[label] = serve_trace(pf, trace, pool)
+    # the same trace served by the plain FP64 path (uncapped pool)
+    runs["fp64_uncapped"] = serve_trace(pf, trace, 48 << 30, pf.PF_PREC_FP64)
     main_run = runs["uncapped"]
     n_chain = sum(r.problem.model == inputs.MODEL_CHAIN for r in trace)
     return {
@@ -631,6 +635,8 @@ def serving(pf, args):
                                f"{n_chain} chain16 / {len(trace) - n_chain} robertson, "
                                "N in {4096, 16384, 65536}, observation gaps Exp(10 ms), fp32 propagation"},
         "latency_p50_ms": main_run["latency_p50_ms"], "latency_p99_ms": main_run["latency_p99_ms"],
+        "fp64_latency_p50_ms": runs["fp64_uncapped"]["latency_p50_ms"],
+        "fp64_latency_p99_ms": runs["fp64_uncapped"]["latency_p99_ms"],
         "runs": runs,
     }
 
