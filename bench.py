@@ -603,6 +603,8 @@ def served_leg(pf, streams):
     latency beside the throughput."""
     trace = inputs.serving_trace(n_streams=streams, rate=200.0, seed=0)
     st = serve_trace(pf, trace, 48 << 30)
+    # the same trace served by the plain FP64 path
+    s64 = serve_trace(pf, trace, 48 << 30, pf.PF_PREC_FP64)
     n_chain = sum(r.problem.model == inputs.MODEL_CHAIN for r in trace)
     return {"workload": f"serving {len(trace)} streams, Poisson arrivals 200/s, {n_chain} chain16 / "
                         f"{len(trace) - n_chain} robertson, N in {{4096, 16384, 65536}}, observation gaps "
@@ -611,7 +613,10 @@ def served_leg(pf, streams):
             "latency_max_ms": st["latency_max_ms"], "particle_steps_per_s": st["particle_steps_per_s"],
             "steps_completed": st["steps_completed"], "steps_skipped": st["steps_skipped"],
             "mean_batch": st["mean_batch"], "ticks": st["ticks"], "wall_s": st["wall_s"],
-            "driver_max_lag_ms": st["driver_max_lag_ms"]}
+            "driver_max_lag_ms": st["driver_max_lag_ms"],
+            "fp64": {"latency_p50_ms": s64["latency_p50_ms"], "latency_p99_ms": s64["latency_p99_ms"],
+                     "latency_max_ms": s64["latency_max_ms"], "mean_batch": s64["mean_batch"],
+                     "driver_max_lag_ms": s64["driver_max_lag_ms"]}}
 
 
 def serving(pf, args):
