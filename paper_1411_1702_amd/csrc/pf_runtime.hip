@@ -115,6 +115,7 @@ constexpr int MAX_ITEMS = 1 << 20;   // tiles per submission
 struct Ticket {
     uint64_t seq;
     std::shared_ptr<hipEvent_t> ev;
+    hipStream_t stream;   // the stream the step ran on
 };
 
 struct pf_filter {
@@ -176,6 +177,13 @@ struct pf_context {
     uint64_t use_clock = 0;
     hipStream_t stream = nullptr;
     hipStream_t init_stream = nullptr;   // filter creation runs here, beside the step stream
+    // multi-filter submissions alternate between two more streams of the
+    // context (when it owns its stream), so that one batch's kernels can run
+    // beside the previous one's; a filter's step waits for its previous
+    // step's event when that ran on another stream
+    hipStream_t sub[2] = {nullptr, nullptr};
+    int sub_next = 0;
+    std::shared_ptr<hipEvent_t> last_ev[3];   // latest submission's event on stream, sub[0], sub[1]
     bool own_stream = false;
     Pool pool;
     FilterDesc* d_desc = nullptr;
@@ -475,6 +483,14 @@ static void bind_buffers(FilterDesc& d, char* base, const Layout& L)
 // ---------------------------------------------------------------------------
 // context
 // ---------------------------------------------------------------------------
+// waits for every stream of the context that runs filter steps
+static void sync_streams(pf_context* ctx)
+{
+    (void)hipStreamSynchronize(ctx->stream);
+    for (hipStream_t st : ctx->sub)
+        if (st) (void)hipStreamSynchronize(st);
+}
+
 extern "C" pf_status pf_context_create(int device, uint64_t pool_bytes, const pf_allocator* alloc,
                                        void* hip_stream, pf_context** out)
 {
@@ -493,6 +509,8 @@ extern "C" pf_status pf_context_create(int device, uint64_t pool_bytes, const pf
         ctx->own_stream = true;
     }
     HIP_TRY(hipStreamCreateWithFlags(&ctx->init_stream, hipStreamNonBlocking));
+    if (ctx->own_stream)
+        for (auto& st : ctx->sub) HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
     if (pool_bytes == 0) {
         size_t fr = 0, tot = 0;
         HIP_TRY(hipMemGetInfo(&fr, &tot));
@@ -550,7 +568,7 @@ extern "C" void pf_context_destroy(pf_context* ctx)
 {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
-    (void)hipStreamSynchronize(ctx->stream);
+    sync_streams(ctx);
     for (auto& kv : ctx->graphs) (void)hipGraphExecDestroy(kv.second.exec);
     for (int s = 0; s < NSTAGE; ++s) {
         for (int i = 0; i < 5; ++i) (void)hipEventDestroy(ctx->stage[s].tev[i]);
@@ -561,12 +579,15 @@ extern "C" void pf_context_destroy(pf_context* ctx)
     }
     (void)hipHostFree(ctx->h_ring);
     (void)prof_collect(ctx);
+    for (auto& e : ctx->last_ev) e.reset();   // back into the pool
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     (void)hipFree(ctx->d_desc);
     (void)hipFree(ctx->d_state);
     if (ctx->alloc.alloc) ctx->alloc.free(ctx->alloc.user, ctx->pool.base, (void*)ctx->stream);
     else (void)hipFree(ctx->pool.base);
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+    for (hipStream_t st : ctx->sub)
+        if (st) (void)hipStreamDestroy(st);
     (void)hipStreamDestroy(ctx->init_stream);
     delete ctx;
 }
@@ -846,6 +867,14 @@ static pf_status submit(pf_context* ctx, uint32_t count, pf_filter* const* fs, c
     // used one: the host can run ahead of the GPU up to the filter's ring of
     // pending steps.  Other submissions cycle through the staging blocks.
     const bool light = count == 1 && !ctx->profiling;
+    // the stream of this submission: the context's own for a single filter
+    // and for profiled submissions (their events bracket kernel groups),
+    // else the next of the two batch streams
+    hipStream_t S = ctx->stream;
+    if (!light && !ctx->profiling && ctx->sub[0]) {
+        S = ctx->sub[ctx->sub_next];
+        ctx->sub_next ^= 1;
+    }
     const int si = light ? -1 : ctx->stage_next;
     Stage& sg = light ? ctx->light : ctx->stage[si];
     if (!light) {
@@ -964,9 +993,9 @@ static pf_status submit(pf_context* ctx, uint32_t count, pf_filter* const* fs, c
             const int nch = (d.d + AD_CHUNK - 1) / AD_CHUNK;
             const unsigned gt = grid_for(ctx, update ? d.ntiles * nch : d.ntiles);
             const int slot = fs[b]->slot;
-            hipLaunchKernelGGL(update ? k.update : k.predict, dim3(gp), dim3(k.wgs), k.lds, ctx->stream, recs[b],
+            hipLaunchKernelGGL(update ? k.update : k.predict, dim3(gp), dim3(k.wgs), k.lds, S, recs[b],
                                slot, ctx->d_desc, ctx->d_state);
-            hipLaunchKernelGGL(update ? k.part2 : k.part1, dim3(gt), dim3(TILE), 0, ctx->stream, recs[b], slot,
+            hipLaunchKernelGGL(update ? k.part2 : k.part1, dim3(gt), dim3(TILE), 0, S, recs[b], slot,
                                ctx->d_desc, ctx->d_state);
         }
     };
@@ -976,11 +1005,11 @@ static pf_status submit(pf_context* ctx, uint32_t count, pf_filter* const* fs, c
         hipError_t e = hipSuccess;
         if (!inline_rec) {
             e = hipMemcpyAsync(sg.dev, sg.host, rec_bytes + sizeof(uint32_t) * n_all, hipMemcpyHostToDevice,
-                               ctx->stream);
+                               S);
             if (e != hipSuccess) return e;
         }
-        if (timed && (e = hipEventRecord(sg.tev[0], ctx->stream)) != hipSuccess) return e;
-        if (trial && (e = hipEventRecord(sg.uev[0], ctx->stream)) != hipSuccess) return e;
+        if (timed && (e = hipEventRecord(sg.tev[0], S)) != hipSuccess) return e;
+        if (trial && (e = hipEventRecord(sg.uev[0], S)) != hipSuccess) return e;
         for (const Range& r : ranges) {
             int model, lmm, prec, order;
             class_decode(r.cls, model, lmm, prec, order);
@@ -988,21 +1017,21 @@ static pf_status submit(pf_context* ctx, uint32_t count, pf_filter* const* fs, c
             hipLaunchKernelGGL(inline_rec ? predict_kernel<true>(model, lmm, prec, order)
                                           : predict_kernel<false>(model, lmm, prec, order),
                                dim3(grid_of(gcap[0], r.cnt)), dim3(TILE), 0,
-                               ctx->stream, part(r), ctx->d_desc, ctx->d_state);
+                               S, part(r), ctx->d_desc, ctx->d_state);
         }
-        if (trial && (e = hipEventRecord(sg.uev[1], ctx->stream)) != hipSuccess) return e;
+        if (trial && (e = hipEventRecord(sg.uev[1], S)) != hipSuccess) return e;
         ad_launch(false);
-        if (timed && (e = hipEventRecord(sg.tev[1], ctx->stream)) != hipSuccess) return e;
+        if (timed && (e = hipEventRecord(sg.tev[1], S)) != hipSuccess) return e;
         hipLaunchKernelGGL(inline_rec ? k_count<true> : k_count<false>, dim3(grid_of(gcap[1], n_all)), dim3(TILE), 0,
-                           ctx->stream, all, ctx->d_desc,
+                           S, all, ctx->d_desc,
                            ctx->d_state);
         // a single kinetic filter's update kernel does the systematic scatter itself
         if (!(inline_rec && fold_scatter(fs[0]->desc)))
             hipLaunchKernelGGL(inline_rec ? k_scatter<true> : k_scatter<false>, dim3(grid_of(gcap[1], n_all)),
-                               dim3(TILE), 0, ctx->stream, all, ctx->d_desc,
+                               dim3(TILE), 0, S, all, ctx->d_desc,
                                ctx->d_state);
-        if (trial && (e = hipEventRecord(sg.uev[2], ctx->stream)) != hipSuccess) return e;
-        if (timed && (e = hipEventRecord(sg.tev[2], ctx->stream)) != hipSuccess) return e;
+        if (trial && (e = hipEventRecord(sg.uev[2], S)) != hipSuccess) return e;
+        if (timed && (e = hipEventRecord(sg.tev[2], S)) != hipSuccess) return e;
         for (const Range& r : ranges) {
             int model, lmm, prec, order;
             class_decode(r.cls, model, lmm, prec, order);
@@ -1010,23 +1039,34 @@ static pf_status submit(pf_context* ctx, uint32_t count, pf_filter* const* fs, c
             hipLaunchKernelGGL(inline_rec ? update_kernel<true>(model, lmm, prec, order)
                                           : update_kernel<false>(model, lmm, prec, order),
                                dim3(grid_of(gcap[2], r.cnt)), dim3(TILE), 0,
-                               ctx->stream, part(r), ctx->d_desc, ctx->d_state);
+                               S, part(r), ctx->d_desc, ctx->d_state);
         }
-        if (trial && (e = hipEventRecord(sg.uev[3], ctx->stream)) != hipSuccess) return e;
+        if (trial && (e = hipEventRecord(sg.uev[3], S)) != hipSuccess) return e;
         ad_launch(true);
-        if (timed && (e = hipEventRecord(sg.tev[3], ctx->stream)) != hipSuccess) return e;
+        if (timed && (e = hipEventRecord(sg.tev[3], S)) != hipSuccess) return e;
         // a single kinetic filter's moment pass also draws the next step's
         // normals, in workgroups beside the one that does the moments
         const uint32_t mom_grid =
             inline_rec && fs[0]->desc.z ? 1u + (uint32_t)std::min((fs[0]->desc.ntiles + 1) / 2, ctx->grid_cap)
                                         : std::min<uint32_t>(count, (uint32_t)ctx->grid_cap);
         hipLaunchKernelGGL(moments_kernel, dim3(mom_grid), dim3(TILE), 0,
-                           ctx->stream, all, ctx->d_desc, ctx->d_state, ctx->d_ring);
+                           S, all, ctx->d_desc, ctx->d_state, ctx->d_ring);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        if (timed && (e = hipEventRecord(sg.tev[4], ctx->stream)) != hipSuccess) return e;
+        if (timed && (e = hipEventRecord(sg.tev[4], S)) != hipSuccess) return e;
         return hipSuccess;
     };
 
+    // a filter's previous step, if still pending on another stream, comes
+    // first (outside any graph capture): this stream waits for the latest
+    // submission on each such stream, which follows that step
+    hipStream_t const all_streams[3] = {ctx->stream, ctx->sub[0], ctx->sub[1]};
+    for (int x = 0; x < 3; ++x) {
+        if (!all_streams[x] || all_streams[x] == S || !ctx->last_ev[x]) continue;
+        bool need = false;
+        for (uint32_t b = 0; b < count && !need; ++b)
+            need = !fs[b]->pending.empty() && fs[b]->pending.back().stream == all_streams[x];
+        if (need) HIP_TRY(hipStreamWaitEvent(S, *ctx->last_ev[x], 0));
+    }
     bool launched = false;
     // profiled submissions launch directly: their events then bracket the
     // kernels themselves.  A single filter's step launches directly too: its
@@ -1038,7 +1078,7 @@ static pf_status submit(pf_context* ctx, uint32_t count, pf_filter* const* fs, c
         if (it == ctx->graphs.end() && ++ctx->seen[sig] >= 2) {
             // a repeated batch shape: capture it once and replay it afterwards
             if (ctx->graphs.size() >= 64) {
-                HIP_TRY(hipStreamSynchronize(ctx->stream));
+                sync_streams(ctx);
                 auto old = ctx->graphs.begin();
                 for (auto g = ctx->graphs.begin(); g != ctx->graphs.end(); ++g)
                     if (g->second.last_use < old->second.last_use) old = g;
@@ -1046,10 +1086,10 @@ static pf_status submit(pf_context* ctx, uint32_t count, pf_filter* const* fs, c
                 ctx->graphs.erase(old);
             }
             hipGraph_t graph = nullptr;
-            hipError_t e = hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeRelaxed);
+            hipError_t e = hipStreamBeginCapture(S, hipStreamCaptureModeRelaxed);
             hipError_t e2 = e == hipSuccess ? enqueue() : e;
             if (e == hipSuccess) {
-                e = hipStreamEndCapture(ctx->stream, &graph);
+                e = hipStreamEndCapture(S, &graph);
                 if (e2 != hipSuccess) e = e2;
             }
             hipGraphExec_t exec = nullptr;
@@ -1064,7 +1104,7 @@ static pf_status submit(pf_context* ctx, uint32_t count, pf_filter* const* fs, c
         }
         if (ctx->use_graphs && it != ctx->graphs.end()) {
             it->second.last_use = ++ctx->use_clock;
-            HIP_TRY(hipGraphLaunch(it->second.exec, ctx->stream));
+            HIP_TRY(hipGraphLaunch(it->second.exec, S));
             launched = true;
         }
     }
@@ -1076,20 +1116,21 @@ static pf_status submit(pf_context* ctx, uint32_t count, pf_filter* const* fs, c
             sg.trial_key[g] = gcand[g] >= 0 ? gkey[g] : -1;
             sg.trial_cand[g] = gcand[g] >= 0 ? gcand[g] : 0;
         }
-        HIP_TRY(hipEventRecord(sg.ev, ctx->stream));
+        HIP_TRY(hipEventRecord(sg.ev, S));
     }
     hipEvent_t raw = pooled_event(ctx);
-    HIP_TRY(hipEventRecord(raw, ctx->stream));
+    HIP_TRY(hipEventRecord(raw, S));
     auto ev = std::shared_ptr<hipEvent_t>(new hipEvent_t(raw), [ctx](hipEvent_t* e) {
         std::lock_guard<std::mutex> lk(ctx->ev_mu);
         ctx->ev_pool.push_back(*e);   // pooled; destroyed with the context
         delete e;
     });
+    ctx->last_ev[S == ctx->stream ? 0 : S == ctx->sub[0] ? 1 : 2] = ev;
     for (uint32_t b = 0; b < count; ++b) {
         pf_filter* f = fs[b];
         const uint64_t seq = f->next_seq++;
         f->t_submitted = t_obs[b];
-        f->pending.push_back({seq, ev});
+        f->pending.push_back({seq, ev, S});
         if (tickets) tickets[b] = seq;
     }
     return PF_OK;
