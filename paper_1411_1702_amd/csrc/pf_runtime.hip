@@ -509,7 +509,8 @@ extern "C" pf_status pf_context_create(int device, uint64_t pool_bytes, const pf
         ctx->own_stream = true;
     }
     HIP_TRY(hipStreamCreateWithFlags(&ctx->init_stream, hipStreamNonBlocking));
-    if (ctx->own_stream)
+    const char* envs = std::getenv("PF_BATCH_STREAMS");   // "0": every submission on the one stream
+    if (ctx->own_stream && !(envs && envs[0] == '0'))
         for (auto& st : ctx->sub) HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
     if (pool_bytes == 0) {
         size_t fr = 0, tot = 0;
