@@ -147,7 +147,10 @@ typedef struct {
  * (0 = 1/4 of free device memory) from which every filter's ensemble is
  * carved.  alloc: where the pool comes from (NULL, or alloc->alloc == NULL:
  * hipMalloc); the allocator is copied.  hip_stream: a hipStream_t to submit
- * on (NULL: the context creates its own).  PF_ENOMEM if the pool cannot be
+ * on (NULL: the context creates its own, and two more on which multi-filter
+ * submissions alternate, each filter's steps kept in order by events; with
+ * the environment variable PF_BATCH_STREAMS=0 it uses its one stream for
+ * everything).  A caller's stream is used alone.  PF_ENOMEM if the pool cannot be
  * allocated, PF_EINVAL for an allocator with only one of its functions or a
  * pool not aligned to 256 bytes.
  */
