@@ -117,6 +117,8 @@ def lib():
                                      C.POINTER(_Diag)]
         L.or_filter_stage1.argtypes = [C.POINTER(_Cfg), C.POINTER(_State), C.c_double, dp, dp,
                                        dp, C.POINTER(C.c_int32)]
+        L.or_filter_step_given.argtypes = [C.POINTER(_Cfg), C.POINTER(_State), C.c_double, dp, dp,
+                                           C.POINTER(C.c_int32), C.POINTER(_Diag)]
         L.or_num_threads.restype = C.c_int
         L.or_set_num_threads.argtypes = [C.c_int]
         _lib = L
@@ -404,6 +406,17 @@ class Filter:
                "newton_iters": dg.newton_iters, "newton_fails": dg.newton_fails,
                "lu_fails": dg.lu_fails, "nonfinite": dg.nonfinite, "jitters": dg.jitters}
         return out
+
+    def step_given(self, t_next, y, sigma, anc):
+        """The step with these N ancestors in place of its own index draw of
+        step 3(b) (test use: the rest of the step for another implementation's
+        draw); returns the status."""
+        a = np.ascontiguousarray(anc, dtype=np.int32)
+        assert a.shape == (self.N,)
+        dg = _Diag()
+        return lib().or_filter_step_given(C.byref(self.cfg), C.byref(self.st), float(t_next),
+                                          _dp(_f64(y)), _dp(_f64(sigma)),
+                                          a.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(dg))
 
     def stage1(self, t_next, y, sigma):
         g = np.zeros(self.N)

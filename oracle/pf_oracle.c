@@ -1019,9 +1019,12 @@ int or_filter_init(const or_config* cfg, double t0, or_state* s)
     return st;
 }
 
-/* Steps 2-6 for the next observation y (m values, sd sigma) at t_next. */
-int or_filter_step(const or_config* cfg, or_state* s, double t_next,
-                   const double* y, const double* sigma, or_diag* dg)
+/* Steps 2-6 for the next observation y (m values, sd sigma) at t_next;
+ * anc_in, when given, replaces the index draw of step 3(b) by these N
+ * ancestors (test use: the rest of the step for another implementation's
+ * draw), each in [0, N). */
+static int filter_step(const or_config* cfg, or_state* s, double t_next,
+                       const double* y, const double* sigma, const int32_t* anc_in, or_diag* dg)
 {
     long N = cfg->N;
     int d = cfg->d, p = cfg->p, m = cfg->m;
@@ -1061,7 +1064,12 @@ int or_filter_step(const or_config* cfg, or_state* s, double t_next,
 
     /* Step 3(b): indices; systematic: one uniform word per filter and step,
      * multinomial: one per output slot */
-    if (cfg->resampling == 1) {
+    if (anc_in) {
+        for (long n = 0; n < N; ++n) {
+            if (anc_in[n] < 0 || anc_in[n] >= N) { status = OR_EINVAL; goto done; }
+            anc[n] = anc_in[n];
+        }
+    } else if (cfg->resampling == 1) {
         if (or_resample_multinomial(N, g, cfg->seed, step, anc) != OR_OK) { status = OR_EDEGENERATE; goto done; }
     } else {
         uint64_t key[2] = {cfg->seed, 0}, ctr[4] = {step, 0, PUR_RESAMPLE, 0}, wv[4];
@@ -1135,6 +1143,18 @@ done:
     free(mshr); free(xbar); free(lbar); free(lg); free(g); free(anc);
     free(xn); free(thn); free(lwn); free(wn);
     return status;
+}
+
+int or_filter_step(const or_config* cfg, or_state* s, double t_next,
+                   const double* y, const double* sigma, or_diag* dg)
+{
+    return filter_step(cfg, s, t_next, y, sigma, NULL, dg);
+}
+
+int or_filter_step_given(const or_config* cfg, or_state* s, double t_next,
+                         const double* y, const double* sigma, const int32_t* anc, or_diag* dg)
+{
+    return filter_step(cfg, s, t_next, y, sigma, anc, dg);
 }
 
 /* diagnostic entry used by the pins: the ancestor vector and the first-stage

@@ -188,6 +188,15 @@ def test_step_matches_oracle(pf, ctx, oracle, prec, n, N, j0):
         dev_ = np.abs(th - ora.theta)
         print("FP32 jitter: worst |d theta| / bound %.3f" % (dev_[same] / bound[same]).max())
         assert np.all(dev_[same] <= bound[same])
+        # every slot, against the oracle's step taken with the GPU's ancestors
+        orb = oracle.Filter(prob)
+        for j in range(j0):
+            orb.step(prob.times[j], prob.y[j], prob.sigma[j])
+        assert orb.step_given(prob.times[j0], prob.y[j0], prob.sigma[j0], anc_g) == 0
+        ea = (np.abs(x - orb.x).max(axis=1) / np.abs(orb.x).max(axis=1)).max()
+        print("FP32 step, all slots with the GPU's ancestors: state err", ea)
+        assert ea < 2e-4, ea
+        assert np.all(np.abs(th - orb.theta) <= bound)
     if prec == 0:
         fin = np.isfinite(ora.logw)
         assert np.allclose(lw[fin], ora.logw[fin], rtol=0, atol=1e-8)

@@ -431,6 +431,27 @@ def _step_case(pf, ctx, oracle, prob, prec, j0):
     return ora, out, anc_o, anc_g, x, th, lw, post, scale
 
 
+def _fp32_all_slots(oracle, prob, j0, anc_g, x, th):
+    """The FP32 step against the oracle's step taken with the GPU's own
+    ancestors (FP32 predictions can move a borderline integer weight, so the
+    two index draws may differ in a few slots): every slot's state within
+    the FP32 bound, every slot's parameters within the FP32 jitter bound."""
+    orb = oracle.Filter(prob)
+    for j in range(j0):
+        assert orb.step(prob.times[j], prob.y[j], prob.sigma[j])["status"] == 0
+    x_in, t_in, L = orb.x.copy(), orb.t, orb.chol()
+    assert orb.step_given(prob.times[j0], prob.y[j0], prob.sigma[j0], anc_g) == 0
+    scale = np.maximum(_innovation_scale(oracle, prob, x_in, t_in, anc_g, orb.theta, j0 + 1),
+                       prob.state_floor)
+    err = np.abs(x - orb.x) / scale
+    bound = JB.fp32_jitter_bound(oracle, prob, L, j0 + 1, len(th))
+    dth = np.abs(th - orb.theta)
+    print("FP32 step, all slots with the GPU's ancestors: state error %.2e, worst |d theta| / bound %.3f"
+          % (err.max(), (dth / bound).max()))
+    assert err.max() < TOL[1], err.max()
+    assert np.all(dth <= bound)
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("j0", [0, 7, 30])
 def test_step_parity_robertson(pf, ctx, oracle, prec, j0):
@@ -441,6 +462,7 @@ def test_step_parity_robertson(pf, ctx, oracle, prec, j0):
         assert same.all()
     else:
         assert same.mean() > 0.98
+        _fp32_all_slots(oracle, prob, j0, anc_g, x, th)
     err = np.abs(x[same] - ora.x[same]) / scale[same]
     assert err.max() < TOL[prec], err.max()
     if prec == 0:
@@ -513,6 +535,7 @@ def test_step_parity_robertson_multinomial(pf, ctx, oracle, prec):
         assert same.all()
     else:
         assert same.mean() > 0.98
+        _fp32_all_slots(oracle, prob, 7, anc_g, x, th)
     assert not np.all(np.diff(anc_o) >= 0)     # multinomial ancestors are not sorted
     err = np.abs(x[same] - ora.x[same]) / scale[same]
     assert err.max() < TOL[prec], err.max()
@@ -536,6 +559,7 @@ def test_step_parity_robertson_am1(pf, ctx, oracle, prec):
         assert same.all()
     else:
         assert same.mean() > 0.98
+        _fp32_all_slots(oracle, prob, 7, anc_g, x, th)
     err = np.abs(x[same] - ora.x[same]) / scale[same]
     assert err.max() < TOL[prec], err.max()
     if prec == 0:
@@ -570,6 +594,7 @@ def test_step_parity_robertson_sdirk(pf, ctx, oracle, prec):
         assert same.all()
     else:
         assert same.mean() > 0.98
+        _fp32_all_slots(oracle, prob, 7, anc_g, x, th)
     err = np.abs(x[same] - ora.x[same]) / scale[same]
     assert err.max() < TOL[prec], err.max()
     if prec == 0:
@@ -598,6 +623,7 @@ def test_step_parity_chain(pf, ctx, oracle, prec):
         assert same.all(), (~same).sum()
     else:
         assert same.mean() > 0.95
+        _fp32_all_slots(oracle, prob, 3, anc_g, x, th)
     err = np.abs(x[same] - ora.x[same]) / scale[same]
     assert err.max() < TOL[prec], err.max()
     if prec == 0:

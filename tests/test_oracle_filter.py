@@ -82,6 +82,32 @@ def test_stage1_ancestors_consistent(oracle):
     assert np.all(np.diff(anc) >= 0)
 
 
+def test_step_given_own_ancestors_is_the_step(oracle):
+    # the step with its own draw passed in computes exactly the plain step;
+    # with a different valid draw the copies follow those ancestors
+    pr = inputs.robertson(500, 10)
+    A, B, C = oracle.Filter(pr), oracle.Filter(pr), oracle.Filter(pr)
+    for F in (A, B, C):
+        F.run(3)
+    rc, _, anc = A.stage1(pr.times[3], pr.y[3], pr.sigma[3])
+    assert rc == 0
+    assert A.step(pr.times[3], pr.y[3], pr.sigma[3])["status"] == 0
+    assert B.step_given(pr.times[3], pr.y[3], pr.sigma[3], anc) == 0
+    assert np.array_equal(A.x, B.x) and np.array_equal(A.theta, B.theta)
+    assert np.array_equal(A.logw, B.logw)
+    shifted = np.roll(anc, 1)
+    assert C.step_given(pr.times[3], pr.y[3], pr.sigma[3], shifted) == 0
+    # slot n now repropagates ancestor shifted[n]: its parameters are that
+    # ancestor's shrunk ones plus the slot's own jitter, so they differ
+    assert not np.array_equal(C.theta, A.theta)
+    bad = anc.copy()
+    bad[0] = pr.n_particles
+    D = oracle.Filter(pr)
+    D.run(3)
+    assert D.step_given(pr.times[3], pr.y[3], pr.sigma[3], bad) == oracle.EINVAL
+    assert D.j == 3
+
+
 def test_degenerate_observation_leaves_state_unchanged(oracle):
     pr = inputs.robertson(200, 5)
     F = oracle.Filter(pr)
