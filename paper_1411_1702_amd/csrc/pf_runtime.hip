@@ -1215,8 +1215,8 @@ static pf_status read_state(pf_filter* f, FilterState* st)
     HIP_TRY(hipSetDevice(f->ctx->device));
     pf_status s = drain(f, f->next_seq - 1);
     if (s != PF_OK) return s;
-    // the context stream may still run other filters' steps: read on the
-    // same stream so this filter's last step is ordered before the copy
+    // drain has waited for this filter's steps (on whichever stream they
+    // ran); the copy runs on the context's stream
     HIP_TRY(hipMemcpyAsync(st, f->ctx->d_state + f->slot, sizeof(FilterState), hipMemcpyDeviceToHost,
                            f->ctx->stream));
     HIP_TRY(hipStreamSynchronize(f->ctx->stream));
