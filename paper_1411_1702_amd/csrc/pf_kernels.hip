@@ -836,13 +836,26 @@ __device__ inline StepRec record(const Batch& B, int b)
     else return B.recs[b];
 }
 
+// The tile of workgroup w when a single filter's kernel runs one workgroup
+// per tile: workgroups go to the eight XCDs in turn (XCD w mod 8), so XCD x
+// takes the contiguous tiles [x q + min(x, r), ...) with nt = 8 q + r, as
+// many as it has workgroups.  A tile's neighbours (its slots' ancestors and
+// the prefix tiles their search reads) then sit in the same XCD's L2, in
+// every kernel of the step.  A bijection on [0, nt); results do not depend
+// on which workgroup runs a tile.
+__device__ inline int xcd_tile(int w, int nt)
+{
+    const int x = w % 8, q = nt / 8, r = nt % 8;
+    return x * q + (x < r ? x : r) + w / 8;
+}
+
 template <bool INL>
 __device__ inline Item fetch(const Batch& B, int itx)
 {
     Item r;
     if constexpr (INL) {
         r.b = 0;
-        r.tile = itx;
+        r.tile = (int)gridDim.x == B.fd.ntiles ? xcd_tile(itx, B.fd.ntiles) : itx;
         r.rec = B.one;
     } else {
         const uint32_t it = (uint32_t)uniform((int)B.items[itx]);
