@@ -97,7 +97,7 @@ def algorithmic_bytes(prob):
 # sources: once they change, the figure no longer applies and bench reports
 # null until the counters are taken again.
 TRAFFIC = {
-    "2f062900fdbd26f2": {"fetch_kib": 5757.1, "write_kib": 6464.0, "fetch_scale": 2.0, "write_scale": 1.0},
+    "5a36f625785c7981": {"fetch_kib": 5025.1, "write_kib": 6224.0, "fetch_scale": 2.0, "write_scale": 1.0},
 }
 KERNEL_SOURCES = ("pf_kernels.hip", "pf_device.hpp", "pf_types.hpp")
 
@@ -295,6 +295,11 @@ def _cpu_model():
     return None
 
 
+# the largest advection-diffusion grid (states) whose oracle step of one
+# particle fits a bounded CPU sample (19 x 19 modes: ~4 s on one core)
+ADVDIFF_CPU_MAX_STATES = 400
+
+
 def cpu_baseline(prob, target_s):
     """The FP64 oracle on the host cores: the first S observation steps of the
     same workload, S chosen so the sample takes about target_s seconds.  The
@@ -344,7 +349,17 @@ def cpu_baseline_particles(O, prob, target_s, threads):
     step of the full ensemble far longer than the budget, so the sample is
     the first observation step for a subset of the particles (its cost is
     linear in their number: the per-particle integrations dominate), sized
-    from a pilot of one particle per thread."""
+    from a pilot of one particle per thread.  A particle's step cannot be
+    split, and its dense LU grows with the cube of the state count: at 361
+    states it takes ~4 s on one core, at 1521 states ~75 times that, past
+    any bounded sample, so larger grids report the leg as skipped."""
+    if prob.d > ADVDIFF_CPU_MAX_STATES:
+        return {"value": None, "unit": "particle-steps/s", "cores": threads, "kind": "oracle",
+                "skipped": f"one particle's observation step of the FP64 oracle at {prob.d} states "
+                           f"(dense LU, cubic in the state count) takes minutes on one core, past "
+                           f"the {target_s:.0f} s sample; measured on grids of at most "
+                           f"{ADVDIFF_CPU_MAX_STATES} states"}
+    progress(f"cpu baseline: pilot of {threads} particles")
     t0 = time.perf_counter()
     O.Filter(prob.with_particles(threads)).step(prob.times[0], prob.y[0], prob.sigma[0])
     pilot = time.perf_counter() - t0
