@@ -92,7 +92,7 @@ def algorithmic_bytes(prob):
 # HBM bytes of one k_update launch (Robertson, N = 2^17, FP32 propagation)
 # from two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE; KiB per dispatch),
 # each scaled by what the counter reads for a plain 1 GiB device copy in the
-# same run (FETCH_SIZE reads 524308 KiB for the copy's 1048576 KiB of reads:
+# same run (FETCH_SIZE reads 524316 KiB for the copy's 1048576 KiB of reads:
 # x2.0; WRITE_SIZE reads 1048576: x1.0).  Keyed by a hash of the kernel
 # sources: once they change, the figure no longer applies and bench reports
 # null until the counters are taken again.
